@@ -1,0 +1,596 @@
+/*
+ * lcs_oracle.c -- plain, slow, FP64 CPU oracle for the LCS flow-map / FTLE path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * path (the HIP library) never links, calls or falls back to it, and the two
+ * share no source, header, table or helper.
+ *
+ * What it computes (paper: Ameli, Desai & Shadden, "Development of an efficient
+ * and flexible pipeline for Lagrangian coherent structure computation"):
+ *
+ *   - seed a structured grid of tracers                      (Sec. 2, Seed filter)
+ *   - space-time interpolation of gridded velocity frames:
+ *     multilinear in space, linear in time between the two
+ *     frames that bracket t                                   (Sec. 2, Interpolator;
+ *                                                              Sec. 3.2 grid kernels)
+ *   - fixed-step classical RK4 integration of dx/dt = u(x,t)  (Eq. 2; Sec. 3.1)
+ *   - trajectories that leave the domain are flagged and
+ *     frozen at their last accepted position                  (Sec. 2, Flow Map filter)
+ *   - flow-map gradient by central differences on the seed
+ *     grid                                                     (Sec. 2, Cauchy-Green filter)
+ *   - Cauchy-Green tensor C = grad(F)^T grad(F)                (Eq. 1)
+ *   - largest eigenvalue of C and the FTLE                     (Sec. 1; Sec. 2)
+ *
+ * Readings where the paper is silent (each is stated where it is used):
+ * node placement, the locate/tie-break rule, the domain-exit rule, one-sided
+ * differences at non-periodic seed edges, the periodic-seam shift, and
+ * FTLE = ln(lambda_max) / (2|T|).
+ *
+ * Everything is IEEE FP64, round-to-nearest, built with -ffp-contract=off.
+ * Parallelism: independent tracers are distributed over OpenMP threads; no
+ * tracer's arithmetic depends on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_FLAG_OUT 1u
+#define ORC_FLAG_NONFINITE 2u
+#define ORC_FLAG_STENCIL_OUT 4u
+
+/* Velocity frames, structure of arrays: component c of node (i,j,k) in frame f
+ * is u[c][f*n0*n1*n2 + i + n0*(j + n1*k)].  Node i of axis a is at
+ * origin[a] + i*spacing[a].  A periodic axis a has period n[a]*spacing[a].
+ * Frame f holds the field at t_first + f*dt_frame. */
+typedef struct {
+    int32_t dim;
+    int32_t n_frames;
+    int64_t n[3];
+    double origin[3];
+    double spacing[3];
+    uint32_t periodic_mask;
+    uint32_t reserved;
+    double t_first;
+    double dt_frame;
+    const double *u[3];
+} orc_velocity;
+
+/* Structured seed grid: seed (i,j,k) at origin + (i,j,k)*spacing.  A periodic
+ * seed axis has period n*spacing, which must equal the velocity period. */
+typedef struct {
+    int32_t dim;
+    uint32_t periodic_mask;
+    int64_t n[3];
+    double origin[3];
+    double spacing[3];
+} orc_seed_grid;
+
+static int axis_periodic(uint32_t mask, int a) { return (int)((mask >> a) & 1u); }
+
+/* ------------------------------------------------------------------------ */
+/* Spatial location (reading: cell of a point along one axis)                */
+/* ------------------------------------------------------------------------ */
+
+/* Along axis a: s = (x - origin)/h in cell units.
+ *  non-periodic: lower node i = floor(s), limited to [0, n-2]; a point on a
+ *                face belongs to the higher cell except on the last face.
+ *  periodic:     s is folded into [0, n) as s - n*floor(s/n); a fold that
+ *                rounds up to exactly n is node 0; the upper node is (i+1) mod n.
+ * Returns the lower node, the upper node and the local coordinate xi = s - i. */
+static void locate_axis(double x, double origin, double h, int64_t n, int periodic,
+                        int64_t *lo, int64_t *hi, double *xi)
+{
+    double s = (x - origin) / h;
+    int64_t i;
+    if (periodic) {
+        double nd = (double)n;
+        s = s - nd * floor(s / nd);
+        i = (int64_t)floor(s);
+        if (i >= n) { i = 0; s = 0.0; }
+        if (i < 0) { i = 0; s = 0.0; }
+        *lo = i;
+        *hi = (i + 1 == n) ? 0 : i + 1;
+    } else {
+        i = (int64_t)floor(s);
+        if (i > n - 2) i = n - 2;
+        if (i < 0) i = 0;
+        *lo = i;
+        *hi = i + 1;
+    }
+    *xi = s - (double)i;
+}
+
+/* Linear index i + n0*(j + n1*k) of the lower corner of the velocity cell that
+ * holds x (the rule of locate_axis).  Returns -1 for a non-finite point. */
+int64_t orc_cell_index(const orc_velocity *v, const double *x)
+{
+    int64_t idx = 0, stride = 1;
+    for (int a = 0; a < v->dim; ++a) {
+        if (!isfinite(x[a])) return -1;
+        int64_t lo, hi;
+        double xi;
+        locate_axis(x[a], v->origin[a], v->spacing[a], v->n[a],
+                    axis_periodic(v->periodic_mask, a), &lo, &hi, &xi);
+        idx += lo * stride;
+        stride *= v->n[a];
+    }
+    return idx;
+}
+
+void orc_cell_index_many(const orc_velocity *v, const double *x, int64_t m, int64_t *cell)
+{
+    for (int64_t p = 0; p < m; ++p) {
+        double q[3] = {0, 0, 0};
+        for (int a = 0; a < v->dim; ++a) q[a] = x[a * m + p];
+        cell[p] = orc_cell_index(v, q);
+    }
+}
+
+/* Closed domain on non-periodic axes: origin <= x <= origin + (n-1)h.
+ * Periodic axes never exit. */
+int orc_in_domain(const orc_velocity *v, const double *x)
+{
+    for (int a = 0; a < v->dim; ++a) {
+        if (axis_periodic(v->periodic_mask, a)) continue;
+        double lo = v->origin[a];
+        double hi = v->origin[a] + (double)(v->n[a] - 1) * v->spacing[a];
+        if (!(x[a] >= lo && x[a] <= hi)) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Space-time interpolation                                                   */
+/* ------------------------------------------------------------------------ */
+
+static double node_value(const orc_velocity *v, int c, int64_t f, const int64_t idx[3])
+{
+    int64_t per_frame = v->n[0] * v->n[1] * v->n[2];
+    int64_t lin = idx[0] + v->n[0] * (idx[1] + v->n[1] * idx[2]);
+    return v->u[c][f * per_frame + lin];
+}
+
+/* Multilinear interpolation of component c in frame f: the sum over the 2^dim
+ * cell corners of the corner value times the product, over axes, of xi (upper
+ * corner) or 1-xi (lower corner). */
+static double frame_interp(const orc_velocity *v, int c, int64_t f,
+                           const int64_t lo[3], const int64_t hi[3], const double xi[3])
+{
+    double acc = 0.0;
+    int ncorner = 1 << v->dim;
+    for (int corner = 0; corner < ncorner; ++corner) {
+        double w = 1.0;
+        int64_t idx[3] = {0, 0, 0};
+        for (int a = 0; a < v->dim; ++a) {
+            int upper = (corner >> a) & 1;
+            idx[a] = upper ? hi[a] : lo[a];
+            w *= upper ? xi[a] : (1.0 - xi[a]);
+        }
+        acc += w * node_value(v, c, f, idx);
+    }
+    return acc;
+}
+
+/* Frame pair bracketing t: f = floor((t - t_first)/dt_frame) limited to
+ * [0, F-2]; alpha = (t - t_f)/dt_frame with t_f = t_first + f*dt_frame.
+ * No extrapolation: callers keep t inside the frame span. */
+static void frame_pair(const orc_velocity *v, double t, int64_t *f, double *alpha)
+{
+    double q = floor((t - v->t_first) / v->dt_frame);
+    int64_t fi = (int64_t)q;
+    if (fi > v->n_frames - 2) fi = v->n_frames - 2;
+    if (fi < 0) fi = 0;
+    double tf = v->t_first + (double)fi * v->dt_frame;
+    *f = fi;
+    *alpha = (t - tf) / v->dt_frame;
+}
+
+/* u(x, t): multilinear in space within each frame, then linear in time,
+ * (1-alpha) u_f + alpha u_{f+1}.  x must be finite. */
+void orc_velocity_at(const orc_velocity *v, const double *x, double t, double *out)
+{
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double xi[3] = {0, 0, 0};
+    for (int a = 0; a < v->dim; ++a)
+        locate_axis(x[a], v->origin[a], v->spacing[a], v->n[a],
+                    axis_periodic(v->periodic_mask, a), &lo[a], &hi[a], &xi[a]);
+    int64_t f;
+    double alpha;
+    frame_pair(v, t, &f, &alpha);
+    for (int c = 0; c < v->dim; ++c) {
+        double u0 = frame_interp(v, c, f, lo, hi, xi);
+        double u1 = frame_interp(v, c, f + 1, lo, hi, xi);
+        out[c] = (1.0 - alpha) * u0 + alpha * u1;
+    }
+}
+
+void orc_velocity_at_many(const orc_velocity *v, const double *x, const double *t, int64_t m,
+                          double *out)
+{
+    for (int64_t p = 0; p < m; ++p) {
+        double q[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+        for (int a = 0; a < v->dim; ++a) q[a] = x[a * m + p];
+        orc_velocity_at(v, q, t[p], r);
+        for (int a = 0; a < v->dim; ++a) out[a * m + p] = r[a];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* RK4 advection                                                              */
+/* ------------------------------------------------------------------------ */
+
+static int all_finite(const double *x, int dim)
+{
+    for (int a = 0; a < dim; ++a)
+        if (!isfinite(x[a])) return 0;
+    return 1;
+}
+
+/* Check a point at which the field is about to be sampled (or a new
+ * position): non-finite -> NONFINITE, outside the closed domain -> OUT. */
+static uint32_t check_point(const orc_velocity *v, const double *p)
+{
+    if (!all_finite(p, v->dim)) return ORC_FLAG_NONFINITE;
+    if (!orc_in_domain(v, p)) return ORC_FLAG_OUT;
+    return 0;
+}
+
+/* One classical RK4 step from (x, t) with step dt:
+ *   k1 = u(x, t)
+ *   k2 = u(x + dt/2 k1, t + dt/2)
+ *   k3 = u(x + dt/2 k2, t + dt/2)
+ *   k4 = u(x + dt k3,   t + dt)
+ *   x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+ * Reading of the exit rule: if any stage point or x' is non-finite or outside
+ * the closed domain (or a sampled velocity is non-finite), the step is
+ * rejected, x is left unchanged and the matching flag is returned. */
+static uint32_t rk4_step(const orc_velocity *v, double *x, double t, double dt)
+{
+    int d = v->dim;
+    double k1[3], k2[3], k3[3], k4[3], p[3], xn[3];
+    uint32_t fl;
+
+    orc_velocity_at(v, x, t, k1);
+    if (!all_finite(k1, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k1[a];
+    if ((fl = check_point(v, p))) return fl;
+    orc_velocity_at(v, p, t + 0.5 * dt, k2);
+    if (!all_finite(k2, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k2[a];
+    if ((fl = check_point(v, p))) return fl;
+    orc_velocity_at(v, p, t + 0.5 * dt, k3);
+    if (!all_finite(k3, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + dt * k3[a];
+    if ((fl = check_point(v, p))) return fl;
+    orc_velocity_at(v, p, t + dt, k4);
+    if (!all_finite(k4, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a)
+        xn[a] = x[a] + (dt / 6.0) * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
+    if ((fl = check_point(v, xn))) return fl;
+
+    for (int a = 0; a < d; ++a) x[a] = xn[a];
+    return 0;
+}
+
+/* Integrate one tracer for nsteps fixed steps from t0: t_n = t0 + n*dt is
+ * recomputed every step (never accumulated).  A rejected step freezes the
+ * tracer and records its flag.  A starting point that is non-finite or
+ * outside the domain is flagged before any step. */
+static uint32_t advect_one(const orc_velocity *v, double *x, double t0, int64_t nsteps, double dt)
+{
+    uint32_t fl = check_point(v, x);
+    if (fl) return fl;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        double t = t0 + (double)n * dt;
+        fl = rk4_step(v, x, t, dt);
+        if (fl) return fl;
+    }
+    return 0;
+}
+
+/* Number of fixed steps: N = round(T/dt).  The caller has checked that T/dt
+ * is integral. */
+static int64_t step_count(double T, double dt) { return (int64_t)llround(T / dt); }
+
+/* Advect arbitrary points x0 (dim x m, SoA), each from its own t0[p], over
+ * the same duration T with step dt.  Outputs (any may be NULL): xf (dim x m),
+ * cell (m), flags (m). */
+void orc_advect_points(const orc_velocity *v, const double *x0, const double *t0, int64_t m,
+                       double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
+                       int nthreads)
+{
+    int64_t nsteps = step_count(T, dt);
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < m; ++p) {
+        double x[3] = {0, 0, 0};
+        for (int a = 0; a < v->dim; ++a) x[a] = x0[a * m + p];
+        uint32_t fl = advect_one(v, x, t0[p], nsteps, dt);
+        if (xf)
+            for (int a = 0; a < v->dim; ++a) xf[a * m + p] = x[a];
+        if (cell) cell[p] = orc_cell_index(v, x);
+        if (flags) flags[p] = (uint8_t)fl;
+    }
+    (void)nthreads;
+}
+
+/* Seed positions of the structured grid (step "Seed"): seed with integer
+ * coordinates (i,j,k) sits at origin + (i,j,k)*spacing, computed in FP64. */
+static void seed_position(const orc_seed_grid *g, int64_t lin, double *x)
+{
+    int64_t i = lin % g->n[0];
+    int64_t r = lin / g->n[0];
+    int64_t j = r % g->n[1];
+    int64_t k = r / g->n[1];
+    int64_t ijk[3] = {i, j, k};
+    for (int a = 0; a < g->dim; ++a) x[a] = g->origin[a] + (double)ijk[a] * g->spacing[a];
+}
+
+void orc_seed_points(const orc_seed_grid *g, const int64_t *idx, int64_t m, double *x)
+{
+    for (int64_t p = 0; p < m; ++p) {
+        double q[3] = {0, 0, 0};
+        seed_position(g, idx[p], q);
+        for (int a = 0; a < g->dim; ++a) x[a * m + p] = q[a];
+    }
+}
+
+/* Advect the seeds with the given linear indices (all seeds if idx == NULL,
+ * then m must be the seed count) from one t0.  Output arrays are indexed like
+ * idx: xf is dim x m. */
+void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64_t *idx, int64_t m,
+                      double t0, double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
+                      int nthreads)
+{
+    int64_t nsteps = step_count(T, dt);
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < m; ++p) {
+        double x[3] = {0, 0, 0};
+        seed_position(g, idx ? idx[p] : p, x);
+        uint32_t fl = advect_one(v, x, t0, nsteps, dt);
+        if (xf)
+            for (int a = 0; a < v->dim; ++a) xf[a * m + p] = x[a];
+        if (cell) cell[p] = orc_cell_index(v, x);
+        if (flags) flags[p] = (uint8_t)fl;
+    }
+    (void)nthreads;
+}
+
+/* Trajectory recording for the mean-trajectory-error curves (Sec. 3.3): the
+ * positions of every point after each of the N steps, traj[(n*dim + a)*m + p]. */
+void orc_advect_points_traj(const orc_velocity *v, const double *x0, const double *t0, int64_t m,
+                            double T, double dt, double *traj, uint8_t *flags, int nthreads)
+{
+    int64_t nsteps = step_count(T, dt);
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < m; ++p) {
+        double x[3] = {0, 0, 0};
+        for (int a = 0; a < v->dim; ++a) x[a] = x0[a * m + p];
+        uint32_t fl = check_point(v, x);
+        for (int64_t n = 0; n < nsteps; ++n) {
+            if (!fl) fl = rk4_step(v, x, t0[p] + (double)n * dt, dt);
+            for (int a = 0; a < v->dim; ++a) traj[(n * v->dim + a) * m + p] = x[a];
+        }
+        if (flags) flags[p] = (uint8_t)fl;
+    }
+    (void)nthreads;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Flow-map gradient and Cauchy-Green tensor                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient of the flow map at one seed with integer coordinates ijk, from the
+ * final positions of the seed (xc) and of its lower and upper neighbours
+ * along each axis b (xm[b], xp[b]); each is a dim-vector.
+ *   interior (and every periodic axis):  J[a][b] = (F_a(+) - F_a(-)) / (2 h_b)
+ *   non-periodic first seed (i = 0):     J[a][b] = (F_a(i+1) - F_a(i)) / h_b
+ *   non-periodic last seed (i = n-1):    J[a][b] = (F_a(i) - F_a(i-1)) / h_b
+ * (one-sided first-order differences at edges are the reading; the paper
+ * only names central differences).  On a periodic axis the neighbour across
+ * the seam is the seed on the far side, and its component b is shifted by the
+ * period L_b = n_b h_b: F(x0 + L e_b) = F(x0) + L e_b for a periodic field.
+ * Then C = J^T J, packed (xx, xy, yy) in 2D or (xx, xy, xz, yy, yz, zz) in 3D. */
+void orc_cg_point(const orc_seed_grid *g, const int64_t *ijk, const double *xc,
+                  const double *const *xm, const double *const *xp, double *Cpacked)
+{
+    int d = g->dim;
+    double J[3][3] = {{0}};
+    for (int b = 0; b < d; ++b) {
+        int64_t i = ijk[b], n = g->n[b];
+        double h = g->spacing[b];
+        if (axis_periodic(g->periodic_mask, b)) {
+            double L = (double)n * h;
+            double shift_p = (i + 1 >= n) ? L : 0.0;
+            double shift_m = (i - 1 < 0) ? -L : 0.0;
+            for (int a = 0; a < d; ++a) {
+                double fp = xp[b][a] + (a == b ? shift_p : 0.0);
+                double fm = xm[b][a] + (a == b ? shift_m : 0.0);
+                J[a][b] = (fp - fm) / (2.0 * h);
+            }
+        } else if (i == 0) {
+            for (int a = 0; a < d; ++a) J[a][b] = (xp[b][a] - xc[a]) / h;
+        } else if (i == n - 1) {
+            for (int a = 0; a < d; ++a) J[a][b] = (xc[a] - xm[b][a]) / h;
+        } else {
+            for (int a = 0; a < d; ++a) J[a][b] = (xp[b][a] - xm[b][a]) / (2.0 * h);
+        }
+    }
+    int k = 0;
+    for (int r = 0; r < d; ++r)
+        for (int s = r; s < d; ++s) {
+            double acc = 0.0;
+            for (int a = 0; a < d; ++a) acc += J[a][r] * J[a][s];
+            Cpacked[k++] = acc;
+        }
+}
+
+/* Neighbour index along axis b: wraps on periodic axes, clamps (and is then
+ * unused or equal to the seed) on non-periodic ones. */
+static int64_t neighbour(const orc_seed_grid *g, int b, int64_t i, int dir)
+{
+    int64_t n = g->n[b];
+    int64_t j = i + dir;
+    if (axis_periodic(g->periodic_mask, b)) {
+        if (j < 0) j += n;
+        if (j >= n) j -= n;
+    } else {
+        if (j < 0) j = 0;
+        if (j >= n) j = n - 1;
+    }
+    return j;
+}
+
+/* C on the whole seed grid from final positions xf (dim x Ns).  flags (may be
+ * NULL) marks tracers that left the domain or met non-finite data; every seed
+ * whose stencil (itself and the neighbours it differences) holds a flagged
+ * tracer gets STENCIL_OUT in sflags.  C is packed SoA: C[q*Ns + s]. */
+void orc_cg_tensor(const orc_seed_grid *g, const double *xf, const uint8_t *flags, double *C,
+                   uint8_t *sflags, int nthreads)
+{
+    int d = g->dim;
+    int64_t Ns = g->n[0] * g->n[1] * g->n[2];
+    int nq = d * (d + 1) / 2;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t s = 0; s < Ns; ++s) {
+        int64_t ijk[3] = {s % g->n[0], (s / g->n[0]) % g->n[1], s / (g->n[0] * g->n[1])};
+        int64_t stride[3] = {1, g->n[0], g->n[0] * g->n[1]};
+        double xc[3], xmv[3][3], xpv[3][3];
+        const double *xm[3], *xp[3];
+        uint8_t any = flags ? flags[s] : 0;
+        for (int a = 0; a < d; ++a) xc[a] = xf[a * Ns + s];
+        for (int b = 0; b < d; ++b) {
+            int64_t im = neighbour(g, b, ijk[b], -1), ip = neighbour(g, b, ijk[b], +1);
+            int64_t sm = s + (im - ijk[b]) * stride[b];
+            int64_t sp = s + (ip - ijk[b]) * stride[b];
+            for (int a = 0; a < d; ++a) {
+                xmv[b][a] = xf[a * Ns + sm];
+                xpv[b][a] = xf[a * Ns + sp];
+            }
+            xm[b] = xmv[b];
+            xp[b] = xpv[b];
+            if (flags) any |= flags[sm] | flags[sp];
+        }
+        double Cp[6];
+        orc_cg_point(g, ijk, xc, xm, xp, Cp);
+        for (int q = 0; q < nq; ++q) C[q * Ns + s] = Cp[q];
+        if (sflags) sflags[s] = any ? ORC_FLAG_STENCIL_OUT : 0;
+    }
+    (void)nthreads;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Largest eigenvalue and FTLE                                                */
+/* ------------------------------------------------------------------------ */
+
+/* 2x2 symmetric [[a, b], [b, c]]: lambda_max = (a+c)/2 + sqrt(((a-c)/2)^2 + b^2). */
+static double eig_max_sym2(const double *c)
+{
+    double a = c[0], b = c[1], d = c[2];
+    return 0.5 * (a + d) + hypot(0.5 * (a - d), b);
+}
+
+/* 3x3 symmetric: cyclic Jacobi.  Each rotation J(p,q,theta) is chosen so that
+ * (J^T A J)[p][q] = 0 (Golub & Van Loan, symmetric Schur decomposition); the
+ * product J^T A J is formed explicitly.  Sweeps stop when the off-diagonal
+ * mass is negligible against the diagonal; lambda_max is the largest diagonal
+ * entry. */
+static double eig_max_sym3(const double *c)
+{
+    double A[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+    static const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off == 0.0 || off <= 1e-36 * dia) break;
+        for (int r = 0; r < 3; ++r) {
+            int p = pairs[r][0], q = pairs[r][1];
+            if (A[p][q] == 0.0) continue;
+            double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+            double t = (tau >= 0.0) ? 1.0 / (tau + hypot(1.0, tau))
+                                    : 1.0 / (tau - hypot(1.0, tau));
+            double cs = 1.0 / sqrt(1.0 + t * t);
+            double sn = t * cs;
+            double R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+            R[p][p] = cs;
+            R[q][q] = cs;
+            R[p][q] = sn;
+            R[q][p] = -sn;
+            double T1[3][3], B[3][3];
+            for (int i = 0; i < 3; ++i)          /* T1 = A R */
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k) acc += A[i][k] * R[k][j];
+                    T1[i][j] = acc;
+                }
+            for (int i = 0; i < 3; ++i)          /* B = R^T T1 */
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k) acc += R[k][i] * T1[k][j];
+                    B[i][j] = acc;
+                }
+            for (int i = 0; i < 3; ++i)          /* keep exact symmetry */
+                for (int j = 0; j < 3; ++j) A[i][j] = (i <= j) ? B[i][j] : B[j][i];
+            A[p][q] = A[q][p] = 0.0;
+        }
+    }
+    double m = A[0][0];
+    if (A[1][1] > m) m = A[1][1];
+    if (A[2][2] > m) m = A[2][2];
+    return m;
+}
+
+double orc_lambda_max(int dim, const double *Cpacked)
+{
+    return dim == 2 ? eig_max_sym2(Cpacked) : eig_max_sym3(Cpacked);
+}
+
+/* FTLE (reading: the standard definition of the cited FTLE work)
+ *   sigma = ln(lambda_max) / (2 |T|);  lambda_max <= 0 (only if grad F = 0)
+ * gives -inf.  C is packed SoA with Ns points; lam and ftle may be NULL. */
+void orc_ftle(int dim, int64_t Ns, const double *C, double T, double *lam, double *ftle,
+              int nthreads)
+{
+    int nq = dim * (dim + 1) / 2;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+    for (int64_t s = 0; s < Ns; ++s) {
+        double c[6];
+        for (int q = 0; q < nq; ++q) c[q] = C[q * Ns + s];
+        double l = orc_lambda_max(dim, c);
+        if (lam) lam[s] = l;
+        if (ftle) ftle[s] = (l > 0.0) ? log(l) / (2.0 * fabs(T)) : -INFINITY;
+    }
+    (void)nthreads;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
