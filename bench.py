@@ -1,0 +1,169 @@
+"""Benchmark of the LCS hot path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+lcs_advect (seed grid -> RK4 flow map) -> lcs_cg_tensor (grad F, C) ->
+lcs_ftle (lambda_max, FTLE), on the time-dependent ABC flow sampled on a
+128^3 periodic grid (33 FP32 frames, t in [0, 16]) with 256^3 seeds,
+t0 = 0, T = 8, dt = 0.02 (400 RK4 steps).
+
+Prints one JSON line.  ``value`` is tracer-RK4-steps per second of the whole
+step; the roofline object covers the advection kernel (the dominant one),
+timed with events on the stream it is launched on; the CPU baseline is the
+FP64 oracle on a bounded sample of the same seeds, on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+BYTES_PER_STEP_3D = 768      # 4 evals x 8 corners x 2 frames x 3 comps x 4 B
+WORKLOAD = dict(name="abc_128cubed_seeds256cubed", grid=128, frames=33, dt_frame=0.5,
+                seeds=(256, 256, 256), t0=0.0, T=8.0, dt=0.02)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(fs, g, t0, T, dt, target_s):
+    """FP64 oracle on a bounded, deterministic sample of the seeds."""
+    import oracle
+    vel = oracle.Velocity(fs)
+    threads = oracle.default_threads()
+    nsteps = int(round(T / dt))
+    rng = np.random.default_rng(0)
+    m = 4096
+    idx = np.sort(rng.choice(g.count, size=m, replace=False))
+    t = time.perf_counter()
+    oracle.advect_seeds(vel, g, t0, T, dt, idx=idx, threads=threads)
+    el = time.perf_counter() - t
+    m2 = int(min(g.count, max(m, m * target_s / max(el, 1e-3))))
+    if m2 > m * 1.5:
+        idx = np.sort(rng.choice(g.count, size=m2, replace=False))
+        t = time.perf_counter()
+        oracle.advect_seeds(vel, g, t0, T, dt, idx=idx, threads=threads)
+        el = time.perf_counter() - t
+        m = m2
+    return {"value": m * nsteps / el, "unit": "tracer-RK4-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{m} seeds drawn from the 256^3 grid (seed 0), full T=8 ({nsteps} RK4 steps), "
+                      f"FP64, OpenMP, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the hot path is measured on a single MI355X; "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2209_13775_amd import inputs, lcs
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W = WORKLOAD
+    L = 2 * math.pi
+    fs = inputs.abc_frames(n=W["grid"], n_frames=W["frames"], dt_frame=W["dt_frame"])
+    g = inputs.periodic_seeds(3, W["seeds"], (L, L, L))
+    ns = g.count
+    nsteps = int(round(W["T"] / W["dt"]))
+    frames = lcs.DeviceFrames(fs, device=dev)
+    xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
+    cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    Cm = torch.empty((6, ns), dtype=torch.float64, device=dev)
+    sfl = torch.empty(ns, dtype=torch.uint8, device=dev)
+    lam = torch.empty(ns, dtype=torch.float64, device=dev)
+    sig = torch.empty(ns, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        lcs.lcs_advect(frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        lcs.lcs_cg_tensor(g, xf, flags, Cm, sfl, stream=stream)
+        lcs.lcs_ftle(3, Cm, W["T"], lam, sig, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    print(f"bench: workload {W['name']}: {ns} seeds x {nsteps} steps; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lcs.lcs_sync_status()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+        print(f"bench: step {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    lcs.lcs_sync_status()
+    adv_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    cgf_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_per_step = wall * 1e3 / args.steps
+    tracer_steps = ns * nsteps
+    value = tracer_steps / (ms_per_step * 1e-3)
+    achieved = BYTES_PER_STEP_3D * tracer_steps / (adv_ms * 1e-3) / 1e9
+    nflag = int((flags != 0).sum().item())
+    out = {
+        "metric": "tracer-RK4-steps/s (whole hot path: advect + C + FTLE), 1 GPU",
+        "value": value,
+        "unit": "tracer-RK4-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "dtype_detail": "advection and interpolation f32; gradient, C, lambda_max, FTLE f64",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "field": "time-dependent ABC flow",
+                   "grid": [W["grid"]] * 3, "frames": W["frames"], "seeds": list(W["seeds"]),
+                   "t0": W["t0"], "T": W["T"], "dt": W["dt"], "rk4_steps": nsteps},
+        "advect_ms": adv_ms,
+        "cg_ftle_ms": cgf_ms,
+        "tracer_steps_per_s_advect_kernel": tracer_steps / (adv_ms * 1e-3),
+        "ftle_points_per_s": ns / (cgf_ms * 1e-3),
+        "flagged_tracers": nflag,
+        "roofline": {"kernel": "advect_grid_kernel<3>", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
+                     "units_per_launch": tracer_steps},
+        "cpu_baseline": None,
+    }
+    del frames, xf, cell, flags, Cm, sfl, lam, sig
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(fs, g, W["t0"], W["T"], W["dt"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * lcs.h -- C ABI of the MI355X (gfx950) LCS flow-map / FTLE library.
+ *
+ * Method: Ameli, Desai & Shadden, "Development of an efficient and flexible
+ * pipeline for Lagrangian coherent structure computation".  The library
+ * implements the data-parallel hot path of that pipeline:
+ *
+ *   seed grid (Sec. 2, Seed filter)
+ *     -> RK4 advection through gridded, time-dependent velocity frames with
+ *        space-time interpolation (Eq. 2; Sec. 2 Interpolator and Flow Map
+ *        filters; Sec. 3.1)
+ *     -> flow-map gradient by central differences on the seed grid and the
+ *        Cauchy-Green tensor C = grad(F)^T grad(F) (Eq. 1; Sec. 2 Cauchy-Green
+ *        filter)
+ *     -> largest eigenvalue of C and the FTLE (Sec. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers marked [device] are HIP device pointers (HBM); [host] are host
+ *   pointers.  The caller owns every buffer; the library keeps no pointer after
+ *   a call returns, except where a plan says otherwise.
+ * - Arrays are contiguous and dense.  Outputs must not alias inputs.
+ * - Vector fields over N points are structure-of-arrays: component a of point
+ *   p is at [a*N + p].  Seed-grid arrays are in natural seed order (x index
+ *   fastest, then y, then z).
+ * - Every call validates all arguments on the host BEFORE anything is
+ *   launched; a non-OK status means nothing was enqueued or written.
+ * - Work is enqueued asynchronously on the caller's stream (hipStream_t passed
+ *   as void*, NULL = the default stream).  A kernel fault surfaces as
+ *   LCS_E_HIP from a later call or from lcs_sync_status().
+ * - lcs_last_error() returns a thread-local description of the last non-OK
+ *   status returned on the calling thread.
+ * - Advection arithmetic is FP32; the gradient, C, lambda_max and the FTLE are
+ *   FP64.
+ */
+#ifndef LCS_H
+#define LCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LCS_OK = 0,
+    LCS_E_ARG = -1,          /* NULL required pointer, bad dim, bad count          */
+    LCS_E_SHAPE = -2,        /* grid sizes out of the supported range              */
+    LCS_E_TIME_RANGE = -3,   /* [t0, t0+T] leaves the span of the frames           */
+    LCS_E_SEED_DOMAIN = -4,  /* a seed lies outside a non-periodic velocity axis   */
+    LCS_E_STEP = -5,         /* T/dt not integral, sign(dt) != sign(T), or T == 0  */
+    LCS_E_HIP = -6,          /* HIP launch or runtime failure                      */
+    LCS_E_UNSUPPORTED = -7   /* valid request this build does not handle           */
+} lcs_status;
+
+/* Per-tracer flag bits (uint8). */
+enum {
+    LCS_FLAG_OUT = 1u,         /* a stage point or new position left the closed domain */
+    LCS_FLAG_NONFINITE = 2u,   /* a position or sampled velocity was not finite         */
+    LCS_FLAG_STENCIL_OUT = 4u, /* (C / FTLE) a tracer of the difference stencil is flagged */
+    LCS_FLAG_TIME_OUT = 8u     /* (points) the tracer's interval leaves the frame span  */
+};
+
+/*
+ * Gridded, time-dependent velocity data (Sec. 2 Interpolator filter: the
+ * frames are held in GPU memory; here every frame stays resident in HBM).
+ *
+ * dim          2 or 3.
+ * n[a]         nodes along axis a (n[2] == 1 in 2D); n[a] >= 2, and
+ *              n0*n1*n2 < 2^31.
+ * origin[a],   node i of axis a sits at origin[a] + i*spacing[a].
+ * spacing[a]   spacing[a] > 0.
+ * periodic_mask  bit a set: axis a is periodic with period n[a]*spacing[a]
+ *              (no duplicated end node).  Otherwise the domain along a is the
+ *              closed interval [origin, origin + (n-1)*spacing].
+ * n_frames     >= 2; frame f holds the field at t_first + f*dt_frame,
+ *              dt_frame > 0.
+ * u[c]         [device] FP32, component c for all frames:
+ *              u[c][f*n0*n1*n2 + i + n0*(j + n1*k)]  (structure of arrays).
+ *              u[2] is ignored in 2D.
+ */
+typedef struct {
+    int32_t dim;
+    int32_t n_frames;
+    int64_t n[3];
+    double origin[3];
+    double spacing[3];
+    uint32_t periodic_mask;
+    uint32_t reserved;        /* must be 0 */
+    double t_first;
+    double dt_frame;
+    const float *u[3];
+} lcs_velocity_t;
+
+/*
+ * Structured seed grid (Sec. 2 Seed filter): seed (i,j,k) starts at
+ * origin + (i,j,k)*spacing.  A periodic seed axis (bit a of periodic_mask)
+ * has period n[a]*spacing[a], which must equal the velocity period on that
+ * axis; the gradient then differences across the seam.  n[a] >= 2 on every
+ * axis < dim, n[2] == 1 in 2D.
+ */
+typedef struct {
+    int32_t dim;
+    uint32_t periodic_mask;
+    int64_t n[3];
+    double origin[3];
+    double spacing[3];
+} lcs_seed_grid_t;
+
+/* One integration window of a batched call: start time and signed duration. */
+typedef struct {
+    double t0;
+    double T;
+} lcs_window_t;
+
+/*
+ * lcs_advect -- flow map F_{t0}^{t0+T} of a structured seed grid (Eq. 2;
+ * Sec. 2 Seed and Flow Map filters; Sec. 3.1 RK4).
+ *
+ * Every seed is integrated with N = T/dt classical RK4 steps,
+ * t_n = t0 + n*dt, through the velocity interpolated multilinearly in space
+ * and linearly in time between the two frames bracketing t.  Backward
+ * integration uses T < 0, dt < 0.  Positions on periodic axes are unwrapped.
+ * A tracer whose stage point or new position leaves the closed domain (or
+ * meets a non-finite value) is frozen at its last accepted position and
+ * flagged.  Seeds are generated on the device from the descriptor.
+ *
+ * xf     [device] FP32, dim x Ns (Ns = n0*n1*n2), final positions.
+ * cell   [device] int64, Ns, or NULL: lower-corner linear index
+ *        i + n0*(j + n1*k) of the velocity cell holding the final position,
+ *        computed in FP64 from the returned FP32 position.
+ * flags  [device] uint8, Ns, or NULL: LCS_FLAG_OUT / LCS_FLAG_NONFINITE.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_TIME_RANGE, LCS_E_SEED_DOMAIN,
+ *         LCS_E_STEP, LCS_E_HIP.
+ */
+lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                      double t0, double T, double dt,
+                      float *xf, int64_t *cell, uint8_t *flags, void *stream);
+
+/*
+ * lcs_advect_points -- flow map of arbitrary points, each with its own start
+ * time (Eq. 2): the same integrator as lcs_advect over the duration T.
+ * Used to resume segments, to draw check samples and to produce training
+ * pairs for the surrogate.
+ *
+ * x0     [device] FP32, dim x n, start positions.
+ * t0     [device] FP64, n, start time of each point.  A point whose
+ *        interval [t0, t0+T] leaves the frame span is not advected and gets
+ *        LCS_FLAG_TIME_OUT (its xf is x0).
+ * xf, cell, flags as in lcs_advect (cell and flags may be NULL).
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_STEP, LCS_E_HIP.
+ */
+lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0,
+                             int64_t n, double T, double dt,
+                             float *xf, int64_t *cell, uint8_t *flags, void *stream);
+
+/*
+ * lcs_cg_tensor -- Cauchy-Green tensor on the seed grid (Eq. 1; Sec. 2
+ * Cauchy-Green filter: central differences of the final positions over the
+ * seed grid).
+ *
+ * grad F is formed in FP64 from the FP32 positions: central differences
+ * (F(x+h e_b) - F(x-h e_b)) / (2h) in the interior and on periodic axes (the
+ * neighbour across a seam is shifted by the period along its own axis),
+ * first-order one-sided differences on the first and last seed of a
+ * non-periodic axis.  C = grad(F)^T grad(F).
+ *
+ * xf            [device] FP32, dim x Ns, as written by lcs_advect.
+ * flags         [device] uint8, Ns, or NULL: tracer flags from lcs_advect.
+ * C             [device] FP64, packed symmetric, nq x Ns with nq = 3 (2D:
+ *               xx, xy, yy) or 6 (3D: xx, xy, xz, yy, yz, zz).
+ * stencil_flags [device] uint8, Ns, or NULL: LCS_FLAG_STENCIL_OUT where the
+ *               seed or a neighbour it differences carries a flag.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP.
+ */
+lcs_status lcs_cg_tensor(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
+                         double *C, uint8_t *stencil_flags, void *stream);
+
+/*
+ * lcs_ftle -- largest eigenvalue of C and the FTLE field (Sec. 1: the FTLE
+ * derives from the largest eigenvalue of C; Sec. 2 Cauchy-Green filter).
+ *
+ * sigma = ln(lambda_max) / (2|T|); lambda_max <= 0 gives -inf.  FP64.
+ * dim         2 or 3.   n_points >= 1.
+ * C           [device] FP64 packed, nq x n_points (layout of lcs_cg_tensor).
+ * lambda_max  [device] FP64, n_points, or NULL.
+ * ftle        [device] FP64, n_points, or NULL (not both NULL).
+ * Errors: LCS_E_ARG, LCS_E_HIP.
+ */
+lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T,
+                    double *lambda_max, double *ftle, void *stream);
+
+/*
+ * lcs_cg_ftle -- lcs_cg_tensor followed by lcs_ftle in one pass, without
+ * materialising C (same arithmetic, same results).  For large seed grids.
+ * lambda_max, ftle, stencil_flags [device] FP64/FP64/uint8, Ns, each may be
+ * NULL but not lambda_max and ftle both.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP.
+ */
+lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
+                       double T, double *lambda_max, double *ftle, uint8_t *stencil_flags,
+                       void *stream);
+
+/* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
+lcs_status lcs_sync_status(void *stream);
+
+/* lcs_last_error -- thread-local text for the last non-OK status ("" if none). */
+const char *lcs_last_error(void);
+
+/* lcs_version -- library ABI version (major*10000 + minor*100 + patch). */
+int32_t lcs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCS_H */

@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liblcs_oracle.so")
 FLAG_OUT = 1
 FLAG_NONFINITE = 2
 FLAG_STENCIL_OUT = 4
+FLAG_TIME_OUT = 8
 
 
 def build(force: bool = True) -> str:
@@ -64,8 +65,8 @@ def lib():
             "orc_cell_index_many": (None, [P, P, I64, P]),
             "orc_in_domain": (C.c_int, [P, P]),
             "orc_velocity_at_many": (None, [P, P, P, I64, P]),
-            "orc_advect_points": (None, [P, P, P, I64, D, D, P, P, P, C.c_int]),
-            "orc_advect_seeds": (None, [P, P, P, I64, D, D, D, P, P, P, C.c_int]),
+            "orc_advect_points": (None, [P, P, P, I64, D, D, P, P, P, P, C.c_int]),
+            "orc_advect_seeds": (None, [P, P, P, I64, D, D, D, P, P, P, P, C.c_int]),
             "orc_advect_points_traj": (None, [P, P, P, I64, D, D, P, P, C.c_int]),
             "orc_seed_points": (None, [P, P, I64, P]),
             "orc_cg_point": (None, [P, P, P, P, P, P]),
@@ -152,17 +153,19 @@ def cell_index(vel: Velocity, x: np.ndarray) -> np.ndarray:
     return out
 
 
-def advect_points(vel: Velocity, x0: np.ndarray, t0, T: float, dt: float, threads=None):
-    """RK4 flow map of arbitrary points; returns (xf, cell, flags)."""
+def advect_points(vel: Velocity, x0: np.ndarray, t0, T: float, dt: float, threads=None,
+                  margin: bool = False):
+    """RK4 flow map of arbitrary points; returns (xf, cell, flags[, margin])."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     m = x0.shape[1]
     tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.float64), (m,)))
     xf = np.empty_like(x0)
     cell = np.empty(m, dtype=np.int64)
     flags = np.empty(m, dtype=np.uint8)
+    mg = np.empty(m) if margin else None
     lib().orc_advect_points(vel.ref, _ptr(x0), _ptr(tt), m, float(T), float(dt), _ptr(xf),
-                            _ptr(cell), _ptr(flags), threads or default_threads())
-    return xf, cell, flags
+                            _ptr(cell), _ptr(flags), _ptr(mg), threads or default_threads())
+    return (xf, cell, flags, mg) if margin else (xf, cell, flags)
 
 
 def advect_points_traj(vel: Velocity, x0: np.ndarray, t0, T: float, dt: float, threads=None):
@@ -189,8 +192,9 @@ def seed_points(g, idx: Optional[np.ndarray] = None) -> np.ndarray:
     return out
 
 
-def advect_seeds(vel: Velocity, g, t0: float, T: float, dt: float, idx=None, threads=None):
-    """RK4 flow map of the seed grid (or of the seeds idx); returns (xf, cell, flags)."""
+def advect_seeds(vel: Velocity, g, t0: float, T: float, dt: float, idx=None, threads=None,
+                 margin: bool = False):
+    """RK4 flow map of the seed grid (or of the seeds idx); returns (xf, cell, flags[, margin])."""
     sg = _seeds(g)
     if idx is not None:
         idx = np.ascontiguousarray(idx, dtype=np.int64)
@@ -200,9 +204,10 @@ def advect_seeds(vel: Velocity, g, t0: float, T: float, dt: float, idx=None, thr
     xf = np.empty((g.dim, m), dtype=np.float64)
     cell = np.empty(m, dtype=np.int64)
     flags = np.empty(m, dtype=np.uint8)
+    mg = np.empty(m) if margin else None
     lib().orc_advect_seeds(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(T), float(dt),
-                           _ptr(xf), _ptr(cell), _ptr(flags), threads or default_threads())
-    return xf, cell, flags
+                           _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg), threads or default_threads())
+    return (xf, cell, flags, mg) if margin else (xf, cell, flags)
 
 
 def cg_tensor(g, xf: np.ndarray, flags: Optional[np.ndarray] = None, threads=None):

@@ -42,6 +42,7 @@
 #define ORC_FLAG_OUT 1u
 #define ORC_FLAG_NONFINITE 2u
 #define ORC_FLAG_STENCIL_OUT 4u
+#define ORC_FLAG_TIME_OUT 8u
 
 /* Velocity frames, structure of arrays: component c of node (i,j,k) in frame f
  * is u[c][f*n0*n1*n2 + i + n0*(j + n1*k)].  Node i of axis a is at
@@ -233,9 +234,20 @@ static int all_finite(const double *x, int dim)
 
 /* Check a point at which the field is about to be sampled (or a new
  * position): non-finite -> NONFINITE, outside the closed domain -> OUT. */
-static uint32_t check_point(const orc_velocity *v, const double *p)
+static uint32_t check_point(const orc_velocity *v, const double *p, double *margin)
 {
     if (!all_finite(p, v->dim)) return ORC_FLAG_NONFINITE;
+    if (margin) {
+        /* diagnostic only: smallest distance of a checked point to the
+         * boundary of the closed domain (negative outside) */
+        for (int a = 0; a < v->dim; ++a) {
+            if (axis_periodic(v->periodic_mask, a)) continue;
+            double lo = v->origin[a];
+            double hi = v->origin[a] + (double)(v->n[a] - 1) * v->spacing[a];
+            double d = fmin(p[a] - lo, hi - p[a]);
+            if (d < *margin) *margin = d;
+        }
+    }
     if (!orc_in_domain(v, p)) return ORC_FLAG_OUT;
     return 0;
 }
@@ -249,7 +261,7 @@ static uint32_t check_point(const orc_velocity *v, const double *p)
  * Reading of the exit rule: if any stage point or x' is non-finite or outside
  * the closed domain (or a sampled velocity is non-finite), the step is
  * rejected, x is left unchanged and the matching flag is returned. */
-static uint32_t rk4_step(const orc_velocity *v, double *x, double t, double dt)
+static uint32_t rk4_step(const orc_velocity *v, double *x, double t, double dt, double *margin)
 {
     int d = v->dim;
     double k1[3], k2[3], k3[3], k4[3], p[3], xn[3];
@@ -259,23 +271,23 @@ static uint32_t rk4_step(const orc_velocity *v, double *x, double t, double dt)
     if (!all_finite(k1, d)) return ORC_FLAG_NONFINITE;
 
     for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k1[a];
-    if ((fl = check_point(v, p))) return fl;
+    if ((fl = check_point(v, p, margin))) return fl;
     orc_velocity_at(v, p, t + 0.5 * dt, k2);
     if (!all_finite(k2, d)) return ORC_FLAG_NONFINITE;
 
     for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k2[a];
-    if ((fl = check_point(v, p))) return fl;
+    if ((fl = check_point(v, p, margin))) return fl;
     orc_velocity_at(v, p, t + 0.5 * dt, k3);
     if (!all_finite(k3, d)) return ORC_FLAG_NONFINITE;
 
     for (int a = 0; a < d; ++a) p[a] = x[a] + dt * k3[a];
-    if ((fl = check_point(v, p))) return fl;
+    if ((fl = check_point(v, p, margin))) return fl;
     orc_velocity_at(v, p, t + dt, k4);
     if (!all_finite(k4, d)) return ORC_FLAG_NONFINITE;
 
     for (int a = 0; a < d; ++a)
         xn[a] = x[a] + (dt / 6.0) * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
-    if ((fl = check_point(v, xn))) return fl;
+    if ((fl = check_point(v, xn, margin))) return fl;
 
     for (int a = 0; a < d; ++a) x[a] = xn[a];
     return 0;
@@ -285,16 +297,28 @@ static uint32_t rk4_step(const orc_velocity *v, double *x, double t, double dt)
  * recomputed every step (never accumulated).  A rejected step freezes the
  * tracer and records its flag.  A starting point that is non-finite or
  * outside the domain is flagged before any step. */
-static uint32_t advect_one(const orc_velocity *v, double *x, double t0, int64_t nsteps, double dt)
+static uint32_t advect_one(const orc_velocity *v, double *x, double t0, int64_t nsteps, double dt,
+                           double *margin)
 {
-    uint32_t fl = check_point(v, x);
+    uint32_t fl = check_point(v, x, margin);
     if (fl) return fl;
     for (int64_t n = 0; n < nsteps; ++n) {
         double t = t0 + (double)n * dt;
-        fl = rk4_step(v, x, t, dt);
+        fl = rk4_step(v, x, t, dt, margin);
         if (fl) return fl;
     }
     return 0;
+}
+
+/* No extrapolation in time (the paper cautions against extrapolating the
+ * velocity, Sec. 2 Flow Map filter): a point whose interval [t0, t0+T] is not
+ * inside the frame span [t_first, t_first + (F-1) dt_frame] is not advected
+ * and is flagged TIME_OUT. */
+static int time_span_ok(const orc_velocity *v, double t0, double T)
+{
+    double t_last = v->t_first + (double)(v->n_frames - 1) * v->dt_frame;
+    double t1 = t0 + T;
+    return t0 >= v->t_first && t0 <= t_last && t1 >= v->t_first && t1 <= t_last;
 }
 
 /* Number of fixed steps: N = round(T/dt).  The caller has checked that T/dt
@@ -303,10 +327,12 @@ static int64_t step_count(double T, double dt) { return (int64_t)llround(T / dt)
 
 /* Advect arbitrary points x0 (dim x m, SoA), each from its own t0[p], over
  * the same duration T with step dt.  Outputs (any may be NULL): xf (dim x m),
- * cell (m), flags (m). */
+ * cell (m), flags (m), margin (m): the smallest distance of any checked stage
+ * point or position to the boundary of the closed domain (a diagnostic used
+ * to tell which tracers sit too close to a wall for an FP32 run to agree). */
 void orc_advect_points(const orc_velocity *v, const double *x0, const double *t0, int64_t m,
                        double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
-                       int nthreads)
+                       double *margin, int nthreads)
 {
     int64_t nsteps = step_count(T, dt);
 #ifdef _OPENMP
@@ -316,7 +342,10 @@ void orc_advect_points(const orc_velocity *v, const double *x0, const double *t0
     for (int64_t p = 0; p < m; ++p) {
         double x[3] = {0, 0, 0};
         for (int a = 0; a < v->dim; ++a) x[a] = x0[a * m + p];
-        uint32_t fl = advect_one(v, x, t0[p], nsteps, dt);
+        double mg = INFINITY;
+        uint32_t fl = time_span_ok(v, t0[p], T) ? advect_one(v, x, t0[p], nsteps, dt, &mg)
+                                                : ORC_FLAG_TIME_OUT;
+        if (margin) margin[p] = mg;
         if (xf)
             for (int a = 0; a < v->dim; ++a) xf[a * m + p] = x[a];
         if (cell) cell[p] = orc_cell_index(v, x);
@@ -351,7 +380,7 @@ void orc_seed_points(const orc_seed_grid *g, const int64_t *idx, int64_t m, doub
  * idx: xf is dim x m. */
 void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64_t *idx, int64_t m,
                       double t0, double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
-                      int nthreads)
+                      double *margin, int nthreads)
 {
     int64_t nsteps = step_count(T, dt);
 #ifdef _OPENMP
@@ -361,7 +390,9 @@ void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64
     for (int64_t p = 0; p < m; ++p) {
         double x[3] = {0, 0, 0};
         seed_position(g, idx ? idx[p] : p, x);
-        uint32_t fl = advect_one(v, x, t0, nsteps, dt);
+        double mg = INFINITY;
+        uint32_t fl = advect_one(v, x, t0, nsteps, dt, &mg);
+        if (margin) margin[p] = mg;
         if (xf)
             for (int a = 0; a < v->dim; ++a) xf[a * m + p] = x[a];
         if (cell) cell[p] = orc_cell_index(v, x);
@@ -383,9 +414,9 @@ void orc_advect_points_traj(const orc_velocity *v, const double *x0, const doubl
     for (int64_t p = 0; p < m; ++p) {
         double x[3] = {0, 0, 0};
         for (int a = 0; a < v->dim; ++a) x[a] = x0[a * m + p];
-        uint32_t fl = check_point(v, x);
+        uint32_t fl = time_span_ok(v, t0[p], T) ? check_point(v, x, NULL) : ORC_FLAG_TIME_OUT;
         for (int64_t n = 0; n < nsteps; ++n) {
-            if (!fl) fl = rk4_step(v, x, t0[p] + (double)n * dt, dt);
+            if (!fl) fl = rk4_step(v, x, t0[p] + (double)n * dt, dt, NULL);
             for (int a = 0; a < v->dim; ++a) traj[(n * v->dim + a) * m + p] = x[a];
         }
         if (flags) flags[p] = (uint8_t)fl;

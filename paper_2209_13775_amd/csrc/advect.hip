@@ -1,0 +1,407 @@
+// advect.hip -- RK4 flow-map kernels for gfx950.
+//
+// One lane = one tracer.  The whole integration (all N steps, all four RK4
+// stages) runs inside one kernel with the tracer state in registers; the
+// paper split every stage into its own kernel to fit Kepler's 31-register
+// budget (Sec. 3.1), which CDNA's 512-VGPR lanes do not need.
+//
+// Per evaluation (Sec. 2 Interpolator; Sec. 3.2): locate the cell on each
+// axis, gather the 2^D corners of the two frames that bracket t from the
+// structure-of-arrays frames, multilinear weights in space, then linear in
+// time.  Seeds, positions and stage points are carried as two-floats
+// (hi + lo): chaotic flows amplify any start or position rounding by
+// exp(sigma T), so only the FP32 interpolation arithmetic itself is left to
+// round.
+
+#include "lcs_internal.h"
+
+namespace lcs {
+namespace {
+
+constexpr uint32_t kOut = LCS_FLAG_OUT;
+constexpr uint32_t kNonFinite = LCS_FLAG_NONFINITE;
+constexpr uint32_t kTimeOut = LCS_FLAG_TIME_OUT;
+
+// Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Lower node, upper node and local coordinate of the two-float point
+// xh + xl along one axis.  s = (x - origin)/h is formed in two-float
+// arithmetic (the product's rounding error is recovered with an FMA), so the
+// local coordinate is accurate to FP32 rounding of xi itself rather than of
+// the unwrapped position.  Non-periodic: node = floor(s) limited to [0, n-2].
+// Periodic: s folded into [0, n) by whole periods (exact); a fold landing on
+// n is node 0.  s is clamped before any float->int conversion, so every input
+// (NaN included) yields in-range node indices.
+__device__ __forceinline__ void locate(const VelDev &v, int a, float xh, float xl, int &lo,
+                                       int &hi, float &xi)
+{
+    const int n = v.n[a];
+    const float nf = v.nf[a];
+    float dh, dl;
+    two_sum(xh, -v.oh[a], dh, dl);
+    dl += xl - v.ol[a];
+    const float sh = dh * v.ih[a];
+    const float sl = fmaf(dh, v.ih[a], -sh) + fmaf(dh, v.il[a], dl * v.ih[a]);
+    if ((v.periodic_mask >> a) & 1u) {
+        float f = sh - nf * floorf(sh * (1.0f / nf));   // exact: sh minus a multiple of n
+        f = fminf(fmaxf(f, 0.0f), nf);
+        int i = (int)f;
+        float fr = (f - (float)i) + sl;
+        if (i >= n) { i = 0; fr = sl; }
+        lo = i;
+        hi = (i + 1 == n) ? 0 : i + 1;
+        xi = fr;
+    } else {
+        const float f = fminf(fmaxf(sh, 0.0f), nf - 1.0f);
+        const int i = min((int)f, n - 2);
+        lo = i;
+        hi = i + 1;
+        xi = (sh - (float)i) + sl;
+    }
+}
+
+// Frame pair bracketing t and the time weight (FP64 in, FP32 weight out).
+__device__ __forceinline__ void frame_at(const VelDev &v, double t, long long &base, float &alpha)
+{
+    double tau = (t - v.t_first) * v.inv_dt_frame;
+    tau = fmin(fmax(tau, 0.0), (double)(v.n_frames - 1));
+    int f = min((int)floor(tau), v.n_frames - 2);
+    alpha = (float)(tau - (double)f);
+    base = (long long)f * v.frame_stride;
+}
+
+// Two x-adjacent nodes (i, i+1) with one dword-aligned 8-byte load.
+__device__ __forceinline__ float2 load_pair(const float *p)
+{
+    float2 v;
+    __builtin_memcpy(&v, p, sizeof(v));
+    return v;
+}
+
+// u at the two-float point (ph + pl): multilinear in space within frames f and
+// f+1, then linear in time.  The corners of a cell come in x-adjacent pairs
+// (i, i+1) that are read with one 8-byte load per (row, frame, component);
+// on a periodic x axis the pair of the last cell wraps to node 0 and is
+// patched by a rarely taken branch.
+template <int D>
+__device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const float *pl,
+                                         long long base, float alpha, float *out)
+{
+    int lo[3], hi[3];
+    float xi[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) locate(v, a, ph[a], pl[a], lo[a], hi[a], xi[a]);
+    const float a1 = alpha, a0 = 1.0f - alpha;
+    const long long fs = v.frame_stride;
+    const int n0 = v.n[0];
+    const bool wrap = (hi[0] != lo[0] + 1);          // periodic x, last cell
+    const int px = wrap ? n0 - 2 : lo[0];             // start of the loaded pair
+    const float wx1 = xi[0], wx0 = 1.0f - xi[0];
+    constexpr int R = (D == 2) ? 2 : 4;               // rows of 2 corners
+    int row[R];
+    float wr[R];
+    if constexpr (D == 2) {
+        const float wy1 = xi[1], wy0 = 1.0f - xi[1];
+        row[0] = n0 * lo[1]; row[1] = n0 * hi[1];
+        wr[0] = wy0; wr[1] = wy1;
+    } else {
+        const int n01 = n0 * v.n[1];
+        const float wy1 = xi[1], wy0 = 1.0f - xi[1];
+        const float wz1 = xi[2], wz0 = 1.0f - xi[2];
+        const int y0 = n0 * lo[1], y1 = n0 * hi[1];
+        const int z0 = n01 * lo[2], z1 = n01 * hi[2];
+        row[0] = y0 + z0; row[1] = y1 + z0; row[2] = y0 + z1; row[3] = y1 + z1;
+        wr[0] = wy0 * wz0; wr[1] = wy1 * wz0; wr[2] = wy0 * wz1; wr[3] = wy1 * wz1;
+    }
+    float2 pa[D][R], pb[D][R];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        const float *__restrict__ A = v.u[c] + base;
+        const float *__restrict__ B = A + fs;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pa[c][r] = load_pair(A + row[r] + px);
+            pb[c][r] = load_pair(B + row[r] + px);
+        }
+    }
+    if (wrap) {
+        // cell (n0-1, 0): the loaded pair is (n0-2, n0-1); shift it and fetch node 0
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const float *__restrict__ A = v.u[c] + base;
+            const float *__restrict__ B = A + fs;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                pa[c][r] = make_float2(pa[c][r].y, A[row[r]]);
+                pb[c][r] = make_float2(pb[c][r].y, B[row[r]]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        float ua = 0.0f, ub = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ua += wr[r] * (wx0 * pa[c][r].x + wx1 * pa[c][r].y);
+            ub += wr[r] * (wx0 * pb[c][r].x + wx1 * pb[c][r].y);
+        }
+        out[c] = a0 * ua + a1 * ub;
+    }
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (!isfinite(p[a])) return kNonFinite;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (!((v.periodic_mask >> a) & 1u) && !(p[a] >= v.lo[a] && p[a] <= v.hi[a])) return kOut;
+    return 0;
+}
+
+template <int D>
+__device__ __forceinline__ bool finite_vec(const float *k)
+{
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ok = ok && isfinite(k[a]);
+    return ok;
+}
+
+// Step-size constants as two-floats, so that the FP32 rounding of dt does not
+// bias every step the same way.
+struct StepConsts {
+    float hh, hl;   // dt/2
+    float fh, fl;   // dt
+    float sh, sl;   // dt/6
+};
+
+__device__ __forceinline__ StepConsts step_consts(double dt)
+{
+    StepConsts c;
+    c.hh = (float)(0.5 * dt); c.hl = (float)(0.5 * dt - (double)c.hh);
+    c.fh = (float)dt;         c.fl = (float)(dt - (double)c.fh);
+    c.sh = (float)(dt / 6.0); c.sl = (float)(dt / 6.0 - (double)c.sh);
+    return c;
+}
+
+// Stage point (ph + pl) = (xh + xl) + (ch + cl) k, renormalised.
+template <int D>
+__device__ __forceinline__ void stage_point(const float *xh, const float *xl, float ch, float cl,
+                                            const float *k, float *ph, float *pl)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const float inc = fmaf(ch, k[a], cl * k[a]);
+        two_sum(xh[a], xl[a] + inc, ph[a], pl[a]);
+    }
+}
+
+// Integrate one tracer in place: nsteps classical RK4 steps from t0 with step
+// dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
+// two-float (x = xh + xl).  A stage point or new position that is non-finite
+// or outside the closed domain (or a non-finite sampled velocity) rejects the
+// step, freezes the tracer and returns its flag.
+template <int D>
+__device__ uint32_t advect_tracer(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                  int nsteps)
+{
+    uint32_t fl = check_point<D>(v, xh);
+    if (fl) return fl;
+    const StepConsts sc = step_consts(dt);
+    for (int n = 0; n < nsteps; ++n) {
+        const double t = t0 + (double)n * dt;
+        long long b1, b2, b4;
+        float al1, al2, al4;
+        frame_at(v, t, b1, al1);
+        frame_at(v, t + 0.5 * dt, b2, al2);
+        frame_at(v, t + dt, b4, al4);
+        float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
+
+        velocity<D>(v, xh, xl, b1, al1, k1);
+        if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
+        stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
+        if ((fl = check_point<D>(v, ph))) break;
+
+        velocity<D>(v, ph, pl, b2, al2, k2);
+        if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
+        stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
+        if ((fl = check_point<D>(v, ph))) break;
+
+        velocity<D>(v, ph, pl, b2, al2, k3);
+        if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
+        stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
+        if ((fl = check_point<D>(v, ph))) break;
+
+        velocity<D>(v, ph, pl, b4, al4, k4);
+        if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
+
+        // (xh, xl) <- (xh, xl) + dt/6 (k1 + 2k2 + 2k3 + k4)
+        float nh[3], nl[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const float sum = (k1[a] + k4[a]) + 2.0f * (k2[a] + k3[a]);
+            const float inc = fmaf(sc.sh, sum, sc.sl * sum);
+            two_sum(xh[a], xl[a] + inc, nh[a], nl[a]);
+        }
+        if ((fl = check_point<D>(v, nh))) break;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { xh[a] = nh[a]; xl[a] = nl[a]; }
+    }
+    return fl;
+}
+
+// Velocity-cell index of a returned FP32 position, in FP64 without
+// contraction: per axis s = (x - origin)/h, then the locate rule.  -1 for a
+// non-finite position.
+template <int D>
+__device__ long long cell_index(const VelDev &v, const float *x)
+{
+#pragma clang fp contract(off)
+    long long idx = 0, stride = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double xd = (double)x[a];
+        if (!isfinite(xd)) return -1;
+        const long long n = v.n[a];
+        double s = (xd - v.origin_d[a]) / v.spacing_d[a];
+        long long i;
+        if ((v.periodic_mask >> a) & 1u) {
+            const double nd = (double)n;
+            s = s - nd * floor(s / nd);
+            s = fmin(fmax(s, -1.0), nd + 1.0);
+            i = (long long)floor(s);
+            if (i >= n) i = 0;
+            if (i < 0) i = 0;
+        } else {
+            s = fmin(fmax(s, -1.0), (double)n);
+            i = (long long)floor(s);
+            if (i > n - 2) i = n - 2;
+            if (i < 0) i = 0;
+        }
+        idx += i * stride;
+        stride *= n;
+    }
+    return idx;
+}
+
+// XCD-aware block order: workgroups are dealt round-robin to the 8 XCDs, so
+// block b runs on XCD b % 8.  Give each XCD a contiguous run of the curve:
+// XCDs < r take q+1 consecutive positions, the others q (q, r = divmod(B, 8)).
+__device__ __forceinline__ int xcd_remap(int b, int nblocks)
+{
+    constexpr int kXcd = 8;
+    const int q = nblocks / kXcd, r = nblocks % kXcd;
+    const int x = b % kXcd, local = b / kXcd;
+    return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
+{
+    const SeedTiling &g = A.g;
+    const int m = xcd_remap((int)blockIdx.x, g.n_blocks);
+    // Morton decode with per-axis bit counts (an axis that runs out of bits
+    // drops out of the interleave)
+    int tc[3] = {0, 0, 0};
+    int pos = 0;
+    for (int l = 0; l < g.max_bits; ++l)
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (l < g.bits[a]) tc[a] |= ((m >> (pos++)) & 1) << l;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (tc[a] >= g.ntiles[a]) return;
+
+    const int t = threadIdx.x;
+    const int w = t / kWave, l = t % kWave;
+    int wc[3], lc[3];
+    wc[0] = w % g.wg[0];
+    wc[1] = (w / g.wg[0]) % g.wg[1];
+    wc[2] = w / (g.wg[0] * g.wg[1]);
+    lc[0] = l % g.wt[0];
+    lc[1] = (l / g.wt[0]) % g.wt[1];
+    lc[2] = l / (g.wt[0] * g.wt[1]);
+    int sc[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        sc[a] = (tc[a] * g.wg[a] + wc[a]) * g.wt[a] + lc[a];
+        if (sc[a] >= g.sn[a]) return;
+    }
+    const long long s = (long long)sc[0] + (long long)g.sn[0] * ((long long)sc[1] +
+                        (long long)g.sn[1] * (long long)sc[2]);
+    // seed position, carried exactly (to FP64 rounding) as a two-float
+    float xh[3], xl[3], x[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double x0 = g.s_origin[a] + (double)sc[a] * g.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+
+    const uint32_t fl = advect_tracer<D>(A.v, xh, xl, A.t0, A.dt, A.nsteps);
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = xh[a] + xl[a];
+
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.xf[a * A.ns + s] = x[a];
+    if (A.cell) A.cell[s] = cell_index<D>(A.v, x);
+    if (A.flags) A.flags[s] = (uint8_t)fl;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void advect_points_kernel(AdvectArgs A)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.ns) return;
+    float x[3], xl[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = A.x0[a * A.ns + p];
+    const double t0 = A.t0v[p];
+    const double t1 = t0 + A.T;
+    uint32_t fl;
+    // no extrapolation in time: the whole interval must lie in the frame span
+    if (!(t0 >= A.v.t_first && t0 <= A.v.t_last && t1 >= A.v.t_first && t1 <= A.v.t_last)) {
+        fl = kTimeOut;
+    } else {
+        fl = advect_tracer<D>(A.v, x, xl, t0, A.dt, A.nsteps);
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = x[a] + xl[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.xf[a * A.ns + p] = x[a];
+    if (A.cell) A.cell[p] = cell_index<D>(A.v, x);
+    if (A.flags) A.flags[p] = (uint8_t)fl;
+}
+
+}  // namespace
+
+hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.g.n_blocks), block(256);
+    if (dim == 2)
+        hipLaunchKernelGGL(advect_grid_kernel<2>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(advect_grid_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_points(int dim, const AdvectArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.ns + 255) / 256)), block(256);
+    if (dim == 2)
+        hipLaunchKernelGGL(advect_points_kernel<2>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(advect_points_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lcs

@@ -1,0 +1,321 @@
+// api.hip -- the C ABI declared in include/lcs.h: host-side validation,
+// work decomposition and launches.  Every argument is checked before anything
+// is enqueued.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "lcs_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lcs_status fail(lcs_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+lcs_status ok()
+{
+    g_err[0] = '\0';
+    return LCS_OK;
+}
+
+lcs_status hip_fail(hipError_t e, const char *where)
+{
+    return fail(LCS_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+constexpr long long kMaxNodes = (1LL << 31) - 1;
+constexpr long long kMaxSeeds = (1LL << 31) - 1;
+
+lcs_status check_velocity(const lcs_velocity_t *v)
+{
+    if (!v) return fail(LCS_E_ARG, "velocity descriptor is NULL");
+    if (v->dim != 2 && v->dim != 3) return fail(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
+    if (v->reserved != 0) return fail(LCS_E_ARG, "velocity reserved field must be 0");
+    if (v->n_frames < 2) return fail(LCS_E_SHAPE, "need at least 2 frames (got %d)", v->n_frames);
+    if (!finite_pos(v->dt_frame) || !isfinite(v->t_first))
+        return fail(LCS_E_ARG, "t_first must be finite and dt_frame > 0");
+    if (v->periodic_mask >> v->dim) return fail(LCS_E_ARG, "periodic_mask has bits beyond dim");
+    long long nodes = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < v->dim) {
+            if (v->n[a] < 2) return fail(LCS_E_SHAPE, "velocity axis %d needs >= 2 nodes", a);
+            if (!finite_pos(v->spacing[a]) || !isfinite(v->origin[a]))
+                return fail(LCS_E_ARG, "velocity axis %d: bad origin/spacing", a);
+            if (!v->u[a]) return fail(LCS_E_ARG, "velocity component %d pointer is NULL", a);
+        } else if (v->n[a] != 1) {
+            return fail(LCS_E_SHAPE, "velocity n[%d] must be 1 in %dD", a, v->dim);
+        }
+        nodes *= v->n[a];
+        if (nodes > kMaxNodes) return fail(LCS_E_SHAPE, "velocity frame exceeds 2^31-1 nodes");
+    }
+    return LCS_OK;
+}
+
+lcs_status check_seeds(const lcs_seed_grid_t *g, int dim)
+{
+    if (!g) return fail(LCS_E_ARG, "seed grid descriptor is NULL");
+    if (g->dim != dim) return fail(LCS_E_ARG, "seed grid dim %d != %d", g->dim, dim);
+    if (g->periodic_mask >> g->dim) return fail(LCS_E_ARG, "seed periodic_mask has bits beyond dim");
+    long long ns = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < g->dim) {
+            if (g->n[a] < 2) return fail(LCS_E_SHAPE, "seed axis %d needs >= 2 seeds", a);
+            if (!finite_pos(g->spacing[a]) || !isfinite(g->origin[a]))
+                return fail(LCS_E_ARG, "seed axis %d: bad origin/spacing", a);
+        } else if (g->n[a] != 1) {
+            return fail(LCS_E_SHAPE, "seed n[%d] must be 1 in %dD", a, g->dim);
+        }
+        ns *= g->n[a];
+        if (ns > kMaxSeeds) return fail(LCS_E_SHAPE, "seed grid exceeds 2^31-1 seeds");
+    }
+    return LCS_OK;
+}
+
+// N = T/dt must be a positive integer (to 1e-9 relative), with sign(dt) == sign(T).
+lcs_status check_steps(double T, double dt, int *nsteps)
+{
+    if (!isfinite(T) || !isfinite(dt) || T == 0.0 || dt == 0.0)
+        return fail(LCS_E_STEP, "T and dt must be finite and non-zero");
+    if ((T > 0.0) != (dt > 0.0)) return fail(LCS_E_STEP, "sign(dt) must equal sign(T)");
+    const double r = T / dt;
+    const double N = nearbyint(r);
+    if (fabs(r - N) > 1e-9 * fabs(r)) return fail(LCS_E_STEP, "T/dt = %.17g is not an integer", r);
+    if (N < 1.0 || N > 2147483647.0) return fail(LCS_E_STEP, "step count out of range");
+    *nsteps = (int)N;
+    return LCS_OK;
+}
+
+lcs::VelDev make_vel(const lcs_velocity_t *v)
+{
+    lcs::VelDev d;
+    memset(&d, 0, sizeof(d));
+    d.frame_stride = v->n[0] * v->n[1] * v->n[2];
+    for (int a = 0; a < 3; ++a) {
+        d.u[a] = a < v->dim ? v->u[a] : nullptr;
+        d.n[a] = (int)v->n[a];
+        d.nf[a] = (float)v->n[a];
+        const double inv = 1.0 / v->spacing[a];
+        d.oh[a] = (float)v->origin[a];
+        d.ol[a] = (float)(v->origin[a] - (double)d.oh[a]);
+        d.ih[a] = (float)inv;
+        d.il[a] = (float)(inv - (double)d.ih[a]);
+        d.lo[a] = (float)v->origin[a];
+        d.hi[a] = (float)(v->origin[a] + (double)(v->n[a] - 1) * v->spacing[a]);
+        d.origin_d[a] = v->origin[a];
+        d.spacing_d[a] = v->spacing[a];
+    }
+    d.periodic_mask = v->periodic_mask;
+    d.n_frames = v->n_frames;
+    d.t_first = v->t_first;
+    d.dt_frame = v->dt_frame;
+    d.inv_dt_frame = 1.0 / v->dt_frame;
+    d.t_last = v->t_first + (double)(v->n_frames - 1) * v->dt_frame;
+    return d;
+}
+
+int ceil_log2(int x)
+{
+    int b = 0;
+    while ((1 << b) < x) ++b;
+    return b;
+}
+
+lcs::SeedTiling make_tiling(const lcs_seed_grid_t *g)
+{
+    lcs::SeedTiling t;
+    memset(&t, 0, sizeof(t));
+    // wave sub-tile: 8x8 in 2D, 4x4x4 in 3D; 4 waves per workgroup as 2x2(x1)
+    const int wt2[3] = {8, 8, 1}, wt3[3] = {4, 4, 4};
+    const int wg[3] = {2, 2, 1};
+    int nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        t.sn[a] = (int)g->n[a];
+        t.s_origin[a] = g->origin[a];
+        t.s_spacing[a] = g->spacing[a];
+        t.wt[a] = (g->dim == 2) ? wt2[a] : wt3[a];
+        t.wg[a] = (a < g->dim) ? wg[a] : 1;
+        const int tile = t.wt[a] * t.wg[a];
+        t.ntiles[a] = (a < g->dim) ? (int)((g->n[a] + tile - 1) / tile) : 1;
+        t.bits[a] = (a < g->dim) ? ceil_log2(t.ntiles[a]) : 0;
+        if (t.bits[a] > t.max_bits) t.max_bits = t.bits[a];
+        nb *= (1 << t.bits[a]);
+    }
+    t.n_blocks = nb;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lcs_last_error(void) { return g_err; }
+
+int32_t lcs_version(void) { return 100; }
+
+lcs_status lcs_sync_status(void *stream)
+{
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "pending error");
+    return ok();
+}
+
+lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                      double T, double dt, float *xf, int64_t *cell, uint8_t *flags, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf) return fail(LCS_E_ARG, "xf is NULL");
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + T;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return fail(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                    vel->t_first, t_last);
+    for (int a = 0; a < vel->dim; ++a) {
+        const bool vper = (vel->periodic_mask >> a) & 1u;
+        const bool sper = (seeds->periodic_mask >> a) & 1u;
+        if (sper && !vper) return fail(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
+        if (vper) continue;
+        const double lo = vel->origin[a];
+        const double hi = vel->origin[a] + (double)(vel->n[a] - 1) * vel->spacing[a];
+        const double s0 = seeds->origin[a];
+        const double s1 = seeds->origin[a] + (double)(seeds->n[a] - 1) * seeds->spacing[a];
+        const double tol = 1e-9 * (hi - lo);
+        if (s0 < lo - tol || s1 > hi + tol)
+            return fail(LCS_E_SEED_DOMAIN, "seeds on axis %d span [%g, %g] outside [%g, %g]", a,
+                        s0, s1, lo, hi);
+    }
+    lcs::AdvectArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = make_vel(vel);
+    A.g = make_tiling(seeds);
+    A.t0 = t0;
+    A.dt = dt;
+    A.nsteps = nsteps;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+    hipError_t e = lcs::launch_advect_grid(vel->dim, A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "advect launch");
+    return ok();
+}
+
+lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0, int64_t n,
+                             double T, double dt, float *xf, int64_t *cell, uint8_t *flags,
+                             void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if (!x0 || !t0 || !xf) return fail(LCS_E_ARG, "x0, t0 and xf must not be NULL");
+    if (n < 1 || n > kMaxSeeds) return fail(LCS_E_SHAPE, "point count %lld out of range", (long long)n);
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    lcs::AdvectArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = make_vel(vel);
+    A.dt = dt;
+    A.T = T;
+    A.nsteps = nsteps;
+    A.ns = n;
+    A.x0 = x0;
+    A.t0v = t0;
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+    hipError_t e = lcs::launch_advect_points(vel->dim, A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "advect_points launch");
+    return ok();
+}
+
+static lcs_status cg_common(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
+                            lcs::CgArgs &A)
+{
+    lcs_status st;
+    if (!seeds) return fail(LCS_E_ARG, "seed grid descriptor is NULL");
+    if ((st = check_seeds(seeds, seeds->dim)) != LCS_OK) return st;
+    if (seeds->dim != 2 && seeds->dim != 3) return fail(LCS_E_ARG, "seed dim must be 2 or 3");
+    if (!xf) return fail(LCS_E_ARG, "xf is NULL");
+    if (seeds->n[1] > 65535 * 4 || seeds->n[2] > 65535)
+        return fail(LCS_E_SHAPE, "seed grid too tall for the launch shape");
+    memset(&A, 0, sizeof(A));
+    A.dim = seeds->dim;
+    for (int a = 0; a < 3; ++a) {
+        A.n[a] = (int)seeds->n[a];
+        A.h[a] = seeds->spacing[a];
+        A.period[a] = (double)seeds->n[a] * seeds->spacing[a];
+    }
+    A.periodic_mask = seeds->periodic_mask;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.xf = xf;
+    A.flags = flags;
+    return LCS_OK;
+}
+
+lcs_status lcs_cg_tensor(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
+                         double *C, uint8_t *stencil_flags, void *stream)
+{
+    lcs::CgArgs A;
+    lcs_status st = cg_common(seeds, xf, flags, A);
+    if (st != LCS_OK) return st;
+    if (!C) return fail(LCS_E_ARG, "C is NULL");
+    A.C = C;
+    A.sflags = stencil_flags;
+    hipError_t e = lcs::launch_cg(A, false, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "cg launch");
+    return ok();
+}
+
+lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags, double T,
+                       double *lambda_max, double *ftle, uint8_t *stencil_flags, void *stream)
+{
+    lcs::CgArgs A;
+    lcs_status st = cg_common(seeds, xf, flags, A);
+    if (st != LCS_OK) return st;
+    if (!lambda_max && !ftle) return fail(LCS_E_ARG, "lambda_max and ftle are both NULL");
+    if (!isfinite(T) || T == 0.0) return fail(LCS_E_ARG, "T must be finite and non-zero");
+    A.lam = lambda_max;
+    A.ftle = ftle;
+    A.sflags = stencil_flags;
+    A.inv_two_T = 1.0 / (2.0 * fabs(T));
+    hipError_t e = lcs::launch_cg(A, true, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "cg_ftle launch");
+    return ok();
+}
+
+lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T, double *lambda_max,
+                    double *ftle, void *stream)
+{
+    if (dim != 2 && dim != 3) return fail(LCS_E_ARG, "dim must be 2 or 3");
+    if (n_points < 1 || n_points > kMaxSeeds) return fail(LCS_E_SHAPE, "n_points out of range");
+    if (!C) return fail(LCS_E_ARG, "C is NULL");
+    if (!lambda_max && !ftle) return fail(LCS_E_ARG, "lambda_max and ftle are both NULL");
+    if (!isfinite(T) || T == 0.0) return fail(LCS_E_ARG, "T must be finite and non-zero");
+    lcs::FtleArgs A;
+    A.n = n_points;
+    A.C = C;
+    A.lam = lambda_max;
+    A.ftle = ftle;
+    A.inv_two_T = 1.0 / (2.0 * fabs(T));
+    hipError_t e = lcs::launch_ftle(dim, A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ftle launch");
+    return ok();
+}
+
+}  // extern "C"

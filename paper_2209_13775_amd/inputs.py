@@ -405,3 +405,21 @@ WORKLOADS = {
         field="random_fourier", n=256, frames=65, dt_frame=0.125, seeds=(512, 512, 256),
         t0=4.0, T=4.0, dt=0.01),
 }
+
+
+# ---------------------------------------------------------------------------
+# 2D periodic test field (time-modulated Taylor-Green cells)
+# ---------------------------------------------------------------------------
+
+
+def taylor_green_frames(n=64, n_frames=9, dt_frame=0.5, t_first=0.0, amp=0.5) -> FrameSet:
+    """u = amp (1 + 0.3 sin t) (sin x cos y, -cos x sin y) + (0.2, 0.1) on [0, 2pi)^2."""
+    L = 2.0 * math.pi
+    h = L / n
+
+    def fn(X, Y, t):
+        s = amp * (1.0 + 0.3 * math.sin(t))
+        return (s * np.sin(X) * np.cos(Y) + 0.2, -s * np.cos(X) * np.sin(Y) + 0.1)
+
+    return sample_field(fn, 2, (n, n), (0.0, 0.0), (h, h), (True, True), t_first, dt_frame,
+                        n_frames)

@@ -1,0 +1,320 @@
+"""ctypes binding of the C ABI in ``include/lcs.h`` (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Buffers are
+torch tensors on the GPU (PyTorch provides device memory and streams); all
+computation happens in ``liblcs_hip.so``.  There is no fallback: if the HIP
+library is missing the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblcs_hip.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lcs.h")
+
+LCS_OK = 0
+LCS_E_ARG = -1
+LCS_E_SHAPE = -2
+LCS_E_TIME_RANGE = -3
+LCS_E_SEED_DOMAIN = -4
+LCS_E_STEP = -5
+LCS_E_HIP = -6
+LCS_E_UNSUPPORTED = -7
+
+FLAG_OUT = 1
+FLAG_NONFINITE = 2
+FLAG_STENCIL_OUT = 4
+FLAG_TIME_OUT = 8
+
+_STATUS_NAMES = {0: "LCS_OK", -1: "LCS_E_ARG", -2: "LCS_E_SHAPE", -3: "LCS_E_TIME_RANGE",
+                 -4: "LCS_E_SEED_DOMAIN", -5: "LCS_E_STEP", -6: "LCS_E_HIP", -7: "LCS_E_UNSUPPORTED"}
+
+
+class LcsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lcs_velocity_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_frames", C.c_int32), ("n", C.c_int64 * 3),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("periodic_mask", C.c_uint32), ("reserved", C.c_uint32),
+                ("t_first", C.c_double), ("dt_frame", C.c_double),
+                ("u", C.c_void_p * 3)]
+
+
+class lcs_seed_grid_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("periodic_mask", C.c_uint32), ("n", C.c_int64 * 3),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class lcs_window_t(C.Structure):
+    _fields_ = [("t0", C.c_double), ("T", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, D, I64, I32 = C.c_void_p, C.c_double, C.c_int64, C.c_int32
+    sig = {
+        "lcs_advect": [P, P, D, D, D, P, P, P, P],
+        "lcs_advect_points": [P, P, P, I64, D, D, P, P, P, P],
+        "lcs_cg_tensor": [P, P, P, P, P, P],
+        "lcs_ftle": [I32, I64, P, D, P, P, P],
+        "lcs_cg_ftle": [P, P, P, D, P, P, P, P],
+        "lcs_sync_status": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.restype = C.c_int
+        fn.argtypes = args
+    L.lcs_last_error.restype = C.c_char_p
+    L.lcs_last_error.argtypes = []
+    L.lcs_version.restype = C.c_int32
+    L.lcs_version.argtypes = []
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def declared_entry_points() -> list:
+    """Names of the functions ``include/lcs.h`` declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcs_[a-z0-9_]+)\s*\(", text)))
+
+
+def lcs_last_error() -> str:
+    return _lib.lcs_last_error().decode()
+
+
+def lcs_version() -> int:
+    return int(_lib.lcs_version())
+
+
+def _check(status: int):
+    if status != LCS_OK:
+        raise LcsError(status, lcs_last_error())
+
+
+# ---------------------------------------------------------------------------
+# Descriptors
+# ---------------------------------------------------------------------------
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape, what):
+    torch = _torch()
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+class DeviceFrames:
+    """Velocity frames resident in HBM (one FP32 tensor per component) and the
+    ``lcs_velocity_t`` that describes them."""
+
+    def __init__(self, fs, device="cuda", tensors: Optional[Sequence] = None):
+        torch = _torch()
+        if tensors is None:
+            tensors = [torch.from_numpy(np.ascontiguousarray(c, dtype=np.float32)).to(device)
+                       for c in fs.u]
+        self.u = list(tensors)
+        self.fs = fs
+        d = lcs_velocity_t()
+        d.dim = fs.dim
+        d.n_frames = int(self.u[0].shape[0])
+        for a in range(3):
+            d.n[a] = int(fs.n[a])
+            d.origin[a] = float(fs.origin[a])
+            d.spacing[a] = float(fs.spacing[a])
+        d.periodic_mask = int(fs.periodic_mask)
+        d.reserved = 0
+        d.t_first = float(fs.t_first)
+        d.dt_frame = float(fs.dt_frame)
+        nodes = int(fs.n[0] * fs.n[1] * fs.n[2])
+        for c in range(3):
+            if c < fs.dim:
+                t = self.u[c]
+                _need(t, torch.float32, t.shape, f"frame component {c}")
+                if t.numel() != d.n_frames * nodes:
+                    raise ValueError("frame tensor size does not match the grid")
+                d.u[c] = t.data_ptr()
+            else:
+                d.u[c] = None
+        self.desc = d
+
+    @property
+    def dim(self) -> int:
+        return self.desc.dim
+
+    @property
+    def ref(self):
+        return C.byref(self.desc)
+
+
+def seed_grid_desc(g) -> lcs_seed_grid_t:
+    s = lcs_seed_grid_t()
+    s.dim = g.dim
+    s.periodic_mask = int(g.periodic_mask)
+    for a in range(3):
+        s.n[a] = int(g.n[a])
+        s.origin[a] = float(g.origin[a])
+        s.spacing[a] = float(g.spacing[a])
+    return s
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+
+
+def lcs_advect(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
+               xf=None, cell=None, flags=None, want_cell=True, want_flags=True, stream=None):
+    """Flow map of the seed grid; returns (xf [dim,Ns] f32, cell [Ns] i64, flags [Ns] u8)."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                           _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_advect_points(frames: DeviceFrames, x0, t0, T: float, dt: float,
+                      xf=None, cell=None, flags=None, want_cell=True, want_flags=True, stream=None):
+    """Flow map of points x0 [dim,n] (f32) with start times t0 [n] (f64)."""
+    torch = _torch()
+    d, n = int(x0.shape[0]), int(x0.shape[1])
+    dev = x0.device
+    if not isinstance(t0, torch.Tensor):
+        t0 = torch.full((n,), float(t0), dtype=torch.float64, device=dev)
+    if xf is None:
+        xf = torch.empty((d, n), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(n, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    if d != frames.dim:
+        raise ValueError("x0 dimension does not match the frames")
+    _need(x0, torch.float32, (d, n), "x0")
+    _need(t0, torch.float64, (n,), "t0")
+    _need(xf, torch.float32, (d, n), "xf")
+    _need(cell, torch.int64, (n,), "cell")
+    _need(flags, torch.uint8, (n,), "flags")
+    _check(_lib.lcs_advect_points(frames.ref, _ptr(x0), _ptr(t0), n, float(T), float(dt),
+                                  _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_cg_tensor(seeds, xf, flags=None, C_out=None, stencil_flags=None, want_stencil=True,
+                  stream=None):
+    """Packed Cauchy-Green tensor [nq, Ns] (f64) and stencil flags [Ns] (u8)."""
+    torch = _torch()
+    d = seeds.dim
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    nq = d * (d + 1) // 2
+    dev = xf.device
+    if C_out is None:
+        C_out = torch.empty((nq, ns), dtype=torch.float64, device=dev)
+    if stencil_flags is None and want_stencil:
+        stencil_flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(flags, torch.uint8, (ns,), "flags")
+    _need(C_out, torch.float64, (nq, ns), "C")
+    _need(stencil_flags, torch.uint8, (ns,), "stencil_flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_cg_tensor(C.byref(sd), _ptr(xf), _ptr(flags), _ptr(C_out), _ptr(stencil_flags),
+                              _stream_handle(stream)))
+    return C_out, stencil_flags
+
+
+def lcs_ftle(dim: int, C_in, T: float, lambda_max=None, ftle=None, want_lambda=True, stream=None):
+    """(lambda_max [n], ftle [n]) in f64 from packed C [nq, n]."""
+    torch = _torch()
+    nq = dim * (dim + 1) // 2
+    n = int(C_in.shape[1])
+    dev = C_in.device
+    if lambda_max is None and want_lambda:
+        lambda_max = torch.empty(n, dtype=torch.float64, device=dev)
+    if ftle is None:
+        ftle = torch.empty(n, dtype=torch.float64, device=dev)
+    _need(C_in, torch.float64, (nq, n), "C")
+    _need(lambda_max, torch.float64, (n,), "lambda_max")
+    _need(ftle, torch.float64, (n,), "ftle")
+    _check(_lib.lcs_ftle(int(dim), n, _ptr(C_in), float(T), _ptr(lambda_max), _ptr(ftle),
+                         _stream_handle(stream)))
+    return lambda_max, ftle
+
+
+def lcs_cg_ftle(seeds, xf, T: float, flags=None, lambda_max=None, ftle=None, stencil_flags=None,
+                want_lambda=True, want_stencil=True, stream=None):
+    """Fused gradient -> C -> lambda_max -> FTLE without materialising C."""
+    torch = _torch()
+    d = seeds.dim
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    dev = xf.device
+    if lambda_max is None and want_lambda:
+        lambda_max = torch.empty(ns, dtype=torch.float64, device=dev)
+    if ftle is None:
+        ftle = torch.empty(ns, dtype=torch.float64, device=dev)
+    if stencil_flags is None and want_stencil:
+        stencil_flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(flags, torch.uint8, (ns,), "flags")
+    _need(lambda_max, torch.float64, (ns,), "lambda_max")
+    _need(ftle, torch.float64, (ns,), "ftle")
+    _need(stencil_flags, torch.uint8, (ns,), "stencil_flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_cg_ftle(C.byref(sd), _ptr(xf), _ptr(flags), float(T), _ptr(lambda_max),
+                            _ptr(ftle), _ptr(stencil_flags), _stream_handle(stream)))
+    return lambda_max, ftle, stencil_flags
+
+
+def lcs_sync_status(stream=None):
+    _check(_lib.lcs_sync_status(_stream_handle(stream)))

@@ -158,3 +158,15 @@ def test_threads_do_not_change_results(orc):
     idx = np.array([0, 5, 100, 560])
     c = orc.advect_seeds(vel, g, 0.0, 5.0, 0.05, idx=idx)
     assert np.array_equal(c[0], a[0][:, idx])
+
+
+def test_time_span_rule(orc):
+    # no extrapolation in time: a point whose [t0, t0+T] leaves the frame span
+    # is flagged TIME_OUT and left where it started
+    fs = inputs.uniform_frames(np.array([0.1, 0.0]), dim=2, n=5, t_first=1.0, dt_frame=2.0)
+    vel = orc.Velocity(fs)          # frames at t = 1 and t = 3
+    x0 = np.array([[0.2, 0.2, 0.2, 0.2], [0.5, 0.5, 0.5, 0.5]])
+    t0 = np.array([1.0, 0.5, 2.5, 3.0])
+    xf, _, flags = orc.advect_points(vel, x0, t0, 0.5, 0.1)
+    np.testing.assert_array_equal(flags, [0, 8, 0, 8])
+    np.testing.assert_allclose(xf[0], [0.25, 0.2, 0.25, 0.2], atol=1e-14)
