@@ -40,7 +40,33 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the oracle sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB, so that "
+                         "profiler byte counters can be scaled by a kernel of known traffic")
     return ap.parse_args()
+
+
+PROFILE = os.path.join(ROOT, "profiles", "advect_grid_kernel_3d_abc128_seeds256.md")
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the advection kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of
+    known size), or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("{") and "traffic_bytes_per_launch" in line:
+            rec = json.loads(line)
+            h = hashlib.sha1()
+            for f in rec["source_files"]:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest()[:16] == rec["source_sha1"]:
+                return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(fs, g, t0, T, dt, target_s):
@@ -80,6 +106,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr,
+              flush=True)
+        del src, dst
     W = WORKLOAD
     L = 2 * math.pi
     fs = inputs.abc_frames(n=W["grid"], n_frames=W["frames"], dt_frame=W["dt_frame"])
@@ -153,7 +189,8 @@ def main():
         "flagged_tracers": nflag,
         "roofline": {"kernel": "advect_grid_kernel<3>", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": profiled_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
                      "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
                      "units_per_launch": tracer_steps},
         "cpu_baseline": None,

@@ -1,0 +1,116 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/lcs.h declares, and rejects bad arguments with the
+documented status codes before anything is launched."""
+import ctypes as C
+
+import pytest
+
+from paper_2209_13775_amd import lcs
+
+
+def test_exports_every_declared_symbol():
+    names = lcs.declared_entry_points()
+    assert "lcs_advect" in names and "lcs_cg_tensor" in names and "lcs_ftle" in names
+    L = C.CDLL(lcs.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _vel(dim=2, n=(5, 4, 1), frames=3, t_first=0.0, dt_frame=1.0, periodic=0):
+    v = lcs.lcs_velocity_t()
+    v.dim = dim
+    v.n_frames = frames
+    for a in range(3):
+        v.n[a] = n[a]
+        v.origin[a] = 0.0
+        v.spacing[a] = 0.25
+    v.periodic_mask = periodic
+    v.t_first = t_first
+    v.dt_frame = dt_frame
+    for c in range(3):
+        v.u[c] = 0x1000 if c < dim else None   # never dereferenced: validation fails first
+    return v
+
+
+def _seeds(dim=2, n=(3, 3, 1), origin=(0.1, 0.1, 0.0), spacing=(0.2, 0.2, 1.0), periodic=0):
+    s = lcs.lcs_seed_grid_t()
+    s.dim = dim
+    s.periodic_mask = periodic
+    for a in range(3):
+        s.n[a] = n[a]
+        s.origin[a] = origin[a]
+        s.spacing[a] = spacing[a]
+    return s
+
+
+def _advect(v, s, t0, T, dt, xf=0x2000):
+    return lcs.lib().lcs_advect(C.byref(v) if v is not None else None,
+                                C.byref(s) if s is not None else None,
+                                t0, T, dt, xf, None, None, None)
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("null_vel", lcs.LCS_E_ARG),
+    ("null_seeds", lcs.LCS_E_ARG),
+    ("null_xf", lcs.LCS_E_ARG),
+    ("bad_dim", lcs.LCS_E_ARG),
+    ("one_frame", lcs.LCS_E_SHAPE),
+    ("one_node", lcs.LCS_E_SHAPE),
+    ("nonint_steps", lcs.LCS_E_STEP),
+    ("sign_mismatch", lcs.LCS_E_STEP),
+    ("zero_T", lcs.LCS_E_STEP),
+    ("time_range", lcs.LCS_E_TIME_RANGE),
+    ("seed_outside", lcs.LCS_E_SEED_DOMAIN),
+    ("periodic_seed_on_closed_axis", lcs.LCS_E_ARG),
+    ("reserved", lcs.LCS_E_ARG),
+])
+def test_advect_validation(case, expect):
+    v, s = _vel(), _seeds()
+    t0, T, dt, xf = 0.0, 1.0, 0.1, 0x2000
+    if case == "null_vel":
+        v = None
+    elif case == "null_seeds":
+        s = None
+    elif case == "null_xf":
+        xf = None
+    elif case == "bad_dim":
+        v.dim = 4
+    elif case == "one_frame":
+        v.n_frames = 1
+    elif case == "one_node":
+        v.n[1] = 1
+    elif case == "nonint_steps":
+        dt = 0.3
+    elif case == "sign_mismatch":
+        dt = -0.1
+    elif case == "zero_T":
+        T = 0.0
+    elif case == "time_range":
+        T = 2.5            # frames span [0, 2]
+    elif case == "seed_outside":
+        s.origin[0] = 0.7  # 0.7 + 2*0.2 = 1.1 > 4*0.25
+    elif case == "periodic_seed_on_closed_axis":
+        s.periodic_mask = 1
+    elif case == "reserved":
+        v.reserved = 7
+    st = _advect(v, s, t0, T, dt, xf)
+    assert st == expect, lcs.lcs_last_error()
+    assert lcs.lcs_last_error() != ""
+
+
+def test_other_entry_points_validate():
+    L = lcs.lib()
+    s = _seeds()
+    assert L.lcs_cg_tensor(C.byref(s), None, None, 0x10, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_cg_tensor(C.byref(s), 0x10, None, None, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_ftle(4, 10, 0x10, 1.0, 0x20, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_ftle(3, 0, 0x10, 1.0, 0x20, None, None) == lcs.LCS_E_SHAPE
+    assert L.lcs_ftle(3, 10, 0x10, 0.0, 0x20, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_ftle(3, 10, 0x10, 1.0, None, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_cg_ftle(C.byref(s), 0x10, None, 1.0, None, None, None, None) == lcs.LCS_E_ARG
+    v = _vel()
+    assert L.lcs_advect_points(C.byref(v), 0x10, 0x20, 0, 1.0, 0.1, 0x30, None, None, None) == \
+        lcs.LCS_E_SHAPE
+    assert L.lcs_advect_points(C.byref(v), None, 0x20, 5, 1.0, 0.1, 0x30, None, None, None) == \
+        lcs.LCS_E_ARG
+    assert lcs.lcs_version() >= 100
