@@ -113,6 +113,14 @@ typedef struct {
     double T;
 } lcs_window_t;
 
+/* Opaque plan: device state the library owns for batched launches (a work
+ * counter, a capture stream and the captured HIP graph).  One plan per device
+ * and per host thread at a time; calls that share a plan must not overlap. */
+typedef struct lcs_plan *lcs_plan_t;
+
+/* Maximum number of windows of one lcs_advect_batched call. */
+#define LCS_MAX_WINDOWS 192
+
 /*
  * lcs_advect -- flow map F_{t0}^{t0+T} of a structured seed grid (Eq. 2;
  * Sec. 2 Seed and Flow Map filters; Sec. 3.1 RK4).
@@ -200,6 +208,44 @@ lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T,
 lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
                        double T, double *lambda_max, double *ftle, uint8_t *stencil_flags,
                        void *stream);
+
+/*
+ * lcs_advect_batched -- the flow map of one seed grid for a time series of
+ * start times (Sec. 1: the computation may be repeated for a time series of
+ * seed grids at different t0; Sec. 4: sampling is dense in space, not in
+ * time), all windows in ONE persistent launch replayed from a HIP graph.
+ *
+ * Window w integrates N_w = T_w/dt RK4 steps from windows[w].t0 (same
+ * integrator, same outputs as lcs_advect, bit-identical to calling lcs_advect
+ * per window).  Work items are (window, seed tile) pairs taken longest window
+ * first from a device counter by persistent workgroups.  The (counter reset,
+ * kernel) pair is captured once into a graph on a plan-owned stream and
+ * replayed on `stream`; a call whose arguments differ from the captured ones
+ * re-captures.
+ *
+ * plan      from lcs_plan_create (must be the current device's).
+ * windows   [host] n_windows entries, 1 <= n_windows <= LCS_MAX_WINDOWS; every
+ *           window inside the frame span; sign(T_w) == sign(dt); T_w/dt integral.
+ * xf        [device] FP32, n_windows x dim x Ns (window-major, caller's order).
+ * cell      [device] int64, n_windows x Ns, or NULL.
+ * flags     [device] uint8, n_windows x Ns, or NULL.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_TIME_RANGE, LCS_E_SEED_DOMAIN,
+ *         LCS_E_STEP, LCS_E_HIP.
+ */
+lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
+                              const lcs_seed_grid_t *seeds, const lcs_window_t *windows,
+                              int32_t n_windows, double dt, float *xf, int64_t *cell,
+                              uint8_t *flags, void *stream);
+
+/* lcs_plan_create / lcs_plan_destroy -- allocate / free a plan on the current
+ * device (hipMalloc of a 4-byte counter, one non-blocking stream).
+ * lcs_plan_destroy waits for the plan's stream and accepts NULL. */
+lcs_status lcs_plan_create(lcs_plan_t *plan);
+lcs_status lcs_plan_destroy(lcs_plan_t plan);
+
+/* lcs_plan_stats -- number of graph launches and graph captures so far
+ * (either pointer may be NULL). */
+lcs_status lcs_plan_stats(lcs_plan_t plan, int64_t *graph_launches, int64_t *graph_captures);
 
 /* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
 lcs_status lcs_sync_status(void *stream);

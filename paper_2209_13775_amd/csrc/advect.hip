@@ -304,13 +304,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
+// Seed of this lane for Morton tile index m, or -1 if the tile or the lane
+// falls outside the seed grid.  Morton decode with per-axis bit counts (an
+// axis that runs out of bits drops out of the interleave); within the tile,
+// waves and lanes are laid out as wg x wt seeds.
 template <int D>
-__global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
+__device__ __forceinline__ long long seed_of(const SeedTiling &g, int m, int t, int *sc)
 {
-    const SeedTiling &g = A.g;
-    const int m = xcd_remap((int)blockIdx.x, g.n_blocks);
-    // Morton decode with per-axis bit counts (an axis that runs out of bits
-    // drops out of the interleave)
     int tc[3] = {0, 0, 0};
     int pos = 0;
     for (int l = 0; l < g.max_bits; ++l)
@@ -319,9 +319,7 @@ __global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
             if (l < g.bits[a]) tc[a] |= ((m >> (pos++)) & 1) << l;
 #pragma unroll
     for (int a = 0; a < D; ++a)
-        if (tc[a] >= g.ntiles[a]) return;
-
-    const int t = threadIdx.x;
+        if (tc[a] >= g.ntiles[a]) return -1;
     const int w = t / kWave, l = t % kWave;
     int wc[3], lc[3];
     wc[0] = w % g.wg[0];
@@ -330,14 +328,24 @@ __global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
     lc[0] = l % g.wt[0];
     lc[1] = (l / g.wt[0]) % g.wt[1];
     lc[2] = l / (g.wt[0] * g.wt[1]);
-    int sc[3] = {0, 0, 0};
+    sc[0] = sc[1] = sc[2] = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         sc[a] = (tc[a] * g.wg[a] + wc[a]) * g.wt[a] + lc[a];
-        if (sc[a] >= g.sn[a]) return;
+        if (sc[a] >= g.sn[a]) return -1;
     }
-    const long long s = (long long)sc[0] + (long long)g.sn[0] * ((long long)sc[1] +
-                        (long long)g.sn[1] * (long long)sc[2]);
+    return (long long)sc[0] + (long long)g.sn[0] * ((long long)sc[1] +
+           (long long)g.sn[1] * (long long)sc[2]);
+}
+
+// Advect the seed with integer coordinates sc from t0 and write its outputs at
+// linear index s of the given output arrays.
+template <int D>
+__device__ __forceinline__ void advect_seed(const VelDev &v, const SeedTiling &g, const int *sc,
+                                            long long s, double t0, double dt, int nsteps,
+                                            long long ns, float *xf, long long *cell,
+                                            uint8_t *flags)
+{
     // seed position, carried exactly (to FP64 rounding) as a two-float
     float xh[3], xl[3], x[3];
 #pragma unroll
@@ -346,15 +354,52 @@ __global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
         xh[a] = (float)x0;
         xl[a] = (float)(x0 - (double)xh[a]);
     }
-
-    const uint32_t fl = advect_tracer<D>(A.v, xh, xl, A.t0, A.dt, A.nsteps);
+    const uint32_t fl = advect_tracer<D>(v, xh, xl, t0, dt, nsteps);
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = xh[a] + xl[a];
-
 #pragma unroll
-    for (int a = 0; a < D; ++a) A.xf[a * A.ns + s] = x[a];
-    if (A.cell) A.cell[s] = cell_index<D>(A.v, x);
-    if (A.flags) A.flags[s] = (uint8_t)fl;
+    for (int a = 0; a < D; ++a) xf[a * ns + s] = x[a];
+    if (cell) cell[s] = cell_index<D>(v, x);
+    if (flags) flags[s] = (uint8_t)fl;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
+{
+    const int m = xcd_remap((int)blockIdx.x, A.g.n_blocks);
+    int sc[3];
+    const long long s = seed_of<D>(A.g, m, threadIdx.x, sc);
+    if (s < 0) return;
+    advect_seed<D>(A.v, A.g, sc, s, A.t0, A.dt, A.nsteps, A.ns, A.xf, A.cell, A.flags);
+}
+
+__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+
+// Persistent batched advection: every block repeatedly claims the next
+// (window, tile) item; items run longest window first and, within a window,
+// along the Morton curve.  All lanes of a block leave the loop together once
+// the counter passes the item count.
+template <int D>
+__global__ __launch_bounds__(256) void advect_batched_kernel(BatchArgs A)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(A.counter, 1);
+        __syncthreads();
+        const int q = s_item;
+        __syncthreads();
+        if (q >= A.total_items) break;
+        const int k = q / A.g.n_blocks;
+        const int m = q - k * A.g.n_blocks;
+        const WindowDev w = A.win[k];
+        int sc[3];
+        const long long s = seed_of<D>(A.g, m, threadIdx.x, sc);
+        if (s >= 0) {
+            const long long off = (long long)w.out_index * A.ns;
+            advect_seed<D>(A.v, A.g, sc, s, w.t0, A.dt, w.nsteps, A.ns, A.xf + D * off,
+                           A.cell ? A.cell + off : nullptr, A.flags ? A.flags + off : nullptr);
+        }
+    }
 }
 
 template <int D>
@@ -392,6 +437,31 @@ hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s)
     else
         hipLaunchKernelGGL(advect_grid_kernel<3>, grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(int *counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_batched(int dim, const BatchArgs &a, int grid_blocks, hipStream_t s)
+{
+    dim3 grid((unsigned)grid_blocks), block(256);
+    if (dim == 2)
+        hipLaunchKernelGGL(advect_batched_kernel<2>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(advect_batched_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+int batched_blocks_per_cu(int dim)
+{
+    int nb = 0;
+    hipError_t e = (dim == 2)
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_batched_kernel<2>, 256, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, advect_batched_kernel<3>, 256, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_advect_points(int dim, const AdvectArgs &a, hipStream_t s)

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <new>
+
 #include "lcs_internal.h"
 
 namespace {
@@ -97,6 +99,27 @@ lcs_status check_steps(double T, double dt, int *nsteps)
     return LCS_OK;
 }
 
+// Seeds must lie inside the closed domain on every non-periodic velocity axis
+// (to 1e-9 of the extent); a periodic seed axis needs a periodic velocity axis.
+lcs_status check_seed_domain(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds)
+{
+    for (int a = 0; a < vel->dim; ++a) {
+        const bool vper = (vel->periodic_mask >> a) & 1u;
+        const bool sper = (seeds->periodic_mask >> a) & 1u;
+        if (sper && !vper) return fail(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
+        if (vper) continue;
+        const double lo = vel->origin[a];
+        const double hi = vel->origin[a] + (double)(vel->n[a] - 1) * vel->spacing[a];
+        const double s0 = seeds->origin[a];
+        const double s1 = seeds->origin[a] + (double)(seeds->n[a] - 1) * seeds->spacing[a];
+        const double tol = 1e-9 * (hi - lo);
+        if (s0 < lo - tol || s1 > hi + tol)
+            return fail(LCS_E_SEED_DOMAIN, "seeds on axis %d span [%g, %g] outside [%g, %g]", a,
+                        s0, s1, lo, hi);
+    }
+    return LCS_OK;
+}
+
 lcs::VelDev make_vel(const lcs_velocity_t *v)
 {
     lcs::VelDev d;
@@ -158,7 +181,75 @@ lcs::SeedTiling make_tiling(const lcs_seed_grid_t *g)
 
 }  // namespace
 
+// Plan: device state owned by the library for batched launches -- the work
+// counter, a capture stream (default priority) and the instantiated graph of
+// (counter reset + persistent kernel) together with the key it was captured
+// for.  Created by lcs_plan_create, freed by lcs_plan_destroy.
+struct lcs_plan {
+    int device = -1;
+    int *d_counter = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool have_graph = false;
+    lcs::BatchArgs key;       // arguments the graph was captured with
+    int key_dim = 0;
+    int key_grid = 0;
+    long long launches = 0;
+    long long captures = 0;
+};
+
+namespace {
+
+void drop_graph(lcs_plan *p)
+{
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->have_graph = false;
+}
+
+}  // namespace
+
 extern "C" {
+
+lcs_status lcs_plan_create(lcs_plan_t *plan)
+{
+    if (!plan) return fail(LCS_E_ARG, "plan pointer is NULL");
+    *plan = nullptr;
+    lcs_plan *p = new (std::nothrow) lcs_plan();
+    if (!p) return fail(LCS_E_ARG, "out of host memory");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_counter, sizeof(int));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (p->d_counter) (void)hipFree(p->d_counter);
+        delete p;
+        return hip_fail(e, "lcs_plan_create");
+    }
+    *plan = p;
+    return ok();
+}
+
+lcs_status lcs_plan_destroy(lcs_plan_t plan)
+{
+    if (!plan) return ok();
+    (void)hipStreamSynchronize(plan->cap_stream);
+    drop_graph(plan);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    if (plan->d_counter) (void)hipFree(plan->d_counter);
+    delete plan;
+    return ok();
+}
+
+lcs_status lcs_plan_stats(lcs_plan_t plan, int64_t *graph_launches, int64_t *graph_captures)
+{
+    if (!plan) return fail(LCS_E_ARG, "plan is NULL");
+    if (graph_launches) *graph_launches = plan->launches;
+    if (graph_captures) *graph_captures = plan->captures;
+    return ok();
+}
 
 const char *lcs_last_error(void) { return g_err; }
 
@@ -187,20 +278,7 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, d
     if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
         return fail(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
                     vel->t_first, t_last);
-    for (int a = 0; a < vel->dim; ++a) {
-        const bool vper = (vel->periodic_mask >> a) & 1u;
-        const bool sper = (seeds->periodic_mask >> a) & 1u;
-        if (sper && !vper) return fail(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
-        if (vper) continue;
-        const double lo = vel->origin[a];
-        const double hi = vel->origin[a] + (double)(vel->n[a] - 1) * vel->spacing[a];
-        const double s0 = seeds->origin[a];
-        const double s1 = seeds->origin[a] + (double)(seeds->n[a] - 1) * seeds->spacing[a];
-        const double tol = 1e-9 * (hi - lo);
-        if (s0 < lo - tol || s1 > hi + tol)
-            return fail(LCS_E_SEED_DOMAIN, "seeds on axis %d span [%g, %g] outside [%g, %g]", a,
-                        s0, s1, lo, hi);
-    }
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
     lcs::AdvectArgs A;
     memset(&A, 0, sizeof(A));
     A.v = make_vel(vel);
@@ -214,6 +292,102 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, d
     A.flags = flags;
     hipError_t e = lcs::launch_advect_grid(vel->dim, A, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "advect launch");
+    return ok();
+}
+
+lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
+                              const lcs_seed_grid_t *seeds, const lcs_window_t *windows,
+                              int32_t n_windows, double dt, float *xf, int64_t *cell,
+                              uint8_t *flags, void *stream)
+{
+    lcs_status st;
+    if (!plan) return fail(LCS_E_ARG, "plan is NULL (create one with lcs_plan_create)");
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf || !windows) return fail(LCS_E_ARG, "xf and windows must not be NULL");
+    if (n_windows < 1 || n_windows > lcs::kMaxWindows)
+        return fail(LCS_E_SHAPE, "n_windows must be in [1, %d]", lcs::kMaxWindows);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    lcs::BatchArgs A;
+    memset(&A, 0, sizeof(A));
+    for (int w = 0; w < n_windows; ++w) {
+        int nsteps = 0;
+        if ((st = check_steps(windows[w].T, dt, &nsteps)) != LCS_OK) return st;
+        const double t0 = windows[w].t0, t1 = t0 + windows[w].T;
+        if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first &&
+              t1 <= t_last))
+            return fail(LCS_E_TIME_RANGE, "window %d [%g, %g] leaves the frame span [%g, %g]", w,
+                        t0, t1, vel->t_first, t_last);
+        A.win[w].t0 = t0;
+        A.win[w].nsteps = nsteps;
+        A.win[w].out_index = w;
+    }
+    // longest window first (stable, so equal lengths keep the caller's order)
+    for (int i = 1; i < n_windows; ++i) {
+        lcs::WindowDev x = A.win[i];
+        int j = i - 1;
+        while (j >= 0 && A.win[j].nsteps < x.nsteps) {
+            A.win[j + 1] = A.win[j];
+            --j;
+        }
+        A.win[j + 1] = x;
+    }
+    A.v = make_vel(vel);
+    A.g = make_tiling(seeds);
+    A.dt = dt;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.n_windows = n_windows;
+    const long long items = (long long)n_windows * A.g.n_blocks;
+    if (items > 2147483647LL) return fail(LCS_E_SHAPE, "too many (window, tile) items");
+    A.total_items = (int)items;
+    A.counter = plan->d_counter;
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != plan->device) return fail(LCS_E_ARG, "plan was created on device %d, current is %d",
+                                         plan->device, dev);
+    int n_cu = 0;
+    e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    const int grid = n_cu * lcs::batched_blocks_per_cu(vel->dim);
+
+    const bool same = plan->have_graph && plan->key_dim == vel->dim && plan->key_grid == grid &&
+                      memcmp(&plan->key, &A, sizeof(A)) == 0;
+    if (!same) {
+        drop_graph(plan);
+        // capture (counter reset, persistent kernel) on the plan's own stream
+        e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t e1 = lcs::launch_reset_counter(plan->d_counter, plan->cap_stream);
+        hipError_t e2 = lcs::launch_advect_batched(vel->dim, A, grid, plan->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(plan->cap_stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        plan->graph = g;
+        plan->exec = x;
+        plan->have_graph = true;
+        plan->key = A;
+        plan->key_dim = vel->dim;
+        plan->key_grid = grid;
+        plan->captures++;
+    }
+    e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    plan->launches++;
     return ok();
 }
 

@@ -87,7 +87,36 @@ struct FtleArgs {
     double inv_two_T;
 };
 
+// Batched windows: (window, tile) work items, windows sorted by step count
+// (longest first) and claimed through an atomic counter by persistent blocks.
+constexpr int kMaxWindows = LCS_MAX_WINDOWS;
+
+struct WindowDev {
+    double t0;
+    int nsteps;
+    int out_index;            // position of the window in the caller's order
+};
+
+struct BatchArgs {
+    VelDev v;
+    SeedTiling g;
+    double dt;
+    long long ns;
+    int n_windows;
+    int total_items;          // n_windows * g.n_blocks
+    int *counter;             // work counter (device)
+    float *xf;
+    long long *cell;
+    uint8_t *flags;
+    WindowDev win[kMaxWindows];
+};
+
+static_assert(sizeof(BatchArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
+
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
+hipError_t launch_reset_counter(int *counter, hipStream_t s);
+hipError_t launch_advect_batched(int dim, const BatchArgs &a, int grid_blocks, hipStream_t s);
+int batched_blocks_per_cu(int dim);
 hipError_t launch_advect_points(int dim, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_cg(const CgArgs &a, bool fused, hipStream_t s);
 hipError_t launch_ftle(int dim, const FtleArgs &a, hipStream_t s);

@@ -59,10 +59,15 @@ class lcs_window_t(C.Structure):
     _fields_ = [("t0", C.c_double), ("T", C.c_double)]
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"HIP library {LIB_PATH} is not built (run __graft_entry__.build())")
-    L = C.CDLL(LIB_PATH)
+def _load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built (run __graft_entry__.build())")
+    # torch carries its own HIP runtime (same soname as ROCm's).  Loading torch
+    # first makes the library bind to that one runtime; loading the library
+    # first would put a second HIP/HSA runtime into the process once torch is
+    # imported, and one of them then finds no device.
+    import torch  # noqa: F401
+    L = C.CDLL(path)
     P, D, I64, I32 = C.c_void_p, C.c_double, C.c_int64, C.c_int32
     sig = {
         "lcs_advect": [P, P, D, D, D, P, P, P, P],
@@ -71,6 +76,10 @@ def _load():
         "lcs_ftle": [I32, I64, P, D, P, P, P],
         "lcs_cg_ftle": [P, P, P, D, P, P, P, P],
         "lcs_sync_status": [P],
+        "lcs_advect_batched": [P, P, P, P, I32, D, P, P, P, P],
+        "lcs_plan_create": [P],
+        "lcs_plan_destroy": [P],
+        "lcs_plan_stats": [P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -318,3 +327,58 @@ def lcs_cg_ftle(seeds, xf, T: float, flags=None, lambda_max=None, ftle=None, ste
 
 def lcs_sync_status(stream=None):
     _check(_lib.lcs_sync_status(_stream_handle(stream)))
+
+
+LCS_MAX_WINDOWS = 192
+
+
+class Plan:
+    """Owns an ``lcs_plan_t`` (work counter, capture stream, cached graph)."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(_lib.lcs_plan_create(C.byref(h)))
+        self.handle = h
+
+    def stats(self):
+        a, b = C.c_int64(), C.c_int64()
+        _check(_lib.lcs_plan_stats(self.handle, C.byref(a), C.byref(b)))
+        return {"graph_launches": a.value, "graph_captures": b.value}
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.lcs_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lcs_advect_batched(plan: Plan, frames: DeviceFrames, seeds, windows, dt: float,
+                       xf=None, cell=None, flags=None, want_cell=True, want_flags=True,
+                       stream=None):
+    """All windows ((t0, T) pairs) in one graph-replayed persistent launch.
+    Returns xf [nw, dim, Ns] f32, cell [nw, Ns] i64, flags [nw, Ns] u8."""
+    torch = _torch()
+    win = np.ascontiguousarray(np.asarray(windows, dtype=np.float64).reshape(-1, 2))
+    nw = int(win.shape[0])
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((nw, d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty((nw, ns), dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty((nw, ns), dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (nw, d, ns), "xf")
+    _need(cell, torch.int64, (nw, ns), "cell")
+    _need(flags, torch.uint8, (nw, ns), "flags")
+    arr = (lcs_window_t * nw)(*[lcs_window_t(float(a), float(b)) for a, b in win])
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_batched(plan.handle, frames.ref, C.byref(sd), arr, nw, float(dt),
+                                   _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags

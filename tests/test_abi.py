@@ -114,3 +114,24 @@ def test_other_entry_points_validate():
     assert L.lcs_advect_points(C.byref(v), None, 0x20, 5, 1.0, 0.1, 0x30, None, None, None) == \
         lcs.LCS_E_ARG
     assert lcs.lcs_version() >= 100
+
+
+def test_batched_validation():
+    L = lcs.lib()
+    v, s = _vel(), _seeds()
+    win = (lcs.lcs_window_t * 2)(lcs.lcs_window_t(0.0, 1.0), lcs.lcs_window_t(0.5, 1.0))
+    fake_plan = C.c_void_p(0x1)      # never dereferenced: validation fails first
+    assert L.lcs_advect_batched(None, C.byref(v), C.byref(s), win, 2, 0.1, 0x10, None, None,
+                                None) == lcs.LCS_E_ARG
+    assert L.lcs_advect_batched(fake_plan, C.byref(v), C.byref(s), win, 0, 0.1, 0x10, None, None,
+                                None) == lcs.LCS_E_SHAPE
+    assert L.lcs_advect_batched(fake_plan, C.byref(v), C.byref(s), win, 193, 0.1, 0x10, None,
+                                None, None) == lcs.LCS_E_SHAPE
+    bad = (lcs.lcs_window_t * 2)(lcs.lcs_window_t(0.0, 1.0), lcs.lcs_window_t(1.5, 1.0))
+    assert L.lcs_advect_batched(fake_plan, C.byref(v), C.byref(s), bad, 2, 0.1, 0x10, None, None,
+                                None) == lcs.LCS_E_TIME_RANGE
+    bad2 = (lcs.lcs_window_t * 2)(lcs.lcs_window_t(0.0, 1.0), lcs.lcs_window_t(0.5, 0.35))
+    assert L.lcs_advect_batched(fake_plan, C.byref(v), C.byref(s), bad2, 2, 0.1, 0x10, None,
+                                None, None) == lcs.LCS_E_STEP
+    assert L.lcs_plan_create(None) == lcs.LCS_E_ARG
+    assert L.lcs_plan_destroy(None) == lcs.LCS_OK
