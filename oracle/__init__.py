@@ -39,7 +39,7 @@ def build(force: bool = True) -> str:
 class _Vel(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_frames", C.c_int32), ("n", C.c_int64 * 3),
                 ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
-                ("periodic_mask", C.c_uint32), ("reserved", C.c_uint32),
+                ("periodic_mask", C.c_uint32), ("frames_f32", C.c_uint32),
                 ("t_first", C.c_double), ("dt_frame", C.c_double),
                 ("u", C.c_void_p * 3)]
 
@@ -94,9 +94,13 @@ def default_threads() -> int:
 class Velocity:
     """Holds FP64 copies of the frames and the descriptor the C code reads."""
 
-    def __init__(self, fs):
+    def __init__(self, fs, keep_f32: bool = False):
+        """keep_f32: read FP32 frames in place (each value widened to FP64 when
+        used) instead of making an FP64 copy -- for very large frame sets."""
         self.dim = fs.dim
-        self._u = [np.ascontiguousarray(c, dtype=np.float64) for c in fs.u]
+        f32 = keep_f32 and all(np.asarray(c).dtype == np.float32 for c in fs.u)
+        dt = np.float32 if f32 else np.float64
+        self._u = [np.ascontiguousarray(c, dtype=dt) for c in fs.u]
         s = _Vel()
         s.dim = fs.dim
         s.n_frames = fs.n_frames
@@ -105,6 +109,7 @@ class Velocity:
             s.origin[a] = float(fs.origin[a])
             s.spacing[a] = float(fs.spacing[a])
         s.periodic_mask = int(fs.periodic_mask)
+        s.frames_f32 = 1 if f32 else 0
         s.t_first = float(fs.t_first)
         s.dt_frame = float(fs.dt_frame)
         for c in range(3):

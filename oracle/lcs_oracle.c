@@ -47,7 +47,8 @@
 /* Velocity frames, structure of arrays: component c of node (i,j,k) in frame f
  * is u[c][f*n0*n1*n2 + i + n0*(j + n1*k)].  Node i of axis a is at
  * origin[a] + i*spacing[a].  A periodic axis a has period n[a]*spacing[a].
- * Frame f holds the field at t_first + f*dt_frame. */
+ * Frame f holds the field at t_first + f*dt_frame.  Frames stored in FP32
+ * are read value by value and widened to FP64 (exact); all arithmetic is FP64. */
 typedef struct {
     int32_t dim;
     int32_t n_frames;
@@ -55,10 +56,10 @@ typedef struct {
     double origin[3];
     double spacing[3];
     uint32_t periodic_mask;
-    uint32_t reserved;
+    uint32_t frames_f32;      /* 1: u[c] point to float arrays (widened on read) */
     double t_first;
     double dt_frame;
-    const double *u[3];
+    const void *u[3];         /* double (or float if frames_f32) arrays */
 } orc_velocity;
 
 /* Structured seed grid: seed (i,j,k) at origin + (i,j,k)*spacing.  A periodic
@@ -153,7 +154,8 @@ static double node_value(const orc_velocity *v, int c, int64_t f, const int64_t 
 {
     int64_t per_frame = v->n[0] * v->n[1] * v->n[2];
     int64_t lin = idx[0] + v->n[0] * (idx[1] + v->n[1] * idx[2]);
-    return v->u[c][f * per_frame + lin];
+    if (v->frames_f32) return (double)((const float *)v->u[c])[f * per_frame + lin];
+    return ((const double *)v->u[c])[f * per_frame + lin];
 }
 
 /* Multilinear interpolation of component c in frame f: the sum over the 2^dim

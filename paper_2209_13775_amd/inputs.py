@@ -308,69 +308,86 @@ def random_frames(dim, n, n_frames, seed, periodic=None, origin=None, spacing=No
 
 
 def random_fourier_frames(n=256, n_frames=65, dt_frame=0.125, kmax=32, tau=2.0, seed=1,
-                          t_first=0.0, dtype=np.float32, device=None) -> FrameSet:
-    """Divergence-free random-Fourier velocity field on [0, 2pi)^3.
+                          t_first=0.0, device=None) -> FrameSet:
+    """Divergence-free random-Fourier velocity field on [0, 2pi)^3, FP32 frames.
 
-    Recipe: integer wavevectors with 1 <= |k| <= kmax; each mode amplitude is
-    P(k) xi_k(t) s(|k|) with the solenoidal projector P = I - k k^T/|k|^2,
-    s^2 proportional to E(k)/(4 pi k^2), E(k) ~ k^(-5/3); xi_k is a complex
-    Gaussian Ornstein-Uhlenbeck process with correlation exp(-|dt|/tau),
-    stationary at t = 0 (random phases).  Transformed to real space with an
-    inverse real FFT, then scaled by one global constant so that the RMS speed
-    over all frames is 1.  Drawn from numpy.random.default_rng(seed).
+    Recipe: integer wavevectors with 1 <= |k| <= kmax (half spectrum of a real
+    FFT); each mode amplitude is P(k) xi_k(t) s(|k|) with the solenoidal
+    projector P = I - k k^T/|k|^2 and s^2 = E(k)/(4 pi k^2), E(k) ~ k^(-5/3);
+    xi_k is a complex Gaussian Ornstein-Uhlenbeck process with correlation
+    exp(-|dt|/tau), stationary at t = 0 (random phases).  An inverse real FFT
+    gives the nodes; one global constant then makes the RMS speed over all
+    frames 1.  The draws come from numpy.random.default_rng(seed), mode by mode
+    in a fixed order, so every device produces the same field.
 
-    ``device`` (a torch device) moves the FFTs to the GPU for large n; the
-    random draws always come from NumPy so every device sees the same field.
+    ``device`` (a torch device) runs the inverse FFTs there and returns the
+    frames as device tensors in ``u`` (large grids); otherwise NumPy arrays.
     """
     rng = np.random.default_rng(seed)
-    kx = np.fft.fftfreq(n, d=1.0 / n)
-    kz_r = np.fft.rfftfreq(n, d=1.0 / n)
-    # spectral array layout (kz, ky, kx_r) matches irfftn over axes (z, y, x) with x last
-    KZ = kx[:, None, None]
-    KY = kx[None, :, None]
-    KX = kz_r[None, None, :]
+    kk = np.fft.fftfreq(n, d=1.0 / n)
+    kr = np.fft.rfftfreq(n, d=1.0 / n)
+    KZ, KY, KX = np.meshgrid(kk, kk, kr, indexing="ij")
     K2 = KX * KX + KY * KY + KZ * KZ
-    Kmag = np.sqrt(K2)
-    mask = (Kmag >= 1.0) & (Kmag <= kmax)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        amp = np.where(mask, np.sqrt(Kmag ** (-5.0 / 3.0) / (4.0 * math.pi * np.maximum(K2, 1.0))), 0.0)
-    shape = K2.shape
+    mask = (K2 >= 1.0) & (K2 <= kmax * kmax)
+    pos = np.flatnonzero(mask.ravel())
+    kx, ky, kz = KX.ravel()[pos], KY.ravel()[pos], KZ.ravel()[pos]
+    kmag = np.sqrt(K2.ravel()[pos])
+    amp = np.sqrt(kmag ** (-5.0 / 3.0) / (4.0 * math.pi * kmag * kmag))
+    khat = np.stack([kx, ky, kz]) / kmag
+    m = pos.size
     rho = math.exp(-dt_frame / tau)
     innov = math.sqrt(1.0 - rho * rho)
 
     def draw():
-        return (rng.standard_normal((3,) + shape) + 1j * rng.standard_normal((3,) + shape)) / math.sqrt(2.0)
+        return (rng.standard_normal((3, m)) + 1j * rng.standard_normal((3, m))) / math.sqrt(2.0)
 
-    xi = draw()
-    Ks = np.stack([np.broadcast_to(KX, shape), np.broadcast_to(KY, shape), np.broadcast_to(KZ, shape)])
-    with np.errstate(divide="ignore", invalid="ignore"):
-        Khat = np.where(mask[None], Ks / np.where(Kmag > 0, Kmag, 1.0)[None], 0.0)
-    comps = [np.empty((n_frames, n, n, n), dtype=dtype) for _ in range(3)]
-    sumsq = 0.0
+    spec_shape = (n, n, n // 2 + 1)
     torch = None
     if device is not None:
-        import torch  # noqa: F811  (plumbing only: FFT on the GPU)
+        import torch  # noqa: F811  (plumbing: FFTs and storage on the GPU)
+        pos_t = torch.from_numpy(pos).to(device)
+    xi = draw()
+    comps = []
+    sumsq = 0.0
+    if torch is not None:
+        u_dev = [torch.empty((n_frames, n, n, n), dtype=torch.float32, device=device)
+                 for _ in range(3)]
     for f in range(n_frames):
         if f > 0:
             xi = rho * xi + innov * draw()
         a = xi * amp[None]
-        # solenoidal projection: a <- a - khat (khat . a)
-        kd = (Khat * a).sum(axis=0)
-        a = a - Khat * kd[None]
+        a = a - khat * (khat * a).sum(axis=0)[None]          # solenoidal projection
+        frame = []
         for c in range(3):
             if torch is None:
-                real = np.fft.irfftn(a[c], s=(n, n, n), axes=(0, 1, 2)) * (n ** 3)
+                spec = np.zeros(np.prod(spec_shape), dtype=np.complex128)
+                spec[pos] = a[c]
+                real = np.fft.irfftn(spec.reshape(spec_shape), s=(n, n, n), axes=(0, 1, 2))
+                real = (real * n ** 3).astype(np.float32)
+                sumsq += float(np.sum(real.astype(np.float64) ** 2))
             else:
-                tt = torch.from_numpy(a[c].astype(np.complex64)).to(device)
-                real = (torch.fft.irfftn(tt, s=(n, n, n), dim=(0, 1, 2)) * (n ** 3)).cpu().numpy()
-            comps[c][f] = real
-            sumsq += float(np.sum(real.astype(np.float64) ** 2))
-    rms = math.sqrt(sumsq / (n_frames * n ** 3))
-    for c in range(3):
-        comps[c] /= dtype(rms) if dtype is not np.float64 else rms
+                spec = torch.zeros(int(np.prod(spec_shape)), dtype=torch.complex128, device=device)
+                spec[pos_t] = torch.from_numpy(a[c]).to(device)
+                real = torch.fft.irfftn(spec.reshape(spec_shape), s=(n, n, n), dim=(0, 1, 2))
+                u_dev[c][f] = (real * float(n ** 3)).to(torch.float32)
+                sumsq += float((u_dev[c][f].double() ** 2).sum().item())
+                del spec, real
+                real = None
+            frame.append(real)
+        comps.append(frame)
+    rms = math.sqrt(sumsq / (n_frames * n ** 3 * 1.0))
+    scale = 1.0 / rms
+    if torch is None:
+        u = [np.stack([comps[f][c] for f in range(n_frames)]) for c in range(3)]
+        for c in range(3):
+            u[c] *= np.float32(scale)
+    else:
+        u = u_dev
+        for c in range(3):
+            u[c].mul_(scale)
     h = 2.0 * math.pi / n
     return FrameSet(3, (n, n, n), (0.0, 0.0, 0.0), (h, h, h), (True, True, True),
-                    float(t_first), float(dt_frame), comps)
+                    float(t_first), float(dt_frame), u)
 
 
 # ---------------------------------------------------------------------------
