@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the oracle sample")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched-window and random-Fourier workloads")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -92,6 +94,97 @@ def cpu_baseline(fs, g, t0, T, dt, target_s):
             "kind": "oracle",
             "sample": f"{m} seeds drawn from the 256^3 grid (seed 0), full T=8 ({nsteps} RK4 steps), "
                       f"FP64, OpenMP, {el:.1f} s"}
+
+
+def bench_batched(torch, lcs, inputs, reps=3):
+    """Double gyre on 1025x513 nodes x 101 FP32 frames (t = 0.25 f); 64 windows
+    (t0 ~ U[0,10], T from {5, 7.5, 10, 12.5, 15}, default_rng(0)) of a
+    1024x512 seed grid, dt = 0.05, all in one graph-replayed persistent launch."""
+    fs = inputs.double_gyre_frames(nx=1025, ny=513, n_frames=101, dt_frame=0.25,
+                                   dtype=np.float32)
+    g = inputs.linspace_seeds(2, (1024, 512), (0.0, 0.0), (2.0, 1.0))
+    windows = inputs.t0_windows(64, seed=0)
+    dt = 0.05
+    frames = lcs.DeviceFrames(fs)
+    plan = lcs.Plan()
+    nw, ns = len(windows), g.count
+    xf = torch.empty((nw, 2, ns), dtype=torch.float32, device="cuda")
+    cell = torch.empty((nw, ns), dtype=torch.int64, device="cuda")
+    flags = torch.empty((nw, ns), dtype=torch.uint8, device="cuda")
+    lcs.lcs_advect_batched(plan, frames, g, windows, dt, xf, cell, flags)   # capture + warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lcs.lcs_advect_batched(plan, frames, g, windows, dt, xf, cell, flags, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    lcs.lcs_sync_status()
+    steps = int(sum(round(T / dt) for _, T in windows)) * ns
+    ms = float(np.median(times))
+    out = {"workload": "double_gyre_batched_1025x513_64windows", "windows": nw,
+           "seeds_per_window": ns, "tracer_steps": steps, "ms_per_launch": ms,
+           "tracer_steps_per_s": steps / (ms * 1e-3),
+           "roofline": {"kernel": "advect_batched_kernel<2>", "bound": "hbm",
+                        "achieved": 256 * steps / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": 256 * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "bytes_per_unit": 256, "unit_of_work": "2D tracer-RK4-step"},
+           "graph": plan.stats()}
+    plan.close()
+    return out
+
+
+def bench_random_fourier(torch, lcs, inputs, reps=2):
+    """Divergence-free random-Fourier field, 256^3 x 65 FP32 frames, 512x512x256
+    seeds, forward and backward FTLE from t0 = 4 with |T| = 4, dt = 0.01."""
+    fs = inputs.random_fourier_frames(n=256, n_frames=65, dt_frame=0.125, device="cuda")
+    L = 2 * math.pi
+    g = inputs.SeedGrid(3, (512, 512, 256), (0.0, 0.0, 0.0), (L / 512, L / 512, L / 256),
+                        (True, True, True))
+    frames = lcs.DeviceFrames(fs, tensors=fs.u)
+    ns = g.count
+    xf = torch.empty((3, ns), dtype=torch.float32, device="cuda")
+    flags = torch.empty(ns, dtype=torch.uint8, device="cuda")
+    lam = torch.empty(ns, dtype=torch.float64, device="cuda")
+    sig = torch.empty(ns, dtype=torch.float64, device="cuda")
+    sfl = torch.empty(ns, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for T, dt in [(4.0, 0.01), (-4.0, -0.01)]:
+        lcs.lcs_advect(frames, g, 4.0, T, dt, xf, None, flags, want_cell=False, stream=stream)
+        torch.cuda.synchronize()
+        ta, tc = [], []
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            lcs.lcs_advect(frames, g, 4.0, T, dt, xf, None, flags, want_cell=False, stream=stream)
+            e[1].record(stream)
+            lcs.lcs_cg_ftle(g, xf, T, flags=flags, lambda_max=lam, ftle=sig, stencil_flags=sfl,
+                            stream=stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            ta.append(e[0].elapsed_time(e[1]))
+            tc.append(e[1].elapsed_time(e[2]))
+        res["forward" if T > 0 else "backward"] = (float(np.median(ta)), float(np.median(tc)),
+                                                   float(sig.mean().item()))
+    lcs.lcs_sync_status()
+    nsteps = 400
+    steps = 2 * ns * nsteps
+    adv = res["forward"][0] + res["backward"][0]
+    cgf = res["forward"][1] + res["backward"][1]
+    return {"workload": "random_fourier_256cubed_seeds512x512x256", "seeds": ns,
+            "tracer_steps": steps, "advect_ms_forward": res["forward"][0],
+            "advect_ms_backward": res["backward"][0], "cg_ftle_ms": cgf,
+            "tracer_steps_per_s": steps / ((adv + cgf) * 1e-3),
+            "ftle_points_per_s": 2 * ns / (cgf * 1e-3),
+            "mean_ftle_forward": res["forward"][2], "mean_ftle_backward": res["backward"][2],
+            "roofline": {"kernel": "advect_grid_kernel<3>", "bound": "hbm",
+                         "achieved": 768 * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": 768 * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "bytes_per_unit": 768, "unit_of_work": "3D tracer-RK4-step"}}
 
 
 def main():
@@ -196,6 +289,15 @@ def main():
         "cpu_baseline": None,
     }
     del frames, xf, cell, flags, Cm, sfl, lam, sig
+    if not args.no_extra:
+        torch.cuda.empty_cache()
+        print("bench: batched double gyre windows", file=sys.stderr, flush=True)
+        extra = {"batched": bench_batched(torch, lcs, inputs)}
+        torch.cuda.empty_cache()
+        print("bench: random-Fourier forward/backward", file=sys.stderr, flush=True)
+        extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs)
+        torch.cuda.empty_cache()
+        out["extra_workloads"] = extra
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(fs, g, W["t0"], W["T"], W["dt"], args.cpu_seconds)
