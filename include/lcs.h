@@ -247,6 +247,85 @@ lcs_status lcs_plan_destroy(lcs_plan_t plan);
  * (either pointer may be NULL). */
 lcs_status lcs_plan_stats(lcs_plan_t plan, int64_t *graph_launches, int64_t *graph_captures);
 
+/* ------------------------------------------------------------------------
+ * Learned flow-map surrogate: a Fourier-feature MLP that predicts the
+ * displacement of a point over a window tau (a local approximation of the
+ * flow map; the paper's discussion cites such approximations as a way to cut
+ * interpolation work on time series of seed grids, Sec. 4).  Plain RK4
+ * remains the reference and the fallback.
+ *
+ * Fixed architecture: input (x, y, z, t) -> v = (input - in_shift) * in_scale
+ * -> 128 features [cos(2 pi B v), sin(2 pi B v)] (B: 64 x 4) -> 4 hidden
+ * layers of 256 with the tanh form of GELU -> 3 outputs -> displacement =
+ * out_scale * output.  Hidden-layer products run on BF16 MFMA with FP32
+ * accumulation; features, biases, head and loss are FP32.
+ *
+ * FP32 master parameters, one flat vector of LCS_MLP_PARAMS values:
+ *   W_0 [128][256] (row-major [in][out]), b_0 [256],
+ *   W_l [256][256], b_l [256] for l = 1, 2, 3,
+ *   W_h [256][3], b_h [3].
+ * BF16 compute copies (LCS_MLP_BF16 values, written by lcs_mlp_refresh_bf16):
+ *   for l = 0..3: W_l as [in][out], then W_l^T as [out][in].
+ * ------------------------------------------------------------------------ */
+#define LCS_MLP_FREQ 64
+#define LCS_MLP_WIDTH 256
+#define LCS_MLP_HIDDEN 4
+#define LCS_MLP_PARAMS 231171
+#define LCS_MLP_BF16 458752
+
+typedef struct {
+    const float *freq;              /* [device] FP32, LCS_MLP_FREQ x 4, row-major */
+    float in_shift[4];
+    float in_scale[4];
+    float out_scale;
+    uint32_t reserved;              /* must be 0 */
+    const float *params;            /* [device] FP32 masters, LCS_MLP_PARAMS */
+    const uint16_t *params_bf16;    /* [device] BF16 copies, LCS_MLP_BF16 */
+} lcs_mlp_t;
+
+/* Bytes of the activation workspace of a batch (training: kept for backward). */
+int64_t lcs_mlp_workspace_bytes(int64_t batch, int32_t training);
+/* Bytes of the scratch lcs_mlp_backward needs for a batch. */
+int64_t lcs_mlp_backward_scratch_bytes(int64_t batch);
+
+/* lcs_mlp_refresh_bf16 -- write the BF16 compute copies of the hidden-layer
+ * matrices from the FP32 masters (after initialisation and every update).
+ * Errors: LCS_E_ARG, LCS_E_HIP. */
+lcs_status lcs_mlp_refresh_bf16(const float *params, uint16_t *params_bf16, void *stream);
+
+/* lcs_mlp_forward -- displacement dx [device] FP32 3 x batch of inputs
+ * xt [device] FP32 4 x batch (rows x, y, z, t).  workspace [device] of at least
+ * lcs_mlp_workspace_bytes(batch, training) bytes; with training != 0 it keeps
+ * the activations lcs_mlp_backward reads.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+lcs_status lcs_mlp_forward(const lcs_mlp_t *mlp, const float *xt, int64_t batch, float *dx,
+                           void *workspace, int64_t workspace_bytes, int32_t training,
+                           void *stream);
+
+/* lcs_mlp_backward -- grads [device] FP32 LCS_MLP_PARAMS (same layout as the
+ * masters) = gradient of sum(ddx * dx) for the batch whose training forward
+ * filled `workspace`; ddx [device] FP32 3 x batch.  Weight gradients are summed
+ * over fixed 2048-row chunks in a fixed order (deterministic).  scratch
+ * [device] of at least lcs_mlp_backward_scratch_bytes(batch) bytes.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const float *ddx,
+                            int64_t batch, float *grads, void *scratch, int64_t scratch_bytes,
+                            void *stream);
+
+/* lcs_mse_grad -- mean squared error of pred against target (n values each,
+ * [device] FP32): grad = 2 (pred - target) / n (or NULL) and loss [device]
+ * FP64 scalar = mean of squares (or NULL), summed in a fixed order.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+lcs_status lcs_mse_grad(const float *pred, const float *target, int64_t n, float *grad,
+                        double *loss, void *stream);
+
+/* lcs_adam_step -- one Adam update (Kingma & Ba, bias-corrected; step counts
+ * from 1) of params with grads, moment buffers m and v ([device] FP32, n each).
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+lcs_status lcs_adam_step(float *params, const float *grads, float *m, float *v, int64_t n,
+                         float lr, float beta1, float beta2, float eps, int32_t step,
+                         void *stream);
+
 /* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
 lcs_status lcs_sync_status(void *stream);
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblcs_hip.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "advect.hip", "cgftle.hip"]
+SOURCES = ["api.hip", "api_mlp.hip", "advect.hip", "cgftle.hip", "mlp.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

@@ -12,10 +12,12 @@
 #include "lcs_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}
 
-lcs_status fail(lcs_status st, const char *fmt, ...)
+namespace lcs {
+
+lcs_status set_error(lcs_status st, const char *fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -24,16 +26,21 @@ lcs_status fail(lcs_status st, const char *fmt, ...)
     return st;
 }
 
-lcs_status ok()
+lcs_status clear_error()
 {
     g_err[0] = '\0';
     return LCS_OK;
 }
 
-lcs_status hip_fail(hipError_t e, const char *where)
+lcs_status hip_error(hipError_t e, const char *where)
 {
-    return fail(LCS_E_HIP, "%s: %s", where, hipGetErrorString(e));
+    return set_error(LCS_E_HIP, "%s: %s", where, hipGetErrorString(e));
 }
+
+}  // namespace lcs
+
+namespace {
+
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
@@ -42,45 +49,45 @@ constexpr long long kMaxSeeds = (1LL << 31) - 1;
 
 lcs_status check_velocity(const lcs_velocity_t *v)
 {
-    if (!v) return fail(LCS_E_ARG, "velocity descriptor is NULL");
-    if (v->dim != 2 && v->dim != 3) return fail(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
-    if (v->reserved != 0) return fail(LCS_E_ARG, "velocity reserved field must be 0");
-    if (v->n_frames < 2) return fail(LCS_E_SHAPE, "need at least 2 frames (got %d)", v->n_frames);
+    if (!v) return lcs::set_error(LCS_E_ARG, "velocity descriptor is NULL");
+    if (v->dim != 2 && v->dim != 3) return lcs::set_error(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
+    if (v->reserved != 0) return lcs::set_error(LCS_E_ARG, "velocity reserved field must be 0");
+    if (v->n_frames < 2) return lcs::set_error(LCS_E_SHAPE, "need at least 2 frames (got %d)", v->n_frames);
     if (!finite_pos(v->dt_frame) || !isfinite(v->t_first))
-        return fail(LCS_E_ARG, "t_first must be finite and dt_frame > 0");
-    if (v->periodic_mask >> v->dim) return fail(LCS_E_ARG, "periodic_mask has bits beyond dim");
+        return lcs::set_error(LCS_E_ARG, "t_first must be finite and dt_frame > 0");
+    if (v->periodic_mask >> v->dim) return lcs::set_error(LCS_E_ARG, "periodic_mask has bits beyond dim");
     long long nodes = 1;
     for (int a = 0; a < 3; ++a) {
         if (a < v->dim) {
-            if (v->n[a] < 2) return fail(LCS_E_SHAPE, "velocity axis %d needs >= 2 nodes", a);
+            if (v->n[a] < 2) return lcs::set_error(LCS_E_SHAPE, "velocity axis %d needs >= 2 nodes", a);
             if (!finite_pos(v->spacing[a]) || !isfinite(v->origin[a]))
-                return fail(LCS_E_ARG, "velocity axis %d: bad origin/spacing", a);
-            if (!v->u[a]) return fail(LCS_E_ARG, "velocity component %d pointer is NULL", a);
+                return lcs::set_error(LCS_E_ARG, "velocity axis %d: bad origin/spacing", a);
+            if (!v->u[a]) return lcs::set_error(LCS_E_ARG, "velocity component %d pointer is NULL", a);
         } else if (v->n[a] != 1) {
-            return fail(LCS_E_SHAPE, "velocity n[%d] must be 1 in %dD", a, v->dim);
+            return lcs::set_error(LCS_E_SHAPE, "velocity n[%d] must be 1 in %dD", a, v->dim);
         }
         nodes *= v->n[a];
-        if (nodes > kMaxNodes) return fail(LCS_E_SHAPE, "velocity frame exceeds 2^31-1 nodes");
+        if (nodes > kMaxNodes) return lcs::set_error(LCS_E_SHAPE, "velocity frame exceeds 2^31-1 nodes");
     }
     return LCS_OK;
 }
 
 lcs_status check_seeds(const lcs_seed_grid_t *g, int dim)
 {
-    if (!g) return fail(LCS_E_ARG, "seed grid descriptor is NULL");
-    if (g->dim != dim) return fail(LCS_E_ARG, "seed grid dim %d != %d", g->dim, dim);
-    if (g->periodic_mask >> g->dim) return fail(LCS_E_ARG, "seed periodic_mask has bits beyond dim");
+    if (!g) return lcs::set_error(LCS_E_ARG, "seed grid descriptor is NULL");
+    if (g->dim != dim) return lcs::set_error(LCS_E_ARG, "seed grid dim %d != %d", g->dim, dim);
+    if (g->periodic_mask >> g->dim) return lcs::set_error(LCS_E_ARG, "seed periodic_mask has bits beyond dim");
     long long ns = 1;
     for (int a = 0; a < 3; ++a) {
         if (a < g->dim) {
-            if (g->n[a] < 2) return fail(LCS_E_SHAPE, "seed axis %d needs >= 2 seeds", a);
+            if (g->n[a] < 2) return lcs::set_error(LCS_E_SHAPE, "seed axis %d needs >= 2 seeds", a);
             if (!finite_pos(g->spacing[a]) || !isfinite(g->origin[a]))
-                return fail(LCS_E_ARG, "seed axis %d: bad origin/spacing", a);
+                return lcs::set_error(LCS_E_ARG, "seed axis %d: bad origin/spacing", a);
         } else if (g->n[a] != 1) {
-            return fail(LCS_E_SHAPE, "seed n[%d] must be 1 in %dD", a, g->dim);
+            return lcs::set_error(LCS_E_SHAPE, "seed n[%d] must be 1 in %dD", a, g->dim);
         }
         ns *= g->n[a];
-        if (ns > kMaxSeeds) return fail(LCS_E_SHAPE, "seed grid exceeds 2^31-1 seeds");
+        if (ns > kMaxSeeds) return lcs::set_error(LCS_E_SHAPE, "seed grid exceeds 2^31-1 seeds");
     }
     return LCS_OK;
 }
@@ -89,12 +96,12 @@ lcs_status check_seeds(const lcs_seed_grid_t *g, int dim)
 lcs_status check_steps(double T, double dt, int *nsteps)
 {
     if (!isfinite(T) || !isfinite(dt) || T == 0.0 || dt == 0.0)
-        return fail(LCS_E_STEP, "T and dt must be finite and non-zero");
-    if ((T > 0.0) != (dt > 0.0)) return fail(LCS_E_STEP, "sign(dt) must equal sign(T)");
+        return lcs::set_error(LCS_E_STEP, "T and dt must be finite and non-zero");
+    if ((T > 0.0) != (dt > 0.0)) return lcs::set_error(LCS_E_STEP, "sign(dt) must equal sign(T)");
     const double r = T / dt;
     const double N = nearbyint(r);
-    if (fabs(r - N) > 1e-9 * fabs(r)) return fail(LCS_E_STEP, "T/dt = %.17g is not an integer", r);
-    if (N < 1.0 || N > 2147483647.0) return fail(LCS_E_STEP, "step count out of range");
+    if (fabs(r - N) > 1e-9 * fabs(r)) return lcs::set_error(LCS_E_STEP, "T/dt = %.17g is not an integer", r);
+    if (N < 1.0 || N > 2147483647.0) return lcs::set_error(LCS_E_STEP, "step count out of range");
     *nsteps = (int)N;
     return LCS_OK;
 }
@@ -106,7 +113,7 @@ lcs_status check_seed_domain(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
     for (int a = 0; a < vel->dim; ++a) {
         const bool vper = (vel->periodic_mask >> a) & 1u;
         const bool sper = (seeds->periodic_mask >> a) & 1u;
-        if (sper && !vper) return fail(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
+        if (sper && !vper) return lcs::set_error(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
         if (vper) continue;
         const double lo = vel->origin[a];
         const double hi = vel->origin[a] + (double)(vel->n[a] - 1) * vel->spacing[a];
@@ -114,7 +121,7 @@ lcs_status check_seed_domain(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
         const double s1 = seeds->origin[a] + (double)(seeds->n[a] - 1) * seeds->spacing[a];
         const double tol = 1e-9 * (hi - lo);
         if (s0 < lo - tol || s1 > hi + tol)
-            return fail(LCS_E_SEED_DOMAIN, "seeds on axis %d span [%g, %g] outside [%g, %g]", a,
+            return lcs::set_error(LCS_E_SEED_DOMAIN, "seeds on axis %d span [%g, %g] outside [%g, %g]", a,
                         s0, s1, lo, hi);
     }
     return LCS_OK;
@@ -216,39 +223,39 @@ extern "C" {
 
 lcs_status lcs_plan_create(lcs_plan_t *plan)
 {
-    if (!plan) return fail(LCS_E_ARG, "plan pointer is NULL");
+    if (!plan) return lcs::set_error(LCS_E_ARG, "plan pointer is NULL");
     *plan = nullptr;
     lcs_plan *p = new (std::nothrow) lcs_plan();
-    if (!p) return fail(LCS_E_ARG, "out of host memory");
+    if (!p) return lcs::set_error(LCS_E_ARG, "out of host memory");
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_counter, sizeof(int));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         if (p->d_counter) (void)hipFree(p->d_counter);
         delete p;
-        return hip_fail(e, "lcs_plan_create");
+        return lcs::hip_error(e, "lcs_plan_create");
     }
     *plan = p;
-    return ok();
+    return lcs::clear_error();
 }
 
 lcs_status lcs_plan_destroy(lcs_plan_t plan)
 {
-    if (!plan) return ok();
+    if (!plan) return lcs::clear_error();
     (void)hipStreamSynchronize(plan->cap_stream);
     drop_graph(plan);
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     if (plan->d_counter) (void)hipFree(plan->d_counter);
     delete plan;
-    return ok();
+    return lcs::clear_error();
 }
 
 lcs_status lcs_plan_stats(lcs_plan_t plan, int64_t *graph_launches, int64_t *graph_captures)
 {
-    if (!plan) return fail(LCS_E_ARG, "plan is NULL");
+    if (!plan) return lcs::set_error(LCS_E_ARG, "plan is NULL");
     if (graph_launches) *graph_launches = plan->launches;
     if (graph_captures) *graph_captures = plan->captures;
-    return ok();
+    return lcs::clear_error();
 }
 
 const char *lcs_last_error(void) { return g_err; }
@@ -258,10 +265,10 @@ int32_t lcs_version(void) { return 100; }
 lcs_status lcs_sync_status(void *stream)
 {
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (e != hipSuccess) return lcs::hip_error(e, "hipStreamSynchronize");
     e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "pending error");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "pending error");
+    return lcs::clear_error();
 }
 
 lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
@@ -270,13 +277,13 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, d
     lcs_status st;
     if ((st = check_velocity(vel)) != LCS_OK) return st;
     if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
-    if (!xf) return fail(LCS_E_ARG, "xf is NULL");
+    if (!xf) return lcs::set_error(LCS_E_ARG, "xf is NULL");
     int nsteps = 0;
     if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
     const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
     const double t1 = t0 + T;
     if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
-        return fail(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
                     vel->t_first, t_last);
     if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
     lcs::AdvectArgs A;
@@ -291,8 +298,8 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, d
     A.cell = reinterpret_cast<long long *>(cell);
     A.flags = flags;
     hipError_t e = lcs::launch_advect_grid(vel->dim, A, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "advect launch");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "advect launch");
+    return lcs::clear_error();
 }
 
 lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
@@ -301,12 +308,12 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
                               uint8_t *flags, void *stream)
 {
     lcs_status st;
-    if (!plan) return fail(LCS_E_ARG, "plan is NULL (create one with lcs_plan_create)");
+    if (!plan) return lcs::set_error(LCS_E_ARG, "plan is NULL (create one with lcs_plan_create)");
     if ((st = check_velocity(vel)) != LCS_OK) return st;
     if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
-    if (!xf || !windows) return fail(LCS_E_ARG, "xf and windows must not be NULL");
+    if (!xf || !windows) return lcs::set_error(LCS_E_ARG, "xf and windows must not be NULL");
     if (n_windows < 1 || n_windows > lcs::kMaxWindows)
-        return fail(LCS_E_SHAPE, "n_windows must be in [1, %d]", lcs::kMaxWindows);
+        return lcs::set_error(LCS_E_SHAPE, "n_windows must be in [1, %d]", lcs::kMaxWindows);
     if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
     const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
     lcs::BatchArgs A;
@@ -317,7 +324,7 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
         const double t0 = windows[w].t0, t1 = t0 + windows[w].T;
         if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first &&
               t1 <= t_last))
-            return fail(LCS_E_TIME_RANGE, "window %d [%g, %g] leaves the frame span [%g, %g]", w,
+            return lcs::set_error(LCS_E_TIME_RANGE, "window %d [%g, %g] leaves the frame span [%g, %g]", w,
                         t0, t1, vel->t_first, t_last);
         A.win[w].t0 = t0;
         A.win[w].nsteps = nsteps;
@@ -339,7 +346,7 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
     A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
     A.n_windows = n_windows;
     const long long items = (long long)n_windows * A.g.n_blocks;
-    if (items > 2147483647LL) return fail(LCS_E_SHAPE, "too many (window, tile) items");
+    if (items > 2147483647LL) return lcs::set_error(LCS_E_SHAPE, "too many (window, tile) items");
     A.total_items = (int)items;
     A.counter = plan->d_counter;
     A.xf = xf;
@@ -348,12 +355,12 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
 
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev != plan->device) return fail(LCS_E_ARG, "plan was created on device %d, current is %d",
+    if (e != hipSuccess) return lcs::hip_error(e, "hipGetDevice");
+    if (dev != plan->device) return lcs::set_error(LCS_E_ARG, "plan was created on device %d, current is %d",
                                          plan->device, dev);
     int n_cu = 0;
     e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    if (e != hipSuccess) return lcs::hip_error(e, "hipDeviceGetAttribute");
     const int grid = n_cu * lcs::batched_blocks_per_cu(vel->dim);
 
     const bool same = plan->have_graph && plan->key_dim == vel->dim && plan->key_grid == grid &&
@@ -362,20 +369,20 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
         drop_graph(plan);
         // capture (counter reset, persistent kernel) on the plan's own stream
         e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        if (e != hipSuccess) return lcs::hip_error(e, "hipStreamBeginCapture");
         hipError_t e1 = lcs::launch_reset_counter(plan->d_counter, plan->cap_stream);
         hipError_t e2 = lcs::launch_advect_batched(vel->dim, A, grid, plan->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(plan->cap_stream, &g);
         if (e1 != hipSuccess || e2 != hipSuccess || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            return hip_fail(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
+            return lcs::hip_error(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e), "graph capture");
         }
         hipGraphExec_t x = nullptr;
         e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             (void)hipGraphDestroy(g);
-            return hip_fail(e, "hipGraphInstantiate");
+            return lcs::hip_error(e, "hipGraphInstantiate");
         }
         plan->graph = g;
         plan->exec = x;
@@ -386,9 +393,9 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
         plan->captures++;
     }
     e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    if (e != hipSuccess) return lcs::hip_error(e, "hipGraphLaunch");
     plan->launches++;
-    return ok();
+    return lcs::clear_error();
 }
 
 lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0, int64_t n,
@@ -397,8 +404,8 @@ lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const d
 {
     lcs_status st;
     if ((st = check_velocity(vel)) != LCS_OK) return st;
-    if (!x0 || !t0 || !xf) return fail(LCS_E_ARG, "x0, t0 and xf must not be NULL");
-    if (n < 1 || n > kMaxSeeds) return fail(LCS_E_SHAPE, "point count %lld out of range", (long long)n);
+    if (!x0 || !t0 || !xf) return lcs::set_error(LCS_E_ARG, "x0, t0 and xf must not be NULL");
+    if (n < 1 || n > kMaxSeeds) return lcs::set_error(LCS_E_SHAPE, "point count %lld out of range", (long long)n);
     int nsteps = 0;
     if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
     lcs::AdvectArgs A;
@@ -414,20 +421,20 @@ lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const d
     A.cell = reinterpret_cast<long long *>(cell);
     A.flags = flags;
     hipError_t e = lcs::launch_advect_points(vel->dim, A, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "advect_points launch");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_points launch");
+    return lcs::clear_error();
 }
 
 static lcs_status cg_common(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags,
                             lcs::CgArgs &A)
 {
     lcs_status st;
-    if (!seeds) return fail(LCS_E_ARG, "seed grid descriptor is NULL");
+    if (!seeds) return lcs::set_error(LCS_E_ARG, "seed grid descriptor is NULL");
     if ((st = check_seeds(seeds, seeds->dim)) != LCS_OK) return st;
-    if (seeds->dim != 2 && seeds->dim != 3) return fail(LCS_E_ARG, "seed dim must be 2 or 3");
-    if (!xf) return fail(LCS_E_ARG, "xf is NULL");
+    if (seeds->dim != 2 && seeds->dim != 3) return lcs::set_error(LCS_E_ARG, "seed dim must be 2 or 3");
+    if (!xf) return lcs::set_error(LCS_E_ARG, "xf is NULL");
     if (seeds->n[1] > 65535 * 4 || seeds->n[2] > 65535)
-        return fail(LCS_E_SHAPE, "seed grid too tall for the launch shape");
+        return lcs::set_error(LCS_E_SHAPE, "seed grid too tall for the launch shape");
     memset(&A, 0, sizeof(A));
     A.dim = seeds->dim;
     for (int a = 0; a < 3; ++a) {
@@ -448,12 +455,12 @@ lcs_status lcs_cg_tensor(const lcs_seed_grid_t *seeds, const float *xf, const ui
     lcs::CgArgs A;
     lcs_status st = cg_common(seeds, xf, flags, A);
     if (st != LCS_OK) return st;
-    if (!C) return fail(LCS_E_ARG, "C is NULL");
+    if (!C) return lcs::set_error(LCS_E_ARG, "C is NULL");
     A.C = C;
     A.sflags = stencil_flags;
     hipError_t e = lcs::launch_cg(A, false, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "cg launch");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "cg launch");
+    return lcs::clear_error();
 }
 
 lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint8_t *flags, double T,
@@ -462,25 +469,25 @@ lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint
     lcs::CgArgs A;
     lcs_status st = cg_common(seeds, xf, flags, A);
     if (st != LCS_OK) return st;
-    if (!lambda_max && !ftle) return fail(LCS_E_ARG, "lambda_max and ftle are both NULL");
-    if (!isfinite(T) || T == 0.0) return fail(LCS_E_ARG, "T must be finite and non-zero");
+    if (!lambda_max && !ftle) return lcs::set_error(LCS_E_ARG, "lambda_max and ftle are both NULL");
+    if (!isfinite(T) || T == 0.0) return lcs::set_error(LCS_E_ARG, "T must be finite and non-zero");
     A.lam = lambda_max;
     A.ftle = ftle;
     A.sflags = stencil_flags;
     A.inv_two_T = 1.0 / (2.0 * fabs(T));
     hipError_t e = lcs::launch_cg(A, true, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "cg_ftle launch");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "cg_ftle launch");
+    return lcs::clear_error();
 }
 
 lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T, double *lambda_max,
                     double *ftle, void *stream)
 {
-    if (dim != 2 && dim != 3) return fail(LCS_E_ARG, "dim must be 2 or 3");
-    if (n_points < 1 || n_points > kMaxSeeds) return fail(LCS_E_SHAPE, "n_points out of range");
-    if (!C) return fail(LCS_E_ARG, "C is NULL");
-    if (!lambda_max && !ftle) return fail(LCS_E_ARG, "lambda_max and ftle are both NULL");
-    if (!isfinite(T) || T == 0.0) return fail(LCS_E_ARG, "T must be finite and non-zero");
+    if (dim != 2 && dim != 3) return lcs::set_error(LCS_E_ARG, "dim must be 2 or 3");
+    if (n_points < 1 || n_points > kMaxSeeds) return lcs::set_error(LCS_E_SHAPE, "n_points out of range");
+    if (!C) return lcs::set_error(LCS_E_ARG, "C is NULL");
+    if (!lambda_max && !ftle) return lcs::set_error(LCS_E_ARG, "lambda_max and ftle are both NULL");
+    if (!isfinite(T) || T == 0.0) return lcs::set_error(LCS_E_ARG, "T must be finite and non-zero");
     lcs::FtleArgs A;
     A.n = n_points;
     A.C = C;
@@ -488,8 +495,8 @@ lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T, do
     A.ftle = ftle;
     A.inv_two_T = 1.0 / (2.0 * fabs(T));
     hipError_t e = lcs::launch_ftle(dim, A, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "ftle launch");
-    return ok();
+    if (e != hipSuccess) return lcs::hip_error(e, "ftle launch");
+    return lcs::clear_error();
 }
 
 }  // extern "C"

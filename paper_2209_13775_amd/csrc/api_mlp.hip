@@ -1,0 +1,235 @@
+// api_mlp.hip -- C ABI of the Fourier-feature MLP surrogate: forward,
+// backward, loss gradient, Adam and the BF16 weight copies.  Arguments are
+// validated before anything is launched; all buffers belong to the caller.
+
+#include <math.h>
+#include <string.h>
+
+#include "lcs_internal.h"
+
+namespace {
+
+constexpr long long kChunk = 2048;   // rows per partial sum of a weight gradient
+
+long long nchunks(long long B) { return (B + kChunk - 1) / kChunk; }
+
+// training workspace (BF16): H0 [B][128], then (Z_l, H_l) [B][256] for l = 1..4
+// inference workspace (BF16): H0 [B][128], Ha [B][256], Hb [B][256]
+long long ws_bytes(long long B, bool training)
+{
+    const long long per = training ? (long long)lcs::kMlpFeat + 2LL * lcs::kMlpHidden * lcs::kMlpWidth
+                                   : (long long)lcs::kMlpFeat + 2LL * lcs::kMlpWidth;
+    return 2LL * B * per;
+}
+
+long long scratch_bytes(long long B)
+{
+    const long long nc = nchunks(B);
+    const long long part = (long long)lcs::kMlpWidth * lcs::kMlpWidth;
+    return 2LL * 2 * B * lcs::kMlpWidth + 4LL * nc * (part + lcs::kMlpWidth + lcs::kHeadPart + 64);
+}
+
+lcs_status check_mlp(const lcs_mlp_t *m)
+{
+    if (!m) return lcs::set_error(LCS_E_ARG, "mlp descriptor is NULL");
+    if (!m->freq || !m->params || !m->params_bf16)
+        return lcs::set_error(LCS_E_ARG, "mlp freq, params and params_bf16 must not be NULL");
+    if (m->reserved != 0) return lcs::set_error(LCS_E_ARG, "mlp reserved field must be 0");
+    for (int a = 0; a < 4; ++a)
+        if (!isfinite(m->in_shift[a]) || !isfinite(m->in_scale[a]))
+            return lcs::set_error(LCS_E_ARG, "mlp input normalisation must be finite");
+    if (!isfinite(m->out_scale)) return lcs::set_error(LCS_E_ARG, "mlp out_scale must be finite");
+    return LCS_OK;
+}
+
+lcs::MlpDev make_dev(const lcs_mlp_t *m)
+{
+    lcs::MlpDev d;
+    memset(&d, 0, sizeof(d));
+    d.freq = m->freq;
+    for (int a = 0; a < 4; ++a) {
+        d.in_shift[a] = m->in_shift[a];
+        d.in_scale[a] = m->in_scale[a];
+    }
+    d.out_scale = m->out_scale;
+    d.params = m->params;
+    d.wbf = m->params_bf16;
+    return d;
+}
+
+struct Ws {
+    uint16_t *H0;
+    uint16_t *Z[lcs::kMlpHidden + 1];
+    uint16_t *H[lcs::kMlpHidden + 1];
+};
+
+Ws carve(void *ws, long long B, bool training)
+{
+    Ws w;
+    memset(&w, 0, sizeof(w));
+    uint16_t *p = static_cast<uint16_t *>(ws);
+    w.H0 = p;
+    p += B * lcs::kMlpFeat;
+    w.H[0] = w.H0;
+    for (int l = 1; l <= lcs::kMlpHidden; ++l) {
+        if (training) {
+            w.Z[l] = p;
+            p += B * lcs::kMlpWidth;
+            w.H[l] = p;
+            p += B * lcs::kMlpWidth;
+        } else {
+            // ping-pong between two buffers
+            w.H[l] = static_cast<uint16_t *>(ws) + B * lcs::kMlpFeat + ((l - 1) % 2) * B * lcs::kMlpWidth;
+        }
+    }
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lcs_mlp_workspace_bytes(int64_t batch, int32_t training)
+{
+    return batch > 0 ? ws_bytes(batch, training != 0) : 0;
+}
+
+int64_t lcs_mlp_backward_scratch_bytes(int64_t batch) { return batch > 0 ? scratch_bytes(batch) : 0; }
+
+lcs_status lcs_mlp_refresh_bf16(const float *params, uint16_t *params_bf16, void *stream)
+{
+    if (!params || !params_bf16) return lcs::set_error(LCS_E_ARG, "params and params_bf16 must not be NULL");
+    hipError_t e = lcs::launch_refresh_bf16(params, params_bf16, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "refresh_bf16 launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_mlp_forward(const lcs_mlp_t *mlp, const float *xt, int64_t batch, float *dx,
+                           void *workspace, int64_t workspace_bytes, int32_t training, void *stream)
+{
+    lcs_status st;
+    if ((st = check_mlp(mlp)) != LCS_OK) return st;
+    if (!xt || !dx || !workspace) return lcs::set_error(LCS_E_ARG, "xt, dx and workspace must not be NULL");
+    if (batch < 1 || batch > (1LL << 31) - 1) return lcs::set_error(LCS_E_SHAPE, "batch out of range");
+    if (workspace_bytes < ws_bytes(batch, training != 0))
+        return lcs::set_error(LCS_E_SHAPE, "workspace of %lld bytes is smaller than the %lld needed",
+                              (long long)workspace_bytes, ws_bytes(batch, training != 0));
+    hipStream_t s = (hipStream_t)stream;
+    const lcs::MlpDev P = make_dev(mlp);
+    const Ws w = carve(workspace, batch, training != 0);
+    hipError_t e = lcs::launch_features(P, xt, batch, w.H0, s);
+    for (int l = 0; l < lcs::kMlpHidden && e == hipSuccess; ++l) {
+        lcs::GemmArgs g;
+        memset(&g, 0, sizeof(g));
+        g.A = w.H[l];
+        g.Bt = P.wbf + lcs::mlp_off_bf16(l) + (long long)lcs::mlp_in_width(l) * lcs::kMlpWidth;
+        g.M = batch;
+        g.N = lcs::kMlpWidth;
+        g.K = lcs::mlp_in_width(l);
+        g.bias = P.params + lcs::mlp_off_b(l);
+        g.H = w.H[l + 1];
+        g.Z = training ? w.Z[l + 1] : nullptr;
+        e = lcs::launch_gemm(g, false, s);
+    }
+    if (e == hipSuccess) e = lcs::launch_head_fwd(P, w.H[lcs::kMlpHidden], batch, dx, s);
+    if (e != hipSuccess) return lcs::hip_error(e, "mlp forward launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const float *ddx,
+                            int64_t batch, float *grads, void *scratch, int64_t scratch_size,
+                            void *stream)
+{
+    lcs_status st;
+    if ((st = check_mlp(mlp)) != LCS_OK) return st;
+    if (!workspace || !ddx || !grads || !scratch)
+        return lcs::set_error(LCS_E_ARG, "workspace, ddx, grads and scratch must not be NULL");
+    if (batch < 1 || batch > (1LL << 31) - 1) return lcs::set_error(LCS_E_SHAPE, "batch out of range");
+    if (scratch_size < scratch_bytes(batch))
+        return lcs::set_error(LCS_E_SHAPE, "scratch of %lld bytes is smaller than the %lld needed",
+                              (long long)scratch_size, scratch_bytes(batch));
+    hipStream_t s = (hipStream_t)stream;
+    const lcs::MlpDev P = make_dev(mlp);
+    const Ws w = carve(const_cast<void *>(workspace), batch, true);
+    const long long nc = nchunks(batch);
+    uint16_t *dA = static_cast<uint16_t *>(scratch);
+    uint16_t *dB = dA + batch * lcs::kMlpWidth;
+    float *part = reinterpret_cast<float *>(dB + batch * lcs::kMlpWidth);
+    float *part_b = part + nc * (long long)lcs::kMlpWidth * lcs::kMlpWidth;
+    float *part_h = part_b + nc * lcs::kMlpWidth;
+
+    hipError_t e = lcs::launch_head_bwd(P, ddx, w.Z[lcs::kMlpHidden], w.H[lcs::kMlpHidden], batch, dA,
+                                        kChunk, (int)nc, part_h, s);
+    if (e == hipSuccess)
+        e = lcs::launch_reduce_chunks(part_h, (int)nc, lcs::kHeadPart, grads + lcs::kOffWh, s);
+    uint16_t *cur = dA, *nxt = dB;
+    for (int l = lcs::kMlpHidden - 1; l >= 0 && e == hipSuccess; --l) {
+        const int K = lcs::mlp_in_width(l);
+        lcs::WgradArgs wg;
+        wg.X = w.H[l];
+        wg.D = cur;
+        wg.M = batch;
+        wg.K = K;
+        wg.N = lcs::kMlpWidth;
+        wg.chunk = kChunk;
+        wg.part = part;
+        e = lcs::launch_wgrad(wg, (int)nc, s);
+        if (e == hipSuccess)
+            e = lcs::launch_reduce_chunks(part, (int)nc, (long long)K * lcs::kMlpWidth,
+                                          grads + lcs::mlp_off_w(l), s);
+        if (e == hipSuccess) e = lcs::launch_colsum(cur, batch, lcs::kMlpWidth, kChunk, (int)nc, part_b, s);
+        if (e == hipSuccess)
+            e = lcs::launch_reduce_chunks(part_b, (int)nc, lcs::kMlpWidth, grads + lcs::mlp_off_b(l), s);
+        if (l > 0 && e == hipSuccess) {
+            lcs::GemmArgs g;
+            memset(&g, 0, sizeof(g));
+            g.A = cur;                                        // dZ_{l+1} [B][256]
+            g.Bt = P.wbf + lcs::mlp_off_bf16(l);              // W_l as [in][out] = Bt[N=in][K=out]
+            g.M = batch;
+            g.N = K;
+            g.K = lcs::kMlpWidth;
+            g.H = nxt;                                        // dZ_l
+            g.Z = w.Z[l];
+            e = lcs::launch_gemm(g, true, s);
+            uint16_t *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+    }
+    if (e != hipSuccess) return lcs::hip_error(e, "mlp backward launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_mse_grad(const float *pred, const float *target, int64_t n, float *grad, double *loss,
+                        void *stream)
+{
+    if (!pred || !target) return lcs::set_error(LCS_E_ARG, "pred and target must not be NULL");
+    if (!grad && !loss) return lcs::set_error(LCS_E_ARG, "grad and loss are both NULL");
+    if (n < 1) return lcs::set_error(LCS_E_SHAPE, "n must be positive");
+    hipError_t e = lcs::launch_mse(pred, target, n, (float)(2.0 / (double)n), grad, loss,
+                                   1.0 / (double)n, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "mse launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_adam_step(float *params, const float *grads, float *m, float *v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int32_t step, void *stream)
+{
+    if (!params || !grads || !m || !v) return lcs::set_error(LCS_E_ARG, "NULL buffer");
+    if (n < 1) return lcs::set_error(LCS_E_SHAPE, "n must be positive");
+    if (step < 1) return lcs::set_error(LCS_E_ARG, "step counts from 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && isfinite(lr)))
+        return lcs::set_error(LCS_E_ARG, "bad Adam hyper-parameters");
+    lcs::AdamArgs a;
+    a.lr = lr;
+    a.beta1 = beta1;
+    a.beta2 = beta2;
+    a.eps = eps;
+    a.c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+    a.c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+    hipError_t e = lcs::launch_adam(params, grads, m, v, n, a, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "adam launch");
+    return lcs::clear_error();
+}
+
+}  // extern "C"

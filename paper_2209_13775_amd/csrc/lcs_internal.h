@@ -113,6 +113,92 @@ struct BatchArgs {
 
 static_assert(sizeof(BatchArgs) <= 4096, "kernel arguments must fit the 4 KiB kernarg segment");
 
+// ---------------------------------------------------------------------------
+// Fourier-feature MLP surrogate (fixed architecture: 64 frequencies -> 128
+// features -> 4 x 256 GELU -> 3)
+// ---------------------------------------------------------------------------
+constexpr int kMlpFreq = LCS_MLP_FREQ;
+constexpr int kMlpFeat = 2 * LCS_MLP_FREQ;
+constexpr int kMlpWidth = LCS_MLP_WIDTH;
+constexpr int kMlpHidden = LCS_MLP_HIDDEN;
+constexpr long long kMlpParams = LCS_MLP_PARAMS;
+constexpr long long kBf16Count = LCS_MLP_BF16;
+constexpr int kHeadPart = 3 * kMlpWidth + 3;
+
+__host__ __device__ constexpr int mlp_in_width(int l) { return l == 0 ? kMlpFeat : kMlpWidth; }
+// FP32 parameter offsets: W_l ([in][out], row-major) then b_l, for l = 0..3; then W_h, b_h
+__host__ __device__ constexpr long long mlp_off_w(int l)
+{
+    return l == 0 ? 0 : (long long)kMlpFeat * kMlpWidth + kMlpWidth +
+                            (long long)(l - 1) * ((long long)kMlpWidth * kMlpWidth + kMlpWidth);
+}
+__host__ __device__ constexpr long long mlp_off_b(int l)
+{
+    return mlp_off_w(l) + (long long)mlp_in_width(l) * kMlpWidth;
+}
+constexpr long long kOffWh = mlp_off_w(kMlpHidden);
+constexpr long long kOffBh = kOffWh + 3LL * kMlpWidth;
+static_assert(kOffBh + 3 == kMlpParams, "parameter layout");
+// BF16 copies: for each hidden layer, W_l as [in][out] then W_l^T as [out][in]
+__host__ __device__ constexpr long long mlp_off_bf16(int l)
+{
+    return l == 0 ? 0 : mlp_off_bf16(l - 1) + 2LL * mlp_in_width(l - 1) * kMlpWidth;
+}
+static_assert(mlp_off_bf16(kMlpHidden) == kBf16Count, "bf16 layout");
+
+struct MlpDev {
+    const float *freq;
+    float in_shift[4];
+    float in_scale[4];
+    float out_scale;
+    const float *params;
+    const uint16_t *wbf;
+};
+
+struct GemmArgs {
+    const uint16_t *A;        // [M][K]
+    const uint16_t *Bt;       // [N][K]
+    long long M;
+    int N, K;
+    const float *bias;        // forward only
+    uint16_t *H;              // output [M][N]
+    uint16_t *Z;              // forward: pre-activation out (optional); backward: pre-activation in
+};
+
+struct WgradArgs {
+    const uint16_t *X;        // [M][K]
+    const uint16_t *D;        // [M][N]
+    long long M;
+    int K, N;
+    long long chunk;
+    float *part;              // [nchunk][K][N]
+};
+
+struct AdamArgs {
+    float lr, beta1, beta2, eps, c1, c2;
+};
+
+hipError_t launch_features(const MlpDev &P, const float *xt, long long M, uint16_t *H0, hipStream_t s);
+hipError_t launch_gemm(const GemmArgs &g, bool backward, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs &g, int nchunk, hipStream_t s);
+hipError_t launch_colsum(const uint16_t *D, long long M, int N, long long chunk, int nchunk,
+                         float *part, hipStream_t s);
+hipError_t launch_reduce_chunks(const float *part, int nchunk, long long len, float *out, hipStream_t s);
+hipError_t launch_head_fwd(const MlpDev &P, const uint16_t *H4, long long M, float *dx, hipStream_t s);
+hipError_t launch_head_bwd(const MlpDev &P, const float *ddx, const uint16_t *Z4, const uint16_t *H4,
+                           long long M, uint16_t *dZ4, long long chunk, int nchunk, float *part,
+                           hipStream_t s);
+hipError_t launch_mse(const float *pred, const float *target, long long n, float scale, float *grad,
+                      double *loss, double loss_mult, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, const AdamArgs &a,
+                       hipStream_t s);
+hipError_t launch_refresh_bf16(const float *params, uint16_t *out, hipStream_t s);
+
+// error reporting shared by the ABI translation units
+lcs_status set_error(lcs_status st, const char *fmt, ...);
+lcs_status clear_error();
+lcs_status hip_error(hipError_t e, const char *where);
+
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_reset_counter(int *counter, hipStream_t s);
 hipError_t launch_advect_batched(int dim, const BatchArgs &a, int grid_blocks, hipStream_t s);

@@ -80,6 +80,11 @@ def _load(path: str = LIB_PATH):
         "lcs_plan_create": [P],
         "lcs_plan_destroy": [P],
         "lcs_plan_stats": [P, P, P],
+        "lcs_mlp_refresh_bf16": [P, P, P],
+        "lcs_mlp_forward": [P, P, I64, P, P, I64, I32, P],
+        "lcs_mlp_backward": [P, P, P, I64, P, P, I64, P],
+        "lcs_mse_grad": [P, P, I64, P, P, P],
+        "lcs_adam_step": [P, P, P, P, I64, C.c_float, C.c_float, C.c_float, C.c_float, I32, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -89,6 +94,11 @@ def _load(path: str = LIB_PATH):
     L.lcs_last_error.argtypes = []
     L.lcs_version.restype = C.c_int32
     L.lcs_version.argtypes = []
+    for name in ("lcs_mlp_workspace_bytes", "lcs_mlp_backward_scratch_bytes"):
+        fn = getattr(L, name)
+        fn.restype = C.c_int64
+    L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
+    L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
     return L
 
 
@@ -382,3 +392,124 @@ def lcs_advect_batched(plan: Plan, frames: DeviceFrames, seeds, windows, dt: flo
     _check(_lib.lcs_advect_batched(plan.handle, frames.ref, C.byref(sd), arr, nw, float(dt),
                                    _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
     return xf, cell, flags
+
+
+# ---------------------------------------------------------------------------
+# Learned surrogate (Fourier-feature MLP)
+# ---------------------------------------------------------------------------
+
+LCS_MLP_FREQ = 64
+LCS_MLP_WIDTH = 256
+LCS_MLP_HIDDEN = 4
+LCS_MLP_PARAMS = 231171
+LCS_MLP_BF16 = 458752
+
+
+class lcs_mlp_t(C.Structure):
+    _fields_ = [("freq", C.c_void_p), ("in_shift", C.c_float * 4), ("in_scale", C.c_float * 4),
+                ("out_scale", C.c_float), ("reserved", C.c_uint32), ("params", C.c_void_p),
+                ("params_bf16", C.c_void_p)]
+
+
+class Mlp:
+    """Device-resident surrogate: FP32 master parameters, BF16 copies, the
+    feature frequencies and the ``lcs_mlp_t`` describing them."""
+
+    def __init__(self, params, freq, in_shift, in_scale, out_scale, device="cuda"):
+        torch = _torch()
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(device).contiguous()
+        self.freq = torch.as_tensor(np.asarray(freq, dtype=np.float32)).to(device).contiguous()
+        if self.params.numel() != LCS_MLP_PARAMS or tuple(self.freq.shape) != (LCS_MLP_FREQ, 4):
+            raise ValueError("parameter vector or frequency matrix has the wrong size")
+        self.bf16 = torch.empty(LCS_MLP_BF16, dtype=torch.int16, device=device)
+        d = lcs_mlp_t()
+        d.freq = self.freq.data_ptr()
+        for a in range(4):
+            d.in_shift[a] = float(in_shift[a])
+            d.in_scale[a] = float(in_scale[a])
+        d.out_scale = float(out_scale)
+        d.reserved = 0
+        d.params = self.params.data_ptr()
+        d.params_bf16 = self.bf16.data_ptr()
+        self.desc = d
+        self.refresh()
+
+    @property
+    def ref(self):
+        return C.byref(self.desc)
+
+    def refresh(self, stream=None):
+        lcs_mlp_refresh_bf16(self.params, self.bf16, stream=stream)
+
+
+def lcs_mlp_workspace_bytes(batch: int, training: bool) -> int:
+    return int(_lib.lcs_mlp_workspace_bytes(int(batch), 1 if training else 0))
+
+
+def lcs_mlp_backward_scratch_bytes(batch: int) -> int:
+    return int(_lib.lcs_mlp_backward_scratch_bytes(int(batch)))
+
+
+def lcs_mlp_refresh_bf16(params, params_bf16, stream=None):
+    _check(_lib.lcs_mlp_refresh_bf16(_ptr(params), _ptr(params_bf16), _stream_handle(stream)))
+
+
+def _bytes_buffer(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 16), dtype=torch.uint8, device=device)
+
+
+def lcs_mlp_forward(mlp: Mlp, xt, dx=None, workspace=None, training=False, stream=None):
+    """dx [3, B] f32 for inputs xt [4, B] f32 (rows x, y, z, t)."""
+    torch = _torch()
+    B = int(xt.shape[1])
+    dev = xt.device
+    _need(xt, torch.float32, (4, B), "xt")
+    if dx is None:
+        dx = torch.empty((3, B), dtype=torch.float32, device=dev)
+    _need(dx, torch.float32, (3, B), "dx")
+    need = lcs_mlp_workspace_bytes(B, training)
+    if workspace is None:
+        workspace = _bytes_buffer(need, dev)
+    _check(_lib.lcs_mlp_forward(mlp.ref, _ptr(xt), B, _ptr(dx), _ptr(workspace),
+                                int(workspace.numel() * workspace.element_size()),
+                                1 if training else 0, _stream_handle(stream)))
+    return dx, workspace
+
+
+def lcs_mlp_backward(mlp: Mlp, workspace, ddx, grads=None, scratch=None, stream=None):
+    """Parameter gradient [LCS_MLP_PARAMS] f32 of sum(ddx * dx) for the batch
+    whose training forward filled ``workspace``."""
+    torch = _torch()
+    B = int(ddx.shape[1])
+    dev = ddx.device
+    _need(ddx, torch.float32, (3, B), "ddx")
+    if grads is None:
+        grads = torch.empty(LCS_MLP_PARAMS, dtype=torch.float32, device=dev)
+    _need(grads, torch.float32, (LCS_MLP_PARAMS,), "grads")
+    if scratch is None:
+        scratch = _bytes_buffer(lcs_mlp_backward_scratch_bytes(B), dev)
+    _check(_lib.lcs_mlp_backward(mlp.ref, _ptr(workspace), _ptr(ddx), B, _ptr(grads), _ptr(scratch),
+                                 int(scratch.numel() * scratch.element_size()),
+                                 _stream_handle(stream)))
+    return grads
+
+
+def lcs_mse_grad(pred, target, grad=None, loss=None, want_grad=True, want_loss=True, stream=None):
+    torch = _torch()
+    n = int(pred.numel())
+    if grad is None and want_grad:
+        grad = torch.empty_like(pred)
+    if loss is None and want_loss:
+        loss = torch.empty(1, dtype=torch.float64, device=pred.device)
+    _check(_lib.lcs_mse_grad(_ptr(pred), _ptr(target), n, _ptr(grad), _ptr(loss),
+                             _stream_handle(stream)))
+    return grad, loss
+
+
+def lcs_adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                  stream=None):
+    n = int(params.numel())
+    _check(_lib.lcs_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, float(lr),
+                              float(beta1), float(beta2), float(eps), int(step),
+                              _stream_handle(stream)))
