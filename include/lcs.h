@@ -326,6 +326,41 @@ lcs_status lcs_adam_step(float *params, const float *grads, float *m, float *v, 
                          float lr, float beta1, float beta2, float eps, int32_t step,
                          void *stream);
 
+/* lcs_sub -- out = a - b elementwise ([device] FP32, n values each); used to
+ * form training displacements xf - x0.  Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *stream);
+
+/*
+ * Surrogate flow map of a seed grid (3D): composition, check samples, fallback.
+ *
+ * lcs_surrogate_compose -- x_{k+1} = x_k + dx(x_k, t0 + k tau), k < n_windows,
+ *   from the seeds, with the network of `mlp`; xf [device] FP32 3 x Ns.  The
+ *   seeds are processed in chunks sized to `workspace` (see
+ *   lcs_surrogate_workspace_bytes(chunk)).
+ * lcs_surrogate_check -- check tiles are aligned 16 x 16 x 8 blocks of seeds
+ *   (lcs_check_tile_count of them, x fastest); in each, the seeds with local
+ *   index 0, 100, 200, ... (about 1 %) are advected with plain RK4 from t0
+ *   over T with step dt and compared with xf.  tile_err [device] FP32 = the
+ *   largest Euclidean distance in the tile (+inf if a sample was flagged);
+ *   tile_fail [device] uint8 = (tile_err > tol); *n_fail [device] int32 = the
+ *   number of failing tiles.
+ * lcs_advect_tiles -- plain RK4 (as lcs_advect) for every seed of the tiles
+ *   with tile_fail != 0, written into xf / cell / flags; other seeds untouched.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_TIME_RANGE, LCS_E_SEED_DOMAIN,
+ *   LCS_E_STEP, LCS_E_UNSUPPORTED (2D), LCS_E_HIP.
+ */
+int64_t lcs_surrogate_workspace_bytes(int64_t chunk);
+int64_t lcs_check_tile_count(const lcs_seed_grid_t *seeds);
+lcs_status lcs_surrogate_compose(const lcs_mlp_t *mlp, const lcs_seed_grid_t *seeds, double t0,
+                                 double tau, int32_t n_windows, float *xf, void *workspace,
+                                 int64_t workspace_bytes, void *stream);
+lcs_status lcs_surrogate_check(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                               double T, double dt, const float *xf, float tol, float *tile_err,
+                               uint8_t *tile_fail, int32_t *n_fail, void *stream);
+lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                            double T, double dt, const uint8_t *tile_fail, float *xf,
+                            int64_t *cell, uint8_t *flags, void *stream);
+
 /* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
 lcs_status lcs_sync_status(void *stream);
 

@@ -427,7 +427,114 @@ __global__ __launch_bounds__(256) void advect_points_kernel(AdvectArgs A)
     if (A.flags) A.flags[p] = (uint8_t)fl;
 }
 
+// ---------------------------------------------------------------------------
+// Surrogate check samples and tile fallback (3D).  Check tiles are aligned
+// 16 x 16 x 8 blocks of seeds (2048); within a tile the seeds with local
+// linear index 0, 100, 200, ... (about 1 %) are advected with RK4 over the
+// whole window and compared with the surrogate's positions.
+// ---------------------------------------------------------------------------
+constexpr int kCtX = 16, kCtY = 16, kCtZ = 8, kCtSeeds = kCtX * kCtY * kCtZ, kCtStride = 100;
+constexpr int kCtSamples = (kCtSeeds + kCtStride - 1) / kCtStride;
+
+__global__ __launch_bounds__(256) void clear_check_kernel(float *tile_err, uint8_t *tile_fail,
+                                                          int *n_fail, long long n_tiles)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_tiles) {
+        tile_err[i] = 0.0f;
+        tile_fail[i] = 0;
+    }
+    if (i == 0) *n_fail = 0;
+}
+
+__global__ __launch_bounds__(256) void check_kernel(CheckArgs A)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= A.n_tiles * kCtSamples) return;
+    const long long tile = id / kCtSamples;
+    const int q = (int)(id % kCtSamples) * kCtStride;
+    const int tx = (int)(tile % A.ct[0]);
+    const int ty = (int)((tile / A.ct[0]) % A.ct[1]);
+    const int tz = (int)(tile / ((long long)A.ct[0] * A.ct[1]));
+    int sc[3] = {tx * kCtX + q % kCtX, ty * kCtY + (q / kCtX) % kCtY, tz * kCtZ + q / (kCtX * kCtY)};
+    if (sc[0] >= A.g.sn[0] || sc[1] >= A.g.sn[1] || sc[2] >= A.g.sn[2]) return;
+    const long long s = (long long)sc[0] + (long long)A.g.sn[0] * ((long long)sc[1] +
+                        (long long)A.g.sn[1] * (long long)sc[2]);
+    float xh[3], xl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double x0 = A.g.s_origin[a] + (double)sc[a] * A.g.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+    const uint32_t fl = advect_tracer<3>(A.v, xh, xl, A.t0, A.dt, A.nsteps);
+    float err2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float d = (xh[a] + xl[a]) - A.xf[a * A.ns + s];
+        err2 += d * d;
+    }
+    float err = sqrtf(err2);
+    if (fl || !(err == err)) err = INFINITY;   // a flagged or NaN check sample fails its tile
+    // non-negative floats order like their bit patterns
+    atomicMax(reinterpret_cast<unsigned int *>(A.tile_err) + tile, __float_as_uint(err));
+}
+
+__global__ __launch_bounds__(256) void mark_kernel(const float *tile_err, float tol, uint8_t *tile_fail,
+                                                   int *n_fail, long long n_tiles)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles) return;
+    const bool bad = !(tile_err[i] <= tol);
+    tile_fail[i] = bad ? 1 : 0;
+    if (bad) atomicAdd(n_fail, 1);
+}
+
+// Plain RK4 for every seed of the failing check tiles: a check tile is 8
+// workgroup tiles of 8 x 8 x 4 seeds (2 x 2 x 2).
+__global__ __launch_bounds__(256) void advect_tiles_kernel(AdvectArgs A, const uint8_t *tile_fail,
+                                                           int ct0, int ct1)
+{
+    const long long b = blockIdx.x;
+    const long long tile = b / 8;
+    if (!tile_fail[tile]) return;
+    const int sub = (int)(b % 8);
+    const int tx = (int)(tile % ct0), ty = (int)((tile / ct0) % ct1), tz = (int)(tile / ((long long)ct0 * ct1));
+    const SeedTiling &g = A.g;
+    const int t = threadIdx.x;
+    const int w = t / kWave, l = t % kWave;
+    int sc[3];
+    sc[0] = tx * kCtX + (sub % 2) * 8 + (w % 2) * 4 + l % 4;
+    sc[1] = ty * kCtY + ((sub / 2) % 2) * 8 + (w / 2) * 4 + (l / 4) % 4;
+    sc[2] = tz * kCtZ + (sub / 4) * 4 + l / 16;
+    if (sc[0] >= g.sn[0] || sc[1] >= g.sn[1] || sc[2] >= g.sn[2]) return;
+    const long long s = (long long)sc[0] + (long long)g.sn[0] * ((long long)sc[1] +
+                        (long long)g.sn[1] * (long long)sc[2]);
+    advect_seed<3>(A.v, g, sc, s, A.t0, A.dt, A.nsteps, A.ns, A.xf, A.cell, A.flags);
+}
+
 }  // namespace
+
+hipError_t launch_surrogate_check(const CheckArgs &a, float tol, uint8_t *tile_fail, int *n_fail,
+                                  hipStream_t s)
+{
+    const unsigned nb = (unsigned)((a.n_tiles + 255) / 256);
+    hipLaunchKernelGGL(clear_check_kernel, dim3(nb), dim3(256), 0, s, a.tile_err, tile_fail, n_fail,
+                       a.n_tiles);
+    const long long work = a.n_tiles * kCtSamples;
+    hipLaunchKernelGGL(check_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mark_kernel, dim3(nb), dim3(256), 0, s, a.tile_err, tol, tile_fail, n_fail,
+                       a.n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_tiles(const AdvectArgs &a, const uint8_t *tile_fail, int ct0, int ct1,
+                               long long n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(advect_tiles_kernel, dim3((unsigned)(n_tiles * 8)), dim3(256), 0, s, a,
+                       tile_fail, ct0, ct1);
+    return hipGetLastError();
+}
 
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s)
 {

@@ -188,6 +188,18 @@ lcs::SeedTiling make_tiling(const lcs_seed_grid_t *g)
 
 }  // namespace
 
+namespace lcs {
+lcs_status validate_velocity(const lcs_velocity_t *v) { return check_velocity(v); }
+lcs_status validate_seeds(const lcs_seed_grid_t *g, int dim) { return check_seeds(g, dim); }
+lcs_status validate_steps(double T, double dt, int *nsteps) { return check_steps(T, dt, nsteps); }
+lcs_status validate_seed_domain(const lcs_velocity_t *v, const lcs_seed_grid_t *g)
+{
+    return check_seed_domain(v, g);
+}
+VelDev velocity_dev(const lcs_velocity_t *v) { return make_vel(v); }
+SeedTiling seed_tiling(const lcs_seed_grid_t *g) { return make_tiling(g); }
+}  // namespace lcs
+
 // Plan: device state owned by the library for batched launches -- the work
 // counter, a capture stream (default priority) and the instantiated graph of
 // (counter reset + persistent kernel) together with the key it was captured

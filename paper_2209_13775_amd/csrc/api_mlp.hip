@@ -85,9 +85,164 @@ Ws carve(void *ws, long long B, bool training)
     return w;
 }
 
+// surrogate composition workspace: x (3 x M), xt (4 x M), dx (3 x M) FP32,
+// then the inference activations of a batch of M
+long long compose_bytes(long long M) { return 4LL * 10 * M + 256 + ws_bytes(M, false); }
+
+long long check_tiles(const lcs_seed_grid_t *g, int *ct)
+{
+    long long n = 1;
+    for (int a = 0; a < 3; ++a) {
+        ct[a] = (int)((g->n[a] + lcs::kCheckTile[a] - 1) / lcs::kCheckTile[a]);
+        n *= ct[a];
+    }
+    return n;
+}
+
+lcs_status check_window(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0, double T,
+                        double dt, int *nsteps)
+{
+    lcs_status st;
+    if ((st = lcs::validate_velocity(vel)) != LCS_OK) return st;
+    if (vel->dim != 3) return lcs::set_error(LCS_E_UNSUPPORTED, "the surrogate path is 3D only");
+    if ((st = lcs::validate_seeds(seeds, 3)) != LCS_OK) return st;
+    if ((st = lcs::validate_steps(T, dt, nsteps)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t0 + T >= vel->t_first &&
+          t0 + T <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span", t0, t0 + T);
+    return lcs::validate_seed_domain(vel, seeds);
+}
+
 }  // namespace
 
 extern "C" {
+
+lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *stream)
+{
+    if (!a || !b || !out) return lcs::set_error(LCS_E_ARG, "NULL buffer");
+    if (n < 1) return lcs::set_error(LCS_E_SHAPE, "n must be positive");
+    hipError_t e = lcs::launch_sub(a, b, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "sub launch");
+    return lcs::clear_error();
+}
+
+int64_t lcs_surrogate_workspace_bytes(int64_t chunk) { return chunk > 0 ? compose_bytes(chunk) : 0; }
+
+int64_t lcs_check_tile_count(const lcs_seed_grid_t *seeds)
+{
+    if (!seeds) return 0;
+    int ct[3];
+    return check_tiles(seeds, ct);
+}
+
+lcs_status lcs_surrogate_compose(const lcs_mlp_t *mlp, const lcs_seed_grid_t *seeds, double t0,
+                                 double tau, int32_t n_windows, float *xf, void *workspace,
+                                 int64_t workspace_bytes, void *stream)
+{
+    lcs_status st;
+    if ((st = check_mlp(mlp)) != LCS_OK) return st;
+    if ((st = lcs::validate_seeds(seeds, 3)) != LCS_OK) return st;
+    if (!xf || !workspace) return lcs::set_error(LCS_E_ARG, "xf and workspace must not be NULL");
+    if (n_windows < 1 || !isfinite(tau) || tau == 0.0 || !isfinite(t0))
+        return lcs::set_error(LCS_E_ARG, "need n_windows >= 1 and finite non-zero tau");
+    // largest chunk whose buffers fit the workspace (compose_bytes is affine in M)
+    const long long per = compose_bytes(2) - compose_bytes(1);
+    long long M = (workspace_bytes - compose_bytes(0)) / per;
+    if (M < 1) return lcs::set_error(LCS_E_SHAPE, "workspace too small for one sample");
+    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    if (M > ns) M = ns;
+    if (M >= 128) M = M / 128 * 128;
+    hipStream_t s = (hipStream_t)stream;
+    const lcs::SeedTiling g = lcs::seed_tiling(seeds);
+    const lcs::MlpDev P = make_dev(mlp);
+    float *x = static_cast<float *>(workspace);
+    float *xt = x + 3 * M;
+    float *dx = xt + 4 * M;
+    uintptr_t a = reinterpret_cast<uintptr_t>(dx + 3 * M);
+    void *act = reinterpret_cast<void *>((a + 255) & ~(uintptr_t)255);
+    const Ws w = carve(act, M, false);
+    hipError_t e = hipSuccess;
+    for (long long s0 = 0; s0 < ns && e == hipSuccess; s0 += M) {
+        const long long m = (ns - s0 < M) ? ns - s0 : M;
+        e = lcs::launch_seed_xt(g, s0, m, x, s);
+        for (int k = 0; k < n_windows && e == hipSuccess; ++k) {
+            e = lcs::launch_make_xt(x, m, (float)(t0 + k * tau), xt, s);
+            if (e == hipSuccess) e = lcs::launch_features(P, xt, m, w.H0, s);
+            for (int l = 0; l < lcs::kMlpHidden && e == hipSuccess; ++l) {
+                lcs::GemmArgs ga;
+                memset(&ga, 0, sizeof(ga));
+                ga.A = w.H[l];
+                ga.Bt = P.wbf + lcs::mlp_off_bf16(l) + (long long)lcs::mlp_in_width(l) * lcs::kMlpWidth;
+                ga.M = m;
+                ga.N = lcs::kMlpWidth;
+                ga.K = lcs::mlp_in_width(l);
+                ga.bias = P.params + lcs::mlp_off_b(l);
+                ga.H = w.H[l + 1];
+                e = lcs::launch_gemm(ga, false, s);
+            }
+            if (e == hipSuccess) e = lcs::launch_head_fwd(P, w.H[lcs::kMlpHidden], m, dx, s);
+            if (e == hipSuccess) e = lcs::launch_add_dx(x, dx, m, s);
+        }
+        if (e == hipSuccess) e = lcs::launch_store_xf(x, m, s0, ns, xf, s);
+    }
+    if (e != hipSuccess) return lcs::hip_error(e, "surrogate compose launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_surrogate_check(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                               double T, double dt, const float *xf, float tol, float *tile_err,
+                               uint8_t *tile_fail, int32_t *n_fail, void *stream)
+{
+    int nsteps = 0;
+    lcs_status st = check_window(vel, seeds, t0, T, dt, &nsteps);
+    if (st != LCS_OK) return st;
+    if (!xf || !tile_err || !tile_fail || !n_fail)
+        return lcs::set_error(LCS_E_ARG, "xf, tile_err, tile_fail and n_fail must not be NULL");
+    if (!(tol >= 0.0f)) return lcs::set_error(LCS_E_ARG, "tol must be >= 0");
+    lcs::CheckArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = lcs::velocity_dev(vel);
+    A.g = lcs::seed_tiling(seeds);
+    A.t0 = t0;
+    A.dt = dt;
+    A.nsteps = nsteps;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.xf = xf;
+    A.tile_err = tile_err;
+    A.n_tiles = check_tiles(seeds, A.ct);
+    hipError_t e = lcs::launch_surrogate_check(A, tol, tile_fail, n_fail, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "surrogate check launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0, double T,
+                            double dt, const uint8_t *tile_fail, float *xf, int64_t *cell,
+                            uint8_t *flags, void *stream)
+{
+    int nsteps = 0;
+    lcs_status st = check_window(vel, seeds, t0, T, dt, &nsteps);
+    if (st != LCS_OK) return st;
+    if (!tile_fail || !xf) return lcs::set_error(LCS_E_ARG, "tile_fail and xf must not be NULL");
+    lcs::AdvectArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = lcs::velocity_dev(vel);
+    A.g = lcs::seed_tiling(seeds);
+    A.t0 = t0;
+    A.dt = dt;
+    A.nsteps = nsteps;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+    int ct[3];
+    const long long nt = check_tiles(seeds, ct);
+    if (nt * 8 > 2147483647LL) return lcs::set_error(LCS_E_SHAPE, "too many tiles");
+    hipError_t e = lcs::launch_advect_tiles(A, tile_fail, ct[0], ct[1], nt, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_tiles launch");
+    return lcs::clear_error();
+}
+
 
 int64_t lcs_mlp_workspace_bytes(int64_t batch, int32_t training)
 {

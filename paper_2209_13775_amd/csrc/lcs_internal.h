@@ -194,6 +194,40 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n
                        hipStream_t s);
 hipError_t launch_refresh_bf16(const float *params, uint16_t *out, hipStream_t s);
 
+// Surrogate check samples (3D): tiles of 16 x 16 x 8 seeds.
+constexpr int kCheckTile[3] = {16, 16, 8};
+
+struct CheckArgs {
+    VelDev v;
+    SeedTiling g;             // only sn, s_origin, s_spacing are used
+    double t0, dt;
+    int nsteps;
+    long long ns;
+    const float *xf;          // surrogate positions, 3 x ns
+    float *tile_err;          // per check tile
+    long long n_tiles;
+    int ct[3];                // check tiles per axis
+};
+
+hipError_t launch_surrogate_check(const CheckArgs &a, float tol, uint8_t *tile_fail, int *n_fail,
+                                  hipStream_t s);
+hipError_t launch_advect_tiles(const AdvectArgs &a, const uint8_t *tile_fail, int ct0, int ct1,
+                               long long n_tiles, hipStream_t s);
+hipError_t launch_sub(const float *a, const float *b, long long n, float *out, hipStream_t s);
+hipError_t launch_seed_xt(const SeedTiling &g, long long s0, long long M, float *x, hipStream_t s);
+hipError_t launch_make_xt(const float *x, long long M, float t, float *xt, hipStream_t s);
+hipError_t launch_add_dx(float *x, const float *dx, long long M, hipStream_t s);
+hipError_t launch_store_xf(const float *x, long long M, long long s0, long long ns, float *xf,
+                           hipStream_t s);
+
+// host-side validation and descriptor conversion (api.hip)
+lcs_status validate_velocity(const lcs_velocity_t *v);
+lcs_status validate_seeds(const lcs_seed_grid_t *g, int dim);
+lcs_status validate_steps(double T, double dt, int *nsteps);
+lcs_status validate_seed_domain(const lcs_velocity_t *v, const lcs_seed_grid_t *g);
+VelDev velocity_dev(const lcs_velocity_t *v);
+SeedTiling seed_tiling(const lcs_seed_grid_t *g);
+
 // error reporting shared by the ABI translation units
 lcs_status set_error(lcs_status st, const char *fmt, ...);
 lcs_status clear_error();

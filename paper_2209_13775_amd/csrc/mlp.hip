@@ -378,7 +378,89 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
     out[mlp_off_bf16(l) + (long long)K * kMlpWidth + (long long)n * K + k] = b;   // [N][K]
 }
 
+// ---------------------------------------------------------------------------
+// Composition helpers: seeds of a chunk of linear indices, (x, t) inputs,
+// x += dx, and the final store in natural seed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void seed_xt_kernel(SeedTiling g, long long s0, long long M,
+                                                      float *__restrict__ x)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const long long s = s0 + i;
+    const long long c[3] = {s % g.sn[0], (s / g.sn[0]) % g.sn[1], s / ((long long)g.sn[0] * g.sn[1])};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a * M + i] = (float)(g.s_origin[a] + (double)c[a] * g.s_spacing[a]);
+}
+
+__global__ __launch_bounds__(256) void make_xt_kernel(const float *__restrict__ x, long long M, float t,
+                                                      float *__restrict__ xt)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    xt[i] = x[i];
+    xt[M + i] = x[M + i];
+    xt[2 * M + i] = x[2 * M + i];
+    xt[3 * M + i] = t;
+}
+
+__global__ __launch_bounds__(256) void add_dx_kernel(float *__restrict__ x, const float *__restrict__ dx,
+                                                     long long M)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * M) return;
+    x[i] += dx[i];
+}
+
+__global__ __launch_bounds__(256) void store_xf_kernel(const float *__restrict__ x, long long M,
+                                                       long long s0, long long ns, float *__restrict__ xf)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xf[a * ns + s0 + i] = x[a * M + i];
+}
+
+__global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a, const float *__restrict__ b,
+                                                  long long n, float *__restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] - b[i];
+}
+
 }  // namespace
+
+hipError_t launch_sub(const float *a, const float *b, long long n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sub_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_xt(const SeedTiling &g, long long s0, long long M, float *x, hipStream_t s)
+{
+    hipLaunchKernelGGL(seed_xt_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, g, s0, M, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_xt(const float *x, long long M, float t, float *xt, hipStream_t s)
+{
+    hipLaunchKernelGGL(make_xt_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, M, t, xt);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_dx(float *x, const float *dx, long long M, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_dx_kernel, dim3((unsigned)((3 * M + 255) / 256)), dim3(256), 0, s, x, dx, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_xf(const float *x, long long M, long long s0, long long ns, float *xf,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(store_xf_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, M, s0, ns,
+                       xf);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Launchers

@@ -85,6 +85,10 @@ def _load(path: str = LIB_PATH):
         "lcs_mlp_backward": [P, P, P, I64, P, P, I64, P],
         "lcs_mse_grad": [P, P, I64, P, P, P],
         "lcs_adam_step": [P, P, P, P, I64, C.c_float, C.c_float, C.c_float, C.c_float, I32, P],
+        "lcs_surrogate_compose": [P, P, D, D, I32, P, P, I64, P],
+        "lcs_surrogate_check": [P, P, D, D, D, P, C.c_float, P, P, P, P],
+        "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
+        "lcs_sub": [P, P, I64, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -98,6 +102,10 @@ def _load(path: str = LIB_PATH):
         fn = getattr(L, name)
         fn.restype = C.c_int64
     L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
+    L.lcs_surrogate_workspace_bytes.restype = C.c_int64
+    L.lcs_surrogate_workspace_bytes.argtypes = [I64]
+    L.lcs_check_tile_count.restype = C.c_int64
+    L.lcs_check_tile_count.argtypes = [P]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
     return L
 
@@ -513,3 +521,80 @@ def lcs_adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, ep
     _check(_lib.lcs_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, float(lr),
                               float(beta1), float(beta2), float(eps), int(step),
                               _stream_handle(stream)))
+
+
+def lcs_surrogate_workspace_bytes(chunk: int) -> int:
+    return int(_lib.lcs_surrogate_workspace_bytes(int(chunk)))
+
+
+def lcs_check_tile_count(seeds) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_check_tile_count(C.byref(sd)))
+
+
+def lcs_surrogate_compose(mlp: Mlp, seeds, t0: float, tau: float, n_windows: int, xf=None,
+                          workspace=None, chunk: int = 1 << 22, stream=None):
+    """Surrogate flow map of the seed grid: n_windows composed windows of tau."""
+    torch = _torch()
+    dev = mlp.params.device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    if xf is None:
+        xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
+    _need(xf, torch.float32, (3, ns), "xf")
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_surrogate_workspace_bytes(min(chunk, ns)), dev)
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_surrogate_compose(mlp.ref, C.byref(sd), float(t0), float(tau), int(n_windows),
+                                      _ptr(xf), _ptr(workspace),
+                                      int(workspace.numel() * workspace.element_size()),
+                                      _stream_handle(stream)))
+    return xf
+
+
+def lcs_surrogate_check(frames: DeviceFrames, seeds, t0: float, T: float, dt: float, xf, tol: float,
+                        tile_err=None, tile_fail=None, n_fail=None, stream=None):
+    """Per-tile check-sample error of a surrogate flow map and the failing tiles."""
+    torch = _torch()
+    dev = xf.device
+    nt = lcs_check_tile_count(seeds)
+    if tile_err is None:
+        tile_err = torch.empty(nt, dtype=torch.float32, device=dev)
+    if tile_fail is None:
+        tile_fail = torch.empty(nt, dtype=torch.uint8, device=dev)
+    if n_fail is None:
+        n_fail = torch.empty(1, dtype=torch.int32, device=dev)
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    _need(xf, torch.float32, (3, ns), "xf")
+    _need(tile_err, torch.float32, (nt,), "tile_err")
+    _need(tile_fail, torch.uint8, (nt,), "tile_fail")
+    _need(n_fail, torch.int32, (1,), "n_fail")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_surrogate_check(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                                    _ptr(xf), float(tol), _ptr(tile_err), _ptr(tile_fail),
+                                    _ptr(n_fail), _stream_handle(stream)))
+    return tile_err, tile_fail, n_fail
+
+
+def lcs_advect_tiles(frames: DeviceFrames, seeds, t0: float, T: float, dt: float, tile_fail, xf,
+                     cell=None, flags=None, stream=None):
+    torch = _torch()
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    _need(xf, torch.float32, (3, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_tiles(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                                 _ptr(tile_fail), _ptr(xf), _ptr(cell), _ptr(flags),
+                                 _stream_handle(stream)))
+    return xf
+
+
+def lcs_sub(a, b, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(a)
+    _need(a, torch.float32, tuple(a.shape), "a")
+    _need(b, torch.float32, tuple(a.shape), "b")
+    _need(out, torch.float32, tuple(a.shape), "out")
+    _check(_lib.lcs_sub(_ptr(a), _ptr(b), int(a.numel()), _ptr(out), _stream_handle(stream)))
+    return out
