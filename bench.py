@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the oracle sample")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched-window and random-Fourier workloads")
+                    help="skip the batched-window, random-Fourier and surrogate workloads")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -137,7 +138,7 @@ def bench_batched(torch, lcs, inputs, reps=3):
     return out
 
 
-def bench_random_fourier(torch, lcs, inputs, reps=2):
+def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     """Divergence-free random-Fourier field, 256^3 x 65 FP32 frames, 512x512x256
     seeds, forward and backward FTLE from t0 = 4 with |T| = 4, dt = 0.01."""
     fs = inputs.random_fourier_frames(n=256, n_frames=65, dt_frame=0.125, device="cuda")
@@ -154,8 +155,6 @@ def bench_random_fourier(torch, lcs, inputs, reps=2):
     stream = torch.cuda.current_stream()
     res = {}
     for T, dt in [(4.0, 0.01), (-4.0, -0.01)]:
-        lcs.lcs_advect(frames, g, 4.0, T, dt, xf, None, flags, want_cell=False, stream=stream)
-        torch.cuda.synchronize()
         ta, tc = [], []
         for _ in range(reps):
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -170,6 +169,9 @@ def bench_random_fourier(torch, lcs, inputs, reps=2):
             tc.append(e[1].elapsed_time(e[2]))
         res["forward" if T > 0 else "backward"] = (float(np.median(ta)), float(np.median(tc)),
                                                    float(sig.mean().item()))
+        if T > 0 and keep is not None:
+            keep.update(fs=fs, frames=frames, seeds=g, ref_ftle=sig.clone(),
+                        rk4_ms=float(np.median(ta)) + float(np.median(tc)))
     lcs.lcs_sync_status()
     nsteps = 400
     steps = 2 * ns * nsteps
@@ -185,6 +187,74 @@ def bench_random_fourier(torch, lcs, inputs, reps=2):
                          "achieved": 768 * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": 768 * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "bytes_per_unit": 768, "unit_of_work": "3D tracer-RK4-step"}}
+
+
+def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
+    """Learned flow-map surrogate on the random-Fourier field: train on RK4
+    displacements over tau = 0.5 (x0 uniform on the torus, t0 in {4, 4.5, ..,
+    7.5}), compose 8 windows for the forward T = 4 FTLE of the 512x512x256
+    seeds, check 1 % of each 16x16x8 tile against RK4 (tolerance 1e-3) and
+    re-advect failing tiles with RK4.  Compared with plain RK4 (dt = 0.01) and
+    with plain RK4 at coarser steps."""
+    from paper_2209_13775_amd import surrogate as S
+    frames, g, ref = keep["frames"], keep["seeds"], keep["ref_ftle"]
+    T = 4.0
+    cfg = S.SurrogateConfig(tau=0.5, n_windows=8, t0=4.0, dt=0.01, sigma_x=4.0, sigma_t=1.0)
+    mlp = S.new_model(cfg)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    xt, dx, _ = S.training_data(frames, cfg, n_train, seed=1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    data_ms = e0.elapsed_time(e1)
+    vxt, vdx, _ = S.training_data(frames, cfg, 1 << 16, seed=2)
+    base = S.evaluate(mlp, vxt, vdx)
+    log = S.train(mlp, xt, dx, epochs=epochs, batch=65536, lr=2e-3, val=(vxt, vdx))
+    del xt, dx
+    e0.record(stream)
+    comp = lcs.lcs_surrogate_compose(mlp, g, cfg.t0, cfg.tau, cfg.n_windows, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    compose_ms = e0.elapsed_time(e1)
+    flop = 2.0 * 230144 * g.count * cfg.n_windows    # 2 x multiply-adds of all layers
+    del comp
+    e0.record(stream)
+    xf, flags, n_fail, err = S.surrogate_flowmap(mlp, frames, g, cfg, 1e-3, stream=stream)
+    _, sig, _ = lcs.lcs_cg_ftle(g, xf, T, flags=flags, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    path_ms = e0.elapsed_time(e1)
+    e = (sig - ref).abs()
+    nt = lcs.lcs_check_tile_count(g)
+    out = {"workload": "surrogate_on_random_fourier_256cubed_seeds512x512x256",
+           "train_samples": n_train, "train_epochs": epochs, "train_steps": log.steps,
+           "train_seconds": log.seconds, "data_ms": data_ms,
+           "val_mse_before": base, "val_mse_after": log.val_loss,
+           "compose_ms": compose_ms,
+           "compose_tflops": flop / (compose_ms * 1e-3) / 1e12,
+           "compose_mfma_frac": flop / (compose_ms * 1e-3) / 2.5e15,
+           "check_tolerance": 1e-3, "fallback_tiles": int(n_fail.item()), "tiles": nt,
+           "fallback_fraction": int(n_fail.item()) / nt,
+           "tile_err_median": float(err.median().item()),
+           "surrogate_path_ms": path_ms, "rk4_ms": keep["rk4_ms"],
+           "speedup_vs_rk4": keep["rk4_ms"] / path_ms,
+           "ftle_err_mean": float(e.mean().item()), "ftle_err_max": float(e.max().item())}
+    del xf, flags, sig
+    curve = []
+    for dtc in [0.02, 0.05, 0.1, 0.25]:
+        e0.record(stream)
+        xc, _, fc = lcs.lcs_advect(frames, g, cfg.t0, T, dtc, want_cell=False, stream=stream)
+        _, sc, _ = lcs.lcs_cg_ftle(g, xc, T, flags=fc, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ec = (sc - ref).abs()
+        curve.append({"dt": dtc, "ms": e0.elapsed_time(e1), "ftle_err_mean": float(ec.mean().item()),
+                      "ftle_err_max": float(ec.max().item())})
+        del xc, fc, sc
+    out["coarse_rk4"] = curve
+    return out
 
 
 def main():
@@ -295,7 +365,13 @@ def main():
         extra = {"batched": bench_batched(torch, lcs, inputs)}
         torch.cuda.empty_cache()
         print("bench: random-Fourier forward/backward", file=sys.stderr, flush=True)
-        extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs)
+        keep = {}
+        extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs, keep=keep)
+        torch.cuda.empty_cache()
+        if not args.no_surrogate:
+            print("bench: surrogate (train, compose, check, fallback)", file=sys.stderr, flush=True)
+            extra["surrogate"] = bench_surrogate(torch, lcs, keep)
+        keep.clear()
         torch.cuda.empty_cache()
         out["extra_workloads"] = extra
     if not args.no_cpu_baseline:

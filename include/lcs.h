@@ -304,8 +304,9 @@ lcs_status lcs_mlp_forward(const lcs_mlp_t *mlp, const float *xt, int64_t batch,
 
 /* lcs_mlp_backward -- grads [device] FP32 LCS_MLP_PARAMS (same layout as the
  * masters) = gradient of sum(ddx * dx) for the batch whose training forward
- * filled `workspace`; ddx [device] FP32 3 x batch.  Weight gradients are summed
- * over fixed 2048-row chunks in a fixed order (deterministic).  scratch
+ * filled `workspace`; ddx [device] FP32 3 x batch.  Gradients are summed over
+ * fixed row chunks (2048 rows for hidden weights, 128 for biases and the head)
+ * and the chunks in a fixed order (deterministic).  scratch
  * [device] of at least lcs_mlp_backward_scratch_bytes(batch) bytes.
  * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
 lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const float *ddx,
@@ -334,9 +335,9 @@ lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *
  * Surrogate flow map of a seed grid (3D): composition, check samples, fallback.
  *
  * lcs_surrogate_compose -- x_{k+1} = x_k + dx(x_k, t0 + k tau), k < n_windows,
- *   from the seeds, with the network of `mlp`; xf [device] FP32 3 x Ns.  The
- *   seeds are processed in chunks sized to `workspace` (see
- *   lcs_surrogate_workspace_bytes(chunk)).
+ *   from the seeds, with the network of `mlp`; xf [device] FP32 3 x Ns.  One
+ *   launch: each workgroup keeps 128 seeds' activations in LDS through every
+ *   window (features, the four MFMA layers, head, update).
  * lcs_surrogate_check -- check tiles are aligned 16 x 16 x 8 blocks of seeds
  *   (lcs_check_tile_count of them, x fastest); in each, the seeds with local
  *   index 0, 100, 200, ... (about 1 %) are advected with plain RK4 from t0
@@ -349,11 +350,9 @@ lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *
  * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_TIME_RANGE, LCS_E_SEED_DOMAIN,
  *   LCS_E_STEP, LCS_E_UNSUPPORTED (2D), LCS_E_HIP.
  */
-int64_t lcs_surrogate_workspace_bytes(int64_t chunk);
 int64_t lcs_check_tile_count(const lcs_seed_grid_t *seeds);
 lcs_status lcs_surrogate_compose(const lcs_mlp_t *mlp, const lcs_seed_grid_t *seeds, double t0,
-                                 double tau, int32_t n_windows, float *xf, void *workspace,
-                                 int64_t workspace_bytes, void *stream);
+                                 double tau, int32_t n_windows, float *xf, void *stream);
 lcs_status lcs_surrogate_check(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
                                double T, double dt, const float *xf, float tol, float *tile_err,
                                uint8_t *tile_fail, int32_t *n_fail, void *stream);

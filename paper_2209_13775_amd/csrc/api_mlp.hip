@@ -10,8 +10,10 @@
 namespace {
 
 constexpr long long kChunk = 2048;   // rows per partial sum of a weight gradient
+constexpr long long kBChunk = 128;   // rows per partial sum of a bias / head gradient
 
 long long nchunks(long long B) { return (B + kChunk - 1) / kChunk; }
+long long nbchunks(long long B) { return (B + kBChunk - 1) / kBChunk; }
 
 // training workspace (BF16): H0 [B][128], then (Z_l, H_l) [B][256] for l = 1..4
 // inference workspace (BF16): H0 [B][128], Ha [B][256], Hb [B][256]
@@ -24,9 +26,9 @@ long long ws_bytes(long long B, bool training)
 
 long long scratch_bytes(long long B)
 {
-    const long long nc = nchunks(B);
+    const long long nc = nchunks(B), nb = nbchunks(B);
     const long long part = (long long)lcs::kMlpWidth * lcs::kMlpWidth;
-    return 2LL * 2 * B * lcs::kMlpWidth + 4LL * nc * (part + lcs::kMlpWidth + lcs::kHeadPart + 64);
+    return 2LL * 2 * B * lcs::kMlpWidth + 4LL * (nc * part + nb * (lcs::kMlpWidth + lcs::kHeadPart) + 64);
 }
 
 lcs_status check_mlp(const lcs_mlp_t *m)
@@ -85,10 +87,6 @@ Ws carve(void *ws, long long B, bool training)
     return w;
 }
 
-// surrogate composition workspace: x (3 x M), xt (4 x M), dx (3 x M) FP32,
-// then the inference activations of a batch of M
-long long compose_bytes(long long M) { return 4LL * 10 * M + 256 + ws_bytes(M, false); }
-
 long long check_tiles(const lcs_seed_grid_t *g, int *ct)
 {
     long long n = 1;
@@ -127,8 +125,6 @@ lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *
     return lcs::clear_error();
 }
 
-int64_t lcs_surrogate_workspace_bytes(int64_t chunk) { return chunk > 0 ? compose_bytes(chunk) : 0; }
-
 int64_t lcs_check_tile_count(const lcs_seed_grid_t *seeds)
 {
     if (!seeds) return 0;
@@ -137,55 +133,24 @@ int64_t lcs_check_tile_count(const lcs_seed_grid_t *seeds)
 }
 
 lcs_status lcs_surrogate_compose(const lcs_mlp_t *mlp, const lcs_seed_grid_t *seeds, double t0,
-                                 double tau, int32_t n_windows, float *xf, void *workspace,
-                                 int64_t workspace_bytes, void *stream)
+                                 double tau, int32_t n_windows, float *xf, void *stream)
 {
     lcs_status st;
     if ((st = check_mlp(mlp)) != LCS_OK) return st;
     if ((st = lcs::validate_seeds(seeds, 3)) != LCS_OK) return st;
-    if (!xf || !workspace) return lcs::set_error(LCS_E_ARG, "xf and workspace must not be NULL");
+    if (!xf) return lcs::set_error(LCS_E_ARG, "xf must not be NULL");
     if (n_windows < 1 || !isfinite(tau) || tau == 0.0 || !isfinite(t0))
         return lcs::set_error(LCS_E_ARG, "need n_windows >= 1 and finite non-zero tau");
-    // largest chunk whose buffers fit the workspace (compose_bytes is affine in M)
-    const long long per = compose_bytes(2) - compose_bytes(1);
-    long long M = (workspace_bytes - compose_bytes(0)) / per;
-    if (M < 1) return lcs::set_error(LCS_E_SHAPE, "workspace too small for one sample");
-    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
-    if (M > ns) M = ns;
-    if (M >= 128) M = M / 128 * 128;
-    hipStream_t s = (hipStream_t)stream;
-    const lcs::SeedTiling g = lcs::seed_tiling(seeds);
-    const lcs::MlpDev P = make_dev(mlp);
-    float *x = static_cast<float *>(workspace);
-    float *xt = x + 3 * M;
-    float *dx = xt + 4 * M;
-    uintptr_t a = reinterpret_cast<uintptr_t>(dx + 3 * M);
-    void *act = reinterpret_cast<void *>((a + 255) & ~(uintptr_t)255);
-    const Ws w = carve(act, M, false);
-    hipError_t e = hipSuccess;
-    for (long long s0 = 0; s0 < ns && e == hipSuccess; s0 += M) {
-        const long long m = (ns - s0 < M) ? ns - s0 : M;
-        e = lcs::launch_seed_xt(g, s0, m, x, s);
-        for (int k = 0; k < n_windows && e == hipSuccess; ++k) {
-            e = lcs::launch_make_xt(x, m, (float)(t0 + k * tau), xt, s);
-            if (e == hipSuccess) e = lcs::launch_features(P, xt, m, w.H0, s);
-            for (int l = 0; l < lcs::kMlpHidden && e == hipSuccess; ++l) {
-                lcs::GemmArgs ga;
-                memset(&ga, 0, sizeof(ga));
-                ga.A = w.H[l];
-                ga.Bt = P.wbf + lcs::mlp_off_bf16(l) + (long long)lcs::mlp_in_width(l) * lcs::kMlpWidth;
-                ga.M = m;
-                ga.N = lcs::kMlpWidth;
-                ga.K = lcs::mlp_in_width(l);
-                ga.bias = P.params + lcs::mlp_off_b(l);
-                ga.H = w.H[l + 1];
-                e = lcs::launch_gemm(ga, false, s);
-            }
-            if (e == hipSuccess) e = lcs::launch_head_fwd(P, w.H[lcs::kMlpHidden], m, dx, s);
-            if (e == hipSuccess) e = lcs::launch_add_dx(x, dx, m, s);
-        }
-        if (e == hipSuccess) e = lcs::launch_store_xf(x, m, s0, ns, xf, s);
-    }
+    lcs::ComposeArgs A;
+    memset(&A, 0, sizeof(A));
+    A.P = make_dev(mlp);
+    A.g = lcs::seed_tiling(seeds);
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.t0 = t0;
+    A.tau = tau;
+    A.n_windows = n_windows;
+    A.xf = xf;
+    hipError_t e = lcs::launch_compose_fused(A, (hipStream_t)stream);
     if (e != hipSuccess) return lcs::hip_error(e, "surrogate compose launch");
     return lcs::clear_error();
 }
@@ -306,17 +271,17 @@ lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const f
     hipStream_t s = (hipStream_t)stream;
     const lcs::MlpDev P = make_dev(mlp);
     const Ws w = carve(const_cast<void *>(workspace), batch, true);
-    const long long nc = nchunks(batch);
+    const long long nc = nchunks(batch), nb = nbchunks(batch);
     uint16_t *dA = static_cast<uint16_t *>(scratch);
     uint16_t *dB = dA + batch * lcs::kMlpWidth;
     float *part = reinterpret_cast<float *>(dB + batch * lcs::kMlpWidth);
     float *part_b = part + nc * (long long)lcs::kMlpWidth * lcs::kMlpWidth;
-    float *part_h = part_b + nc * lcs::kMlpWidth;
+    float *part_h = part_b + nb * lcs::kMlpWidth;
 
     hipError_t e = lcs::launch_head_bwd(P, ddx, w.Z[lcs::kMlpHidden], w.H[lcs::kMlpHidden], batch, dA,
-                                        kChunk, (int)nc, part_h, s);
+                                        kBChunk, (int)nb, part_h, s);
     if (e == hipSuccess)
-        e = lcs::launch_reduce_chunks(part_h, (int)nc, lcs::kHeadPart, grads + lcs::kOffWh, s);
+        e = lcs::launch_reduce_chunks(part_h, (int)nb, lcs::kHeadPart, grads + lcs::kOffWh, s);
     uint16_t *cur = dA, *nxt = dB;
     for (int l = lcs::kMlpHidden - 1; l >= 0 && e == hipSuccess; --l) {
         const int K = lcs::mlp_in_width(l);
@@ -332,9 +297,9 @@ lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const f
         if (e == hipSuccess)
             e = lcs::launch_reduce_chunks(part, (int)nc, (long long)K * lcs::kMlpWidth,
                                           grads + lcs::mlp_off_w(l), s);
-        if (e == hipSuccess) e = lcs::launch_colsum(cur, batch, lcs::kMlpWidth, kChunk, (int)nc, part_b, s);
+        if (e == hipSuccess) e = lcs::launch_colsum(cur, batch, lcs::kMlpWidth, kBChunk, (int)nb, part_b, s);
         if (e == hipSuccess)
-            e = lcs::launch_reduce_chunks(part_b, (int)nc, lcs::kMlpWidth, grads + lcs::mlp_off_b(l), s);
+            e = lcs::launch_reduce_chunks(part_b, (int)nb, lcs::kMlpWidth, grads + lcs::mlp_off_b(l), s);
         if (l > 0 && e == hipSuccess) {
             lcs::GemmArgs g;
             memset(&g, 0, sizeof(g));

@@ -213,12 +213,16 @@ hipError_t launch_surrogate_check(const CheckArgs &a, float tol, uint8_t *tile_f
                                   hipStream_t s);
 hipError_t launch_advect_tiles(const AdvectArgs &a, const uint8_t *tile_fail, int ct0, int ct1,
                                long long n_tiles, hipStream_t s);
+struct ComposeArgs {
+    MlpDev P;
+    SeedTiling g;             // sn, s_origin, s_spacing
+    long long ns;
+    double t0, tau;
+    int n_windows;
+    float *xf;
+};
+hipError_t launch_compose_fused(const ComposeArgs &a, hipStream_t s);
 hipError_t launch_sub(const float *a, const float *b, long long n, float *out, hipStream_t s);
-hipError_t launch_seed_xt(const SeedTiling &g, long long s0, long long M, float *x, hipStream_t s);
-hipError_t launch_make_xt(const float *x, long long M, float t, float *xt, hipStream_t s);
-hipError_t launch_add_dx(float *x, const float *dx, long long M, hipStream_t s);
-hipError_t launch_store_xf(const float *x, long long M, long long s0, long long ns, float *xf,
-                           hipStream_t s);
 
 // host-side validation and descriptor conversion (api.hip)
 lcs_status validate_velocity(const lcs_velocity_t *v);

@@ -379,46 +379,122 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Composition helpers: seeds of a chunk of linear indices, (x, t) inputs,
-// x += dx, and the final store in natural seed order.
+// Fused surrogate composition: a workgroup owns 128 consecutive seeds and runs
+// every window for them -- features, the four hidden layers on MFMA and the
+// head -- with the activations resident in LDS; weights stream from L2 as
+// MFMA B fragments.  x_{k+1} = x_k + dx(x_k, t0 + k tau).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void seed_xt_kernel(SeedTiling g, long long s0, long long M,
-                                                      float *__restrict__ x)
+constexpr int kFT = 128;                  // samples per workgroup
+constexpr int kActStride = kMlpWidth + 8; // BF16 per LDS row (16-byte aligned rows)
+
+// tanh-form GELU written as z * sigmoid(2u): z / (1 + exp(-2u))
+__device__ __forceinline__ float gelu_fast(float z)
 {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const long long s = s0 + i;
-    const long long c[3] = {s % g.sn[0], (s / g.sn[0]) % g.sn[1], s / ((long long)g.sn[0] * g.sn[1])};
+    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
+    return z / (1.0f + __expf(-2.0f * u));
+}
+
+__global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t act[kFT * kActStride];
+    __shared__ float xs[3][kFT];
+    const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const long long s0 = (long long)blockIdx.x * kFT;
+    const SeedTiling &g = A.g;
+    if (tid < kFT) {
+        const long long s = min(s0 + tid, A.ns - 1);
+        const long long c[3] = {s % g.sn[0], (s / g.sn[0]) % g.sn[1],
+                                s / ((long long)g.sn[0] * g.sn[1])};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x[a * M + i] = (float)(g.s_origin[a] + (double)c[a] * g.s_spacing[a]);
-}
-
-__global__ __launch_bounds__(256) void make_xt_kernel(const float *__restrict__ x, long long M, float t,
-                                                      float *__restrict__ xt)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    xt[i] = x[i];
-    xt[M + i] = x[M + i];
-    xt[2 * M + i] = x[2 * M + i];
-    xt[3 * M + i] = t;
-}
-
-__global__ __launch_bounds__(256) void add_dx_kernel(float *__restrict__ x, const float *__restrict__ dx,
-                                                     long long M)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3 * M) return;
-    x[i] += dx[i];
-}
-
-__global__ __launch_bounds__(256) void store_xf_kernel(const float *__restrict__ x, long long M,
-                                                       long long s0, long long ns, float *__restrict__ xf)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= M) return;
+        for (int a = 0; a < 3; ++a) xs[a][tid] = (float)(g.s_origin[a] + (double)c[a] * g.s_spacing[a]);
+    }
+    __syncthreads();
+    const MlpDev &P = A.P;
+    const float *Wh = P.params + kOffWh;
+    const float *bh = P.params + kOffBh;
+    for (int k = 0; k < A.n_windows; ++k) {
+        const float tk = (float)(A.t0 + (double)k * A.tau);
+        // features: thread -> (sample m, frequency f), f fastest
+        for (int idx = tid; idx < kFT * kMlpFreq; idx += 256) {
+            const int m = idx / kMlpFreq, f = idx % kMlpFreq;
+            const float v0 = (xs[0][m] - P.in_shift[0]) * P.in_scale[0];
+            const float v1 = (xs[1][m] - P.in_shift[1]) * P.in_scale[1];
+            const float v2 = (xs[2][m] - P.in_shift[2]) * P.in_scale[2];
+            const float v3 = (tk - P.in_shift[3]) * P.in_scale[3];
+            const float *b = P.freq + 4 * f;
+            float sn, cs;
+            sincospif(2.0f * (b[0] * v0 + b[1] * v1 + b[2] * v2 + b[3] * v3), &sn, &cs);
+            act[m * kActStride + f] = f2bf(cs);
+            act[m * kActStride + kMlpFreq + f] = f2bf(sn);
+        }
+        __syncthreads();
+        for (int l = 0; l < kMlpHidden; ++l) {
+            const int K = mlp_in_width(l);
+            const uint16_t *Wt = P.wbf + mlp_off_bf16(l) + (long long)K * kMlpWidth;   // [256][K]
+            const float *bias = P.params + mlp_off_b(l);
+            f32x4 acc[8][4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xf[a * ns + s0 + i] = x[a * M + i];
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+            const int ko = 8 * (lane / 16);
+            for (int kk = 0; kk < K; kk += 32) {
+                bf16x8 bfr[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int n = wave * 64 + 16 * j + lane % 16;
+                    bfr[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
+                        &act[(16 * i + lane % 16) * kActStride + kk + ko]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            __syncthreads();   // every wave has read this layer's input
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = wave * 64 + 16 * j + lane % 16;
+                const float bn = bias[n];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = 16 * i + 4 * (lane / 16) + e;
+                        act[m * kActStride + n] = f2bf(gelu_fast(acc[i][j][e] + bn));
+                    }
+            }
+            __syncthreads();
+        }
+        // head: two lanes per sample, each summing half of the 256 inputs
+        {
+            const int m = tid / 2, h = tid % 2;
+            float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
+            for (int q = h * 128; q < h * 128 + 128; ++q) {
+                const float x = bf2f(act[m * kActStride + q]);
+                y0 += x * Wh[3 * q];
+                y1 += x * Wh[3 * q + 1];
+                y2 += x * Wh[3 * q + 2];
+            }
+            y0 += __shfl_xor(y0, 1, 64);
+            y1 += __shfl_xor(y1, 1, 64);
+            y2 += __shfl_xor(y2, 1, 64);
+            __syncthreads();   // all head reads of act done before the next window's features
+            if (h == 0) {
+                xs[0][m] += P.out_scale * (y0 + bh[0]);
+                xs[1][m] += P.out_scale * (y1 + bh[1]);
+                xs[2][m] += P.out_scale * (y2 + bh[2]);
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < kFT && s0 + tid < A.ns) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.xf[a * A.ns + s0 + tid] = xs[a][tid];
+    }
 }
 
 __global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a, const float *__restrict__ b,
@@ -430,35 +506,15 @@ __global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a, c
 
 }  // namespace
 
+hipError_t launch_compose_fused(const ComposeArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(compose_fused_kernel, dim3((unsigned)((a.ns + kFT - 1) / kFT)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_sub(const float *a, const float *b, long long n, float *out, hipStream_t s)
 {
     hipLaunchKernelGGL(sub_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_seed_xt(const SeedTiling &g, long long s0, long long M, float *x, hipStream_t s)
-{
-    hipLaunchKernelGGL(seed_xt_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, g, s0, M, x);
-    return hipGetLastError();
-}
-
-hipError_t launch_make_xt(const float *x, long long M, float t, float *xt, hipStream_t s)
-{
-    hipLaunchKernelGGL(make_xt_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, M, t, xt);
-    return hipGetLastError();
-}
-
-hipError_t launch_add_dx(float *x, const float *dx, long long M, hipStream_t s)
-{
-    hipLaunchKernelGGL(add_dx_kernel, dim3((unsigned)((3 * M + 255) / 256)), dim3(256), 0, s, x, dx, M);
-    return hipGetLastError();
-}
-
-hipError_t launch_store_xf(const float *x, long long M, long long s0, long long ns, float *xf,
-                           hipStream_t s)
-{
-    hipLaunchKernelGGL(store_xf_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, x, M, s0, ns,
-                       xf);
     return hipGetLastError();
 }
 

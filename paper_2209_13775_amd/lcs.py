@@ -85,7 +85,7 @@ def _load(path: str = LIB_PATH):
         "lcs_mlp_backward": [P, P, P, I64, P, P, I64, P],
         "lcs_mse_grad": [P, P, I64, P, P, P],
         "lcs_adam_step": [P, P, P, P, I64, C.c_float, C.c_float, C.c_float, C.c_float, I32, P],
-        "lcs_surrogate_compose": [P, P, D, D, I32, P, P, I64, P],
+        "lcs_surrogate_compose": [P, P, D, D, I32, P, P],
         "lcs_surrogate_check": [P, P, D, D, D, P, C.c_float, P, P, P, P],
         "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
         "lcs_sub": [P, P, I64, P, P],
@@ -102,8 +102,6 @@ def _load(path: str = LIB_PATH):
         fn = getattr(L, name)
         fn.restype = C.c_int64
     L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
-    L.lcs_surrogate_workspace_bytes.restype = C.c_int64
-    L.lcs_surrogate_workspace_bytes.argtypes = [I64]
     L.lcs_check_tile_count.restype = C.c_int64
     L.lcs_check_tile_count.argtypes = [P]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
@@ -523,17 +521,13 @@ def lcs_adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, ep
                               _stream_handle(stream)))
 
 
-def lcs_surrogate_workspace_bytes(chunk: int) -> int:
-    return int(_lib.lcs_surrogate_workspace_bytes(int(chunk)))
-
-
 def lcs_check_tile_count(seeds) -> int:
     sd = seed_grid_desc(seeds)
     return int(_lib.lcs_check_tile_count(C.byref(sd)))
 
 
 def lcs_surrogate_compose(mlp: Mlp, seeds, t0: float, tau: float, n_windows: int, xf=None,
-                          workspace=None, chunk: int = 1 << 22, stream=None):
+                          stream=None):
     """Surrogate flow map of the seed grid: n_windows composed windows of tau."""
     torch = _torch()
     dev = mlp.params.device
@@ -541,13 +535,9 @@ def lcs_surrogate_compose(mlp: Mlp, seeds, t0: float, tau: float, n_windows: int
     if xf is None:
         xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
     _need(xf, torch.float32, (3, ns), "xf")
-    if workspace is None:
-        workspace = _bytes_buffer(lcs_surrogate_workspace_bytes(min(chunk, ns)), dev)
     sd = seed_grid_desc(seeds)
     _check(_lib.lcs_surrogate_compose(mlp.ref, C.byref(sd), float(t0), float(tau), int(n_windows),
-                                      _ptr(xf), _ptr(workspace),
-                                      int(workspace.numel() * workspace.element_size()),
-                                      _stream_handle(stream)))
+                                      _ptr(xf), _stream_handle(stream)))
     return xf
 
 
