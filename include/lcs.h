@@ -146,6 +146,27 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
                       float *xf, int64_t *cell, uint8_t *flags, void *stream);
 
 /*
+ * lcs_advect_sorted -- lcs_advect with re-bundled tracers: the integration
+ * runs in segments of `segment_steps` RK4 steps (0 = 50); before the first and
+ * between segments the tracers are counting-sorted by the Morton code of the
+ * 2 x 2 (x 2) velocity-cell bin they occupy, so that the lanes of a wavefront
+ * gather from one compact region although trajectories spread apart.  The
+ * per-tracer arithmetic is that of lcs_advect, so xf / cell / flags are
+ * bit-identical to it.  (The paper observed that tracers with neighbouring
+ * memory indices stop being neighbours in space, Sec. 3.2, and cites
+ * spatially coherent re-bundling as a remedy.)
+ *
+ * workspace [device] of at least lcs_advect_sorted_workspace_bytes(vel, seeds)
+ * bytes (about 63 B per seed): two copies of the tracer state, keys, the bin
+ * histogram.  Other arguments and errors as lcs_advect.
+ */
+int64_t lcs_advect_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds);
+lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                             double t0, double T, double dt, int32_t segment_steps,
+                             float *xf, int64_t *cell, uint8_t *flags,
+                             void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
  * lcs_advect_points -- flow map of arbitrary points, each with its own start
  * time (Eq. 2): the same integrator as lcs_advect over the duration T.
  * Used to resume segments, to draw check samples and to produce training

@@ -66,7 +66,9 @@ __device__ __forceinline__ void locate(const VelDev &v, int a, float xh, float x
     }
 }
 
-// Frame pair bracketing t and the time weight (FP64 in, FP32 weight out).
+// Frame pair bracketing t and the time weight (FP64 in, FP32 weight out).  t
+// is the same for every lane of a wave in the grid kernels, so the frame
+// index is made explicitly wave-uniform (it then addresses through SGPRs).
 __device__ __forceinline__ void frame_at(const VelDev &v, double t, long long &base, float &alpha)
 {
     double tau = (t - v.t_first) * v.inv_dt_frame;
@@ -76,11 +78,22 @@ __device__ __forceinline__ void frame_at(const VelDev &v, double t, long long &b
     base = (long long)f * v.frame_stride;
 }
 
-// Two x-adjacent nodes (i, i+1) with one dword-aligned 8-byte load.
-__device__ __forceinline__ float2 load_pair(const float *p)
+__device__ __forceinline__ void frame_at_uniform(const VelDev &v, double t, long long &base,
+                                                 float &alpha)
+{
+    double tau = (t - v.t_first) * v.inv_dt_frame;
+    tau = fmin(fmax(tau, 0.0), (double)(v.n_frames - 1));
+    const int f = __builtin_amdgcn_readfirstlane(min((int)floor(tau), v.n_frames - 2));
+    alpha = __builtin_amdgcn_readfirstlane_f32((float)(tau - (double)f));
+    base = (long long)f * v.frame_stride;
+}
+
+// Two x-adjacent nodes (i, i+1) with one dword-aligned 8-byte load at a
+// 32-bit element offset from a (wave-uniform) base.
+__device__ __forceinline__ float2 load_pair(const float *base, unsigned int elem)
 {
     float2 v;
-    __builtin_memcpy(&v, p, sizeof(v));
+    __builtin_memcpy(&v, reinterpret_cast<const char *>(base) + elem * 4u, sizeof(v));
     return v;
 }
 
@@ -104,18 +117,18 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
     const int px = wrap ? n0 - 2 : lo[0];             // start of the loaded pair
     const float wx1 = xi[0], wx0 = 1.0f - xi[0];
     constexpr int R = (D == 2) ? 2 : 4;               // rows of 2 corners
-    int row[R];
+    unsigned int row[R];
     float wr[R];
     if constexpr (D == 2) {
         const float wy1 = xi[1], wy0 = 1.0f - xi[1];
         row[0] = n0 * lo[1]; row[1] = n0 * hi[1];
         wr[0] = wy0; wr[1] = wy1;
     } else {
-        const int n01 = n0 * v.n[1];
+        const unsigned int n01 = (unsigned int)(n0 * v.n[1]);
         const float wy1 = xi[1], wy0 = 1.0f - xi[1];
         const float wz1 = xi[2], wz0 = 1.0f - xi[2];
-        const int y0 = n0 * lo[1], y1 = n0 * hi[1];
-        const int z0 = n01 * lo[2], z1 = n01 * hi[2];
+        const unsigned int y0 = n0 * lo[1], y1 = n0 * hi[1];
+        const unsigned int z0 = n01 * lo[2], z1 = n01 * hi[2];
         row[0] = y0 + z0; row[1] = y1 + z0; row[2] = y0 + z1; row[3] = y1 + z1;
         wr[0] = wy0 * wz0; wr[1] = wy1 * wz0; wr[2] = wy0 * wz1; wr[3] = wy1 * wz1;
     }
@@ -126,8 +139,8 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
         const float *__restrict__ B = A + fs;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            pa[c][r] = load_pair(A + row[r] + px);
-            pb[c][r] = load_pair(B + row[r] + px);
+            pa[c][r] = load_pair(A, row[r] + (unsigned int)px);
+            pb[c][r] = load_pair(B, row[r] + (unsigned int)px);
         }
     }
     if (wrap) {
@@ -205,25 +218,30 @@ __device__ __forceinline__ void stage_point(const float *xh, const float *xl, fl
     }
 }
 
-// Integrate one tracer in place: nsteps classical RK4 steps from t0 with step
-// dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
+// Integrate one tracer in place over steps n_begin <= n < n_end of classical
+// RK4 from t0 with step dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
 // or outside the closed domain (or a non-finite sampled velocity) rejects the
 // step, freezes the tracer and returns its flag.
-template <int D>
-__device__ uint32_t advect_tracer(const VelDev &v, float *xh, float *xl, double t0, double dt,
-                                  int nsteps)
+template <int D, bool UNIFORM_T = true>
+__device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                 int n_begin, int n_end)
 {
-    uint32_t fl = check_point<D>(v, xh);
-    if (fl) return fl;
+    uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
-    for (int n = 0; n < nsteps; ++n) {
+    for (int n = n_begin; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1, b2, b4;
         float al1, al2, al4;
-        frame_at(v, t, b1, al1);
-        frame_at(v, t + 0.5 * dt, b2, al2);
-        frame_at(v, t + dt, b4, al4);
+        if constexpr (UNIFORM_T) {
+            frame_at_uniform(v, t, b1, al1);
+            frame_at_uniform(v, t + 0.5 * dt, b2, al2);
+            frame_at_uniform(v, t + dt, b4, al4);
+        } else {
+            frame_at(v, t, b1, al1);
+            frame_at(v, t + 0.5 * dt, b2, al2);
+            frame_at(v, t + dt, b4, al4);
+        }
         float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
 
         velocity<D>(v, xh, xl, b1, al1, k1);
@@ -257,6 +275,17 @@ __device__ uint32_t advect_tracer(const VelDev &v, float *xh, float *xl, double 
         for (int a = 0; a < D; ++a) { xh[a] = nh[a]; xl[a] = nl[a]; }
     }
     return fl;
+}
+
+// UNIFORM_T: every lane of the wave integrates from the same t0 (grid,
+// batched, re-bundled and check launches); per-point start times use false.
+template <int D, bool UNIFORM_T = true>
+__device__ uint32_t advect_tracer(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                  int nsteps)
+{
+    const uint32_t fl = check_point<D>(v, xh);
+    if (fl) return fl;
+    return advect_steps<D, UNIFORM_T>(v, xh, xl, t0, dt, 0, nsteps);
 }
 
 // Velocity-cell index of a returned FP32 position, in FP64 without
@@ -417,7 +446,7 @@ __global__ __launch_bounds__(256) void advect_points_kernel(AdvectArgs A)
     if (!(t0 >= A.v.t_first && t0 <= A.v.t_last && t1 >= A.v.t_first && t1 <= A.v.t_last)) {
         fl = kTimeOut;
     } else {
-        fl = advect_tracer<D>(A.v, x, xl, t0, A.dt, A.nsteps);
+        fl = advect_tracer<D, false>(A.v, x, xl, t0, A.dt, A.nsteps);
 #pragma unroll
         for (int a = 0; a < D; ++a) x[a] = x[a] + xl[a];
     }
@@ -513,7 +542,224 @@ __global__ __launch_bounds__(256) void advect_tiles_kernel(AdvectArgs A, const u
     advect_seed<3>(A.v, g, sc, s, A.t0, A.dt, A.nsteps, A.ns, A.xf, A.cell, A.flags);
 }
 
+// ---------------------------------------------------------------------------
+// Re-bundled advection kernels
+// ---------------------------------------------------------------------------
+
+// Morton key of the coarse bin holding the point (periodic axes wrap, others
+// clamp; NaN lands in bin 0).
+template <int D>
+__device__ __forceinline__ uint32_t bin_key(const VelDev &v, const SortKeys &k, const float *x)
+{
+    int b[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        float q = (x[a] - k.origin[a]) * k.inv_bin[a];
+        const float nbf = (float)k.nb[a];
+        if ((v.periodic_mask >> a) & 1u) q = q - nbf * floorf(q / nbf);
+        q = fminf(fmaxf(q, 0.0f), nbf - 1.0f);
+        b[a] = (int)q;
+    }
+    uint32_t key = 0;
+    int pos = 0;
+    for (int l = 0; l < k.max_bits; ++l)
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (l < k.bits[a]) key |= (uint32_t)((b[a] >> l) & 1) << (pos++);
+    return key;
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, long long n, uint32_t v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// State of every seed in natural order, its flag for a start outside the
+// domain, its key and the bin histogram.
+template <int D>
+__global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    const SeedTiling &g = A.g;
+    const long long c[3] = {p % g.sn[0], (p / g.sn[0]) % g.sn[1], p / ((long long)g.sn[0] * g.sn[1])};
+    float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double x0 = g.s_origin[a] + (double)c[a] * g.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+        A.st.xh[a][p] = xh[a];
+        A.st.xl[a][p] = xl[a];
+    }
+    A.st.idx[p] = (int)p;
+    A.st.flag[p] = (uint8_t)check_point<D>(A.v, xh);
+    const uint32_t key = bin_key<D>(A.v, A.sk, xh);
+    A.sk.keys[p] = key;
+    atomicAdd(&A.sk.counts[key], 1u);
+}
+
+// Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
+// segment) or the state in place plus its new key and the histogram.
+template <int D>
+__global__ __launch_bounds__(256) void rebundle_segment_kernel(SegmentArgs A)
+{
+    const int nblocks = (int)gridDim.x;
+    const long long p = (long long)xcd_remap((int)blockIdx.x, nblocks) * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        xh[a] = A.st.xh[a][p];
+        xl[a] = A.st.xl[a][p];
+    }
+    uint32_t fl = A.st.flag[p];
+    if (!fl) fl = advect_steps<D>(A.v, xh, xl, A.t0, A.dt, A.n_begin, A.n_end);
+    if (A.last) {
+        const long long s = A.st.idx[p];
+        float x[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            x[a] = xh[a] + xl[a];
+            A.xf[a * A.n + s] = x[a];
+        }
+        if (A.cell) A.cell[s] = cell_index<D>(A.v, x);
+        if (A.flags) A.flags[s] = (uint8_t)fl;
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        A.st.xh[a][p] = xh[a];
+        A.st.xl[a][p] = xl[a];
+    }
+    A.st.flag[p] = (uint8_t)fl;
+    const uint32_t key = bin_key<D>(A.v, A.sk, xh);
+    A.sk.keys[p] = key;
+    atomicAdd(&A.sk.counts[key], 1u);
+}
+
+// Exclusive scan of the counts: blocks of 1024 (4 per thread), block totals,
+// one block scanning the totals, then the block offsets added back.
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t add = (t >= off) ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[255];
+    const uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void scan_blocks_kernel(uint32_t *data, long long n, uint32_t *sums)
+{
+    __shared__ uint32_t sh[256];
+    const long long base = (long long)blockIdx.x * kScanBlock + 4LL * threadIdx.x;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = (base + e < n) ? data[base + e] : 0u;
+        s += v[e];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, total);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (base + e < n) data[base + e] = run;
+        run += v[e];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(uint32_t *sums, long long nb)
+{
+    __shared__ uint32_t sh[256];
+    uint32_t carry = 0;
+    for (long long base = 0; base < nb; base += 256) {
+        const long long i = base + threadIdx.x;
+        const uint32_t v = (i < nb) ? sums[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(uint32_t *data, long long n, const uint32_t *sums)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) data[i] += sums[i / kScanBlock];
+}
+
+// Slot p moves to offset[key] + (its rank among the bin's arrivals).
+template <int D>
+__global__ __launch_bounds__(256) void scatter_kernel(SegmentArgs A, TracerState dst)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.n) return;
+    const uint32_t key = A.sk.keys[p];
+    const long long q = atomicAdd(&A.sk.counts[key], 1u);
+    if (q >= A.n) return;   // cannot happen when the histogram matches the keys
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        dst.xh[a][q] = A.st.xh[a][p];
+        dst.xl[a][q] = A.st.xl[a][p];
+    }
+    dst.idx[q] = A.st.idx[p];
+    dst.flag[q] = A.st.flag[p];
+}
+
 }  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(rebundle_init_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(rebundle_init_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(rebundle_segment_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(rebundle_segment_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+// counts (histogram) -> exclusive offsets -> scatter into dst; then the counts
+// are cleared for the next histogram.
+hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s)
+{
+    const long long nk = a.sk.n_keys;
+    const long long nb = (nk + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(256), 0, s, a.sk.counts, nk,
+                       a.sk.block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, a.sk.block_sums, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
+                       a.sk.counts, nk, a.sk.block_sums);
+    dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(scatter_kernel<2>, grid, block, 0, s, a, dst);
+    else hipLaunchKernelGGL(scatter_kernel<3>, grid, block, 0, s, a, dst);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
+                       a.sk.counts, nk, 0u);
+    return hipGetLastError();
+}
 
 hipError_t launch_surrogate_check(const CheckArgs &a, float tol, uint8_t *tile_fail, int *n_fail,
                                   hipStream_t s)

@@ -410,6 +410,137 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
     return lcs::clear_error();
 }
 
+}  // extern "C"
+
+namespace {
+
+struct SortedLayout {
+    lcs::SortKeys sk;
+    long long bytes;
+};
+
+long long align256(long long x) { return (x + 255) / 256 * 256; }
+
+// Bin geometry and workspace size of lcs_advect_sorted; with base != NULL the
+// state buffers and sort arrays are carved from it.
+SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, lcs::TracerState *st)
+{
+    SortedLayout L;
+    memset(&L, 0, sizeof(L));
+    long long nk = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < vel->dim) {
+            L.sk.nb[a] = (int)((vel->n[a] + lcs::kBinCells - 1) / lcs::kBinCells);
+            L.sk.bits[a] = ceil_log2(L.sk.nb[a]);
+            L.sk.inv_bin[a] = (float)(1.0 / (lcs::kBinCells * vel->spacing[a]));
+            L.sk.origin[a] = (float)vel->origin[a];
+        } else {
+            L.sk.nb[a] = 1;
+        }
+        if (L.sk.bits[a] > L.sk.max_bits) L.sk.max_bits = L.sk.bits[a];
+        nk <<= L.sk.bits[a];
+    }
+    L.sk.n_keys = nk;
+    long long off = 0;
+    auto take = [&](long long bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    for (int b = 0; b < 2; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            char *ph = (a < vel->dim) ? take(4 * n) : nullptr;
+            char *pl = (a < vel->dim) ? take(4 * n) : nullptr;
+            if (st) {
+                st[b].xh[a] = reinterpret_cast<float *>(ph);
+                st[b].xl[a] = reinterpret_cast<float *>(pl);
+            }
+        }
+        char *pi = take(4 * n);
+        char *pf = take(n);
+        if (st) {
+            st[b].idx = reinterpret_cast<int *>(pi);
+            st[b].flag = reinterpret_cast<uint8_t *>(pf);
+        }
+    }
+    L.sk.keys = reinterpret_cast<uint32_t *>(take(4 * n));
+    L.sk.counts = reinterpret_cast<uint32_t *>(take(4 * nk));
+    L.sk.block_sums = reinterpret_cast<uint32_t *>(take(4 * ((nk + 1023) / 1024 + 1)));
+    L.bytes = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lcs_advect_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds)
+{
+    if (check_velocity(vel) != LCS_OK || check_seeds(seeds, vel->dim) != LCS_OK) return 0;
+    const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    return sorted_layout(vel, n, nullptr, nullptr).bytes;
+}
+
+lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                             double T, double dt, int32_t segment_steps, float *xf, int64_t *cell,
+                             uint8_t *flags, void *workspace, int64_t workspace_bytes, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf || !workspace) return lcs::set_error(LCS_E_ARG, "xf and workspace must not be NULL");
+    if (segment_steps < 0) return lcs::set_error(LCS_E_ARG, "segment_steps must be >= 0");
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + T;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                              vel->t_first, t_last);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    lcs::TracerState bufs[2];
+    memset(bufs, 0, sizeof(bufs));
+    const SortedLayout need = sorted_layout(vel, n, nullptr, nullptr);
+    if (workspace_bytes < need.bytes)
+        return lcs::set_error(LCS_E_SHAPE, "workspace of %lld bytes is smaller than the %lld needed",
+                              (long long)workspace_bytes, need.bytes);
+    if (need.sk.n_keys > (1LL << 30)) return lcs::set_error(LCS_E_SHAPE, "velocity grid too large to bin");
+    const SortedLayout L = sorted_layout(vel, n, static_cast<char *>(workspace), bufs);
+    const int seg = segment_steps > 0 ? segment_steps : 50;
+    hipStream_t s = (hipStream_t)stream;
+
+    lcs::SegmentArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = make_vel(vel);
+    A.g = make_tiling(seeds);
+    A.t0 = t0;
+    A.dt = dt;
+    A.n = n;
+    A.sk = L.sk;
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+    A.st = bufs[0];
+    hipError_t e = lcs::launch_fill_u32(L.sk.counts, L.sk.n_keys, 0u, s);
+    if (e == hipSuccess) e = lcs::launch_rebundle_init(vel->dim, A, s);
+    if (e == hipSuccess) e = lcs::launch_rebundle_sort(vel->dim, A, bufs[1], s);
+    int cur = 1;
+    for (int n0 = 0; n0 < nsteps && e == hipSuccess; n0 += seg) {
+        A.st = bufs[cur];
+        A.n_begin = n0;
+        A.n_end = (nsteps - n0 < seg) ? nsteps : n0 + seg;
+        A.last = (A.n_end == nsteps) ? 1 : 0;
+        e = lcs::launch_rebundle_segment(vel->dim, A, s);
+        if (!A.last && e == hipSuccess) {
+            e = lcs::launch_rebundle_sort(vel->dim, A, bufs[1 - cur], s);
+            cur = 1 - cur;
+        }
+    }
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_sorted launch");
+    return lcs::clear_error();
+}
+
 lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0, int64_t n,
                              double T, double dt, float *xf, int64_t *cell, uint8_t *flags,
                              void *stream)

@@ -224,6 +224,52 @@ struct ComposeArgs {
 hipError_t launch_compose_fused(const ComposeArgs &a, hipStream_t s);
 hipError_t launch_sub(const float *a, const float *b, long long n, float *out, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Re-bundled advection: the integration runs in segments; after each segment
+// the tracers are counting-sorted by the Morton code of the coarse cell (2^D
+// velocity cells) they occupy, so that the lanes of a wave gather from one
+// compact region again.  State is carried in HBM between segments.
+// ---------------------------------------------------------------------------
+constexpr int kBinCells = 2;          // velocity cells per sort bin along each axis
+
+struct TracerState {
+    float *xh[3];
+    float *xl[3];
+    int *idx;                         // seed index (natural order)
+    uint8_t *flag;
+};
+
+struct SortKeys {
+    int bits[3];                      // Morton bits per axis
+    int max_bits;
+    int nb[3];                        // bins per axis
+    float inv_bin[3];                 // 1 / (bin width)
+    float origin[3];
+    uint32_t *keys;                   // [N]
+    uint32_t *counts;                 // [n_keys]; turned into offsets by the scan
+    uint32_t *block_sums;             // scan scratch
+    long long n_keys;
+};
+
+struct SegmentArgs {
+    VelDev v;
+    SeedTiling g;
+    double t0, dt;
+    int n_begin, n_end;
+    long long n;                      // tracers
+    TracerState st;
+    SortKeys sk;
+    int last;                         // 1: write outputs instead of state + keys
+    float *xf;
+    long long *cell;
+    uint8_t *flags;
+};
+
+hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s);
+hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s);
+hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
+
 // host-side validation and descriptor conversion (api.hip)
 lcs_status validate_velocity(const lcs_velocity_t *v);
 lcs_status validate_seeds(const lcs_seed_grid_t *g, int dim);

@@ -89,6 +89,7 @@ def _load(path: str = LIB_PATH):
         "lcs_surrogate_check": [P, P, D, D, D, P, C.c_float, P, P, P, P],
         "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
         "lcs_sub": [P, P, I64, P, P],
+        "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -102,6 +103,8 @@ def _load(path: str = LIB_PATH):
         fn = getattr(L, name)
         fn.restype = C.c_int64
     L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
+    L.lcs_advect_sorted_workspace_bytes.restype = C.c_int64
+    L.lcs_advect_sorted_workspace_bytes.argtypes = [P, P]
     L.lcs_check_tile_count.restype = C.c_int64
     L.lcs_check_tile_count.argtypes = [P]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
@@ -248,6 +251,38 @@ def lcs_advect(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
     sd = seed_grid_desc(seeds)
     _check(_lib.lcs_advect(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
                            _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_advect_sorted_workspace_bytes(frames: DeviceFrames, seeds) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_advect_sorted_workspace_bytes(frames.ref, C.byref(sd)))
+
+
+def lcs_advect_sorted(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
+                      segment_steps: int = 0, xf=None, cell=None, flags=None, workspace=None,
+                      want_cell=True, want_flags=True, stream=None):
+    """lcs_advect with tracers re-bundled by position between segments."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_advect_sorted_workspace_bytes(frames, seeds), dev)
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_sorted(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                                  int(segment_steps), _ptr(xf), _ptr(cell), _ptr(flags),
+                                  _ptr(workspace), int(workspace.numel() * workspace.element_size()),
+                                  _stream_handle(stream)))
     return xf, cell, flags
 
 
