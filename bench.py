@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-window, random-Fourier and surrogate workloads")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--strategy", default=None,
+                    help="advection strategy of the main workload ('tiles' or 'sorted:S'); "
+                         "default: autotuned")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that "
                          "profiler byte counters can be scaled by a kernel of known traffic")
@@ -52,10 +55,11 @@ def parse():
 PROFILE = os.path.join(ROOT, "profiles", "advect_grid_kernel_3d_abc128_seeds256.md")
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the advection kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of
-    known size), or None if the kernel source changed since it was taken."""
+def profiled_traffic(strategy):
+    """HBM bytes of one advection call (all its kernels) from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain
+    copy of known size), or None if it was taken for another strategy or the
+    kernel source changed since."""
     import hashlib
     try:
         text = open(PROFILE).read()
@@ -64,6 +68,8 @@ def profiled_traffic():
     for line in text.splitlines():
         if line.startswith("{") and "traffic_bytes_per_launch" in line:
             rec = json.loads(line)
+            if rec.get("strategy") != strategy:
+                continue
             h = hashlib.sha1()
             for f in rec["source_files"]:
                 h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -147,6 +153,12 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
                         (True, True, True))
     frames = lcs.DeviceFrames(fs, tensors=fs.u)
     ns = g.count
+    from paper_2209_13775_amd import autotune
+    tuned = autotune.tune(frames, g, 4.0, 4.0, 0.01, candidates=("sorted:100", "sorted:50",
+                                                                    "sorted:25"))
+    choice = tuned["choice"]
+    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                     device="cuda")
     xf = torch.empty((3, ns), dtype=torch.float32, device="cuda")
     flags = torch.empty(ns, dtype=torch.uint8, device="cuda")
     lam = torch.empty(ns, dtype=torch.float64, device="cuda")
@@ -159,7 +171,8 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
         for _ in range(reps):
             e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
             e[0].record(stream)
-            lcs.lcs_advect(frames, g, 4.0, T, dt, xf, None, flags, want_cell=False, stream=stream)
+            autotune.run(choice, frames, g, 4.0, T, dt, xf, None, flags, ws, want_cell=False,
+                         stream=stream)
             e[1].record(stream)
             lcs.lcs_cg_ftle(g, xf, T, flags=flags, lambda_max=lam, ftle=sig, stencil_flags=sfl,
                             stream=stream)
@@ -177,13 +190,15 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     steps = 2 * ns * nsteps
     adv = res["forward"][0] + res["backward"][0]
     cgf = res["forward"][1] + res["backward"][1]
+    del ws
     return {"workload": "random_fourier_256cubed_seeds512x512x256", "seeds": ns,
+            "advect_strategy": choice, "autotune_ms": tuned["ms"],
             "tracer_steps": steps, "advect_ms_forward": res["forward"][0],
             "advect_ms_backward": res["backward"][0], "cg_ftle_ms": cgf,
             "tracer_steps_per_s": steps / ((adv + cgf) * 1e-3),
             "ftle_points_per_s": 2 * ns / (cgf * 1e-3),
             "mean_ftle_forward": res["forward"][2], "mean_ftle_backward": res["backward"][2],
-            "roofline": {"kernel": "advect_grid_kernel<3>", "bound": "hbm",
+            "roofline": {"kernel": "advection call (%s)" % choice, "bound": "hbm",
                          "achieved": 768 * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": 768 * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "bytes_per_unit": 768, "unit_of_work": "3D tracer-RK4-step"}}
@@ -243,9 +258,12 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
            "ftle_err_mean": float(e.mean().item()), "ftle_err_max": float(e.max().item())}
     del xf, flags, sig
     curve = []
+    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                     device="cuda")
     for dtc in [0.02, 0.05, 0.1, 0.25]:
         e0.record(stream)
-        xc, _, fc = lcs.lcs_advect(frames, g, cfg.t0, T, dtc, want_cell=False, stream=stream)
+        xc, _, fc = lcs.lcs_advect_sorted(frames, g, cfg.t0, T, dtc, 50, workspace=ws,
+                                          want_cell=False, stream=stream)
         _, sc, _ = lcs.lcs_cg_ftle(g, xc, T, flags=fc, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
@@ -254,6 +272,7 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
                       "ftle_err_max": float(ec.max().item())})
         del xc, fc, sc
     out["coarse_rk4"] = curve
+    out["coarse_rk4_strategy"] = "sorted:50"
     return out
 
 
@@ -286,6 +305,18 @@ def main():
     ns = g.count
     nsteps = int(round(W["T"] / W["dt"]))
     frames = lcs.DeviceFrames(fs, device=dev)
+    from paper_2209_13775_amd import autotune
+    if args.strategy:
+        tuned = {"choice": args.strategy, "ms": None}
+    else:
+        print("bench: autotuning the seed ordering", file=sys.stderr, flush=True)
+        tuned = autotune.tune(frames, g, W["t0"], W["T"], W["dt"],
+                              candidates=("tiles", "sorted:100", "sorted:50"))
+    choice = tuned["choice"]
+    ws = None
+    if choice != "tiles":
+        ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                         device=dev)
     xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
     cell = torch.empty(ns, dtype=torch.int64, device=dev)
     flags = torch.empty(ns, dtype=torch.uint8, device=dev)
@@ -298,7 +329,7 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        lcs.lcs_advect(frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, stream=stream)
+        autotune.run(choice, frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, ws, stream=stream)
         if ev is not None:
             ev[1].record(stream)
         lcs.lcs_cg_tensor(g, xf, flags, Cm, sfl, stream=stream)
@@ -350,15 +381,20 @@ def main():
         "tracer_steps_per_s_advect_kernel": tracer_steps / (adv_ms * 1e-3),
         "ftle_points_per_s": ns / (cgf_ms * 1e-3),
         "flagged_tracers": nflag,
-        "roofline": {"kernel": "advect_grid_kernel<3>", "bound": "hbm", "achieved": achieved,
+        "advect_strategy": choice,
+        "autotune_ms": tuned["ms"],
+        "roofline": {"kernel": ("advect_grid_kernel<3>" if choice == "tiles" else
+                                "advection call: rebundle_segment_kernel<3> x %d + re-bundling sorts"
+                                % math.ceil(nsteps / int(choice.split(":")[1]))),
+                     "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(),
+                     "traffic": profiled_traffic(choice),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
                      "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
                      "units_per_launch": tracer_steps},
         "cpu_baseline": None,
     }
-    del frames, xf, cell, flags, Cm, sfl, lam, sig
+    del frames, xf, cell, flags, Cm, sfl, lam, sig, ws
     if not args.no_extra:
         torch.cuda.empty_cache()
         print("bench: batched double gyre windows", file=sys.stderr, flush=True)

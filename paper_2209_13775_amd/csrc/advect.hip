@@ -15,6 +15,17 @@
 
 #include "lcs_internal.h"
 
+// Occupancy hint of the advection kernels (minimum waves per SIMD; 0 = let
+// the compiler choose the register budget).
+#ifndef LCS_ADVECT_MIN_WAVES
+#define LCS_ADVECT_MIN_WAVES 0
+#endif
+#if LCS_ADVECT_MIN_WAVES > 0
+#define LCS_ADVECT_BOUNDS __launch_bounds__(256, LCS_ADVECT_MIN_WAVES)
+#else
+#define LCS_ADVECT_BOUNDS __launch_bounds__(256)
+#endif
+
 namespace lcs {
 namespace {
 
@@ -84,7 +95,7 @@ __device__ __forceinline__ void frame_at_uniform(const VelDev &v, double t, long
     double tau = (t - v.t_first) * v.inv_dt_frame;
     tau = fmin(fmax(tau, 0.0), (double)(v.n_frames - 1));
     const int f = __builtin_amdgcn_readfirstlane(min((int)floor(tau), v.n_frames - 2));
-    alpha = __builtin_amdgcn_readfirstlane_f32((float)(tau - (double)f));
+    alpha = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint((float)(tau - (double)f))));
     base = (long long)f * v.frame_stride;
 }
 
@@ -393,7 +404,7 @@ __device__ __forceinline__ void advect_seed(const VelDev &v, const SeedTiling &g
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void advect_grid_kernel(AdvectArgs A)
+__global__ LCS_ADVECT_BOUNDS void advect_grid_kernel(AdvectArgs A)
 {
     const int m = xcd_remap((int)blockIdx.x, A.g.n_blocks);
     int sc[3];
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
 // Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
 // segment) or the state in place plus its new key and the histogram.
 template <int D>
-__global__ __launch_bounds__(256) void rebundle_segment_kernel(SegmentArgs A)
+__global__ LCS_ADVECT_BOUNDS void rebundle_segment_kernel(SegmentArgs A)
 {
     const int nblocks = (int)gridDim.x;
     const long long p = (long long)xcd_remap((int)blockIdx.x, nblocks) * blockDim.x + threadIdx.x;
