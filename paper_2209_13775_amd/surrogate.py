@@ -150,16 +150,26 @@ def evaluate(mlp: lcs.Mlp, xt, dx, batch: int = 1 << 20) -> float:
 
 
 def surrogate_flowmap(mlp: lcs.Mlp, frames: lcs.DeviceFrames, seeds, cfg: SurrogateConfig,
-                      tol: float, stream=None):
+                      tol: float, full_fallback_fraction: float = 0.25, workspace=None,
+                      stream=None):
     """Composed surrogate flow map with RK4 check samples and RK4 fallback on
-    failing tiles.  Returns (xf, flags, n_fail, n_tiles)."""
+    failing tiles.  When more than ``full_fallback_fraction`` of the tiles fail,
+    the whole grid is re-advected with the re-bundled RK4 path instead (same
+    results, faster than tile by tile).  Returns (xf, flags, n_fail, tile_err)."""
     torch = lcs._torch()
     T = cfg.n_windows * cfg.tau
     xf = lcs.lcs_surrogate_compose(mlp, seeds, cfg.t0, cfg.tau, cfg.n_windows, stream=stream)
     err, fail, n_fail = lcs.lcs_surrogate_check(frames, seeds, cfg.t0, T, cfg.dt, xf, tol,
                                                 stream=stream)
     flags = torch.zeros(xf.shape[1], dtype=torch.uint8, device=xf.device)
-    lcs.lcs_advect_tiles(frames, seeds, cfg.t0, T, cfg.dt, fail, xf, None, flags, stream=stream)
+    nf = int(n_fail.item())                       # host decision: one small copy
+    if nf > full_fallback_fraction * lcs.lcs_check_tile_count(seeds):
+        seg = max(1, int(round(0.5 / abs(cfg.dt))))
+        lcs.lcs_advect_sorted(frames, seeds, cfg.t0, T, cfg.dt, seg, xf, None, flags, workspace,
+                              want_cell=False, stream=stream)
+    elif nf > 0:
+        lcs.lcs_advect_tiles(frames, seeds, cfg.t0, T, cfg.dt, fail, xf, None, flags,
+                             stream=stream)
     return xf, flags, n_fail, err
 
 
