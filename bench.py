@@ -52,7 +52,7 @@ def parse():
     return ap.parse_args()
 
 
-PROFILE = os.path.join(ROOT, "profiles", "advect_grid_kernel_3d_abc128_seeds256.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def profiled_traffic(strategy):
@@ -62,13 +62,17 @@ def profiled_traffic(strategy):
     kernel source changed since."""
     import hashlib
     try:
-        text = open(PROFILE).read()
+        names = sorted(os.listdir(PROFILES))
     except OSError:
         return None
-    for line in text.splitlines():
-        if line.startswith("{") and "traffic_bytes_per_launch" in line:
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)).read().splitlines():
+            if not (line.startswith("{") and "traffic_bytes_per_launch" in line):
+                continue
             rec = json.loads(line)
-            if rec.get("strategy") != strategy:
+            if rec.get("strategy", "tiles") != strategy:
                 continue
             h = hashlib.sha1()
             for f in rec["source_files"]:
