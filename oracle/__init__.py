@@ -74,6 +74,12 @@ def lib():
             "orc_lambda_max": (D, [C.c_int, P]),
             "orc_ftle": (None, [C.c_int, I64, P, D, P, P, C.c_int]),
             "orc_max_threads": (C.c_int, []),
+            "orc_mesh_new": (P, [C.c_int32, I64, P, I64, P, C.c_int32, D, D, P]),
+            "orc_mesh_free": (None, [P]),
+            "orc_mesh_locate_many": (None, [P, P, I64, P, P]),
+            "orc_mesh_velocity_at_many": (None, [P, P, P, I64, P, P]),
+            "orc_mesh_advect_seeds": (None, [P, P, P, I64, D, D, D, P, P, P, P, P, C.c_int]),
+            "orc_mesh_advect_points": (None, [P, P, P, I64, D, D, P, P, P, P, P, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -260,3 +266,88 @@ def ftle(dim: int, Cm: np.ndarray, T: float, threads=None):
     sig = np.empty(Ns)
     lib().orc_ftle(dim, Ns, _ptr(Cm), float(T), _ptr(lam), _ptr(sig), threads or default_threads())
     return lam, sig
+
+
+# ---------------------------------------------------------------------------
+# Unstructured meshes
+# ---------------------------------------------------------------------------
+
+
+class MeshVelocity:
+    """FP64 copies of a mesh and its nodal velocity frames, and the C object
+    (with its bucket locator) that reads them."""
+
+    def __init__(self, mf):
+        mesh = mf.mesh
+        self.dim = mesh.dim
+        self.mf = mf
+        self._nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64)
+        self._cells = np.ascontiguousarray(mesh.cells, dtype=np.int32)
+        self._u = np.ascontiguousarray(mf.u, dtype=np.float64)
+        assert self._u.shape == (mf.n_frames, mesh.n_nodes, mesh.dim)
+        self._h = lib().orc_mesh_new(mesh.dim, mesh.n_nodes, _ptr(self._nodes), mesh.n_cells,
+                                     _ptr(self._cells), mf.n_frames, float(mf.t_first),
+                                     float(mf.dt_frame), _ptr(self._u))
+        if not self._h:
+            raise MemoryError("orc_mesh_new failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_mesh_free(h)
+            self._h = None
+
+    def locate(self, x: np.ndarray):
+        """(cell (m,), barycentric (dim+1, m)) of points x (dim x m); cell -1 outside."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        m = x.shape[1]
+        cell = np.empty(m, dtype=np.int64)
+        lam = np.empty((self.dim + 1, m))
+        lib().orc_mesh_locate_many(self._h, _ptr(x), m, _ptr(cell), _ptr(lam))
+        return cell, lam
+
+    def velocity_at(self, x: np.ndarray, t):
+        """(u (dim x m), found (m,)) at points x; u is NaN where not found."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        m = x.shape[1]
+        tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t, dtype=np.float64), (m,)))
+        out = np.empty_like(x)
+        found = np.empty(m, dtype=np.uint8)
+        lib().orc_mesh_velocity_at_many(self._h, _ptr(x), _ptr(tt), m, _ptr(out), _ptr(found))
+        return out, found.astype(bool)
+
+    def advect_seeds(self, g, t0: float, T: float, dt: float, idx=None, threads=None):
+        """RK4 flow map of the seed grid on the mesh field: (xf, cell, flags,
+        margin, lam_margin); margin = smallest distance of a checked point to
+        the mesh bounding box, lam_margin = smallest barycentric coordinate of
+        the final position in its cell."""
+        sg = _seeds(g)
+        if idx is not None:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            m = idx.size
+        else:
+            m = g.count
+        xf = np.empty((g.dim, m))
+        cell = np.empty(m, dtype=np.int64)
+        flags = np.empty(m, dtype=np.uint8)
+        mg = np.empty(m)
+        lm = np.empty(m)
+        lib().orc_mesh_advect_seeds(self._h, C.byref(sg), _ptr(idx), m, float(t0), float(T),
+                                    float(dt), _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg),
+                                    _ptr(lm), threads or default_threads())
+        return xf, cell, flags, mg, lm
+
+    def advect_points(self, x0: np.ndarray, t0, T: float, dt: float, threads=None):
+        """RK4 flow map of points x0 (dim x m) with start times t0: as advect_seeds."""
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        m = x0.shape[1]
+        tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.float64), (m,)))
+        xf = np.empty_like(x0)
+        cell = np.empty(m, dtype=np.int64)
+        flags = np.empty(m, dtype=np.uint8)
+        mg = np.empty(m)
+        lm = np.empty(m)
+        lib().orc_mesh_advect_points(self._h, _ptr(x0), _ptr(tt), m, float(T), float(dt),
+                                     _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg), _ptr(lm),
+                                     threads or default_threads())
+        return xf, cell, flags, mg, lm

@@ -627,3 +627,430 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Unstructured meshes: triangles (2D) and tetrahedra (3D)                    */
+/* ======================================================================== */
+/*
+ * Velocity given at the nodes of a conforming triangle or tetrahedron mesh
+ * (Sec. 3.2: unstructured data is tetrahedralised so that one cell search and
+ * one interpolation serve every grid topology).  Inside a cell the field is
+ * the piecewise-linear interpolant u(x) = sum_i lambda_i(x) u(node_i), lambda
+ * the barycentric coordinates of x in that cell; in time it is linear between
+ * the two frames that bracket t, as on structured grids.
+ *
+ * The oracle finds the cell holding a point with a structured auxiliary grid
+ * of buckets over the mesh's bounding box, each bucket listing every cell
+ * whose bounding box meets it, and tests the listed cells; it does not use
+ * the local neighbour walk of the GPU code.  The interpolant does not depend
+ * on how the cell is found (it is continuous across faces).
+ */
+typedef struct {
+    int32_t dim;
+    int32_t n_frames;
+    int64_t n_nodes;
+    int64_t n_cells;
+    const double *nodes;   /* [n_nodes][dim] */
+    const int32_t *cells;  /* [n_cells][dim+1] */
+    double t_first;
+    double dt_frame;
+    const double *u;       /* [n_frames][n_nodes][dim] */
+    double lo[3], hi[3];   /* bounding box of the nodes */
+    double bsize[3];
+    int64_t nb[3];
+    int64_t *bstart;       /* CSR offsets, nb[0]*nb[1]*nb[2] + 1 */
+    int32_t *bcells;
+    double tol;            /* a point is in a cell if every lambda >= -tol */
+} orc_mesh;
+
+/* (b - a) x (c - a): twice the signed area of triangle abc */
+static double area2(const double *a, const double *b, const double *c)
+{
+    return (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+}
+
+/* (b - a) . ((c - a) x (d - a)): six times the signed volume of tetrahedron abcd */
+static double vol6(const double *a, const double *b, const double *c, const double *d)
+{
+    double e1[3], e2[3], e3[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = b[k] - a[k];
+        e2[k] = c[k] - a[k];
+        e3[k] = d[k] - a[k];
+    }
+    return e1[0] * (e2[1] * e3[2] - e2[2] * e3[1])
+         - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0])
+         + e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+}
+
+static const double *mesh_node(const orc_mesh *m, int64_t c, int i)
+{
+    return m->nodes + (int64_t)m->cells[c * (m->dim + 1) + i] * m->dim;
+}
+
+/* Barycentric coordinates by their definition as ratios of signed measures:
+ * lambda_i = measure(cell with vertex i replaced by x) / measure(cell). */
+static void barycentric(const orc_mesh *m, int64_t c, const double *x, double *lam)
+{
+    const double *v0 = mesh_node(m, c, 0), *v1 = mesh_node(m, c, 1), *v2 = mesh_node(m, c, 2);
+    if (m->dim == 2) {
+        double A = area2(v0, v1, v2);
+        lam[0] = area2(x, v1, v2) / A;
+        lam[1] = area2(v0, x, v2) / A;
+        lam[2] = area2(v0, v1, x) / A;
+        lam[3] = 0.0;
+    } else {
+        const double *v3 = mesh_node(m, c, 3);
+        double V = vol6(v0, v1, v2, v3);
+        lam[0] = vol6(x, v1, v2, v3) / V;
+        lam[1] = vol6(v0, x, v2, v3) / V;
+        lam[2] = vol6(v0, v1, x, v3) / V;
+        lam[3] = vol6(v0, v1, v2, x) / V;
+    }
+}
+
+static int64_t bucket_axis(const orc_mesh *m, int a, double x)
+{
+    double q = floor((x - m->lo[a]) / m->bsize[a]);
+    if (q < 0.0) return 0;
+    if (q > (double)(m->nb[a] - 1)) return m->nb[a] - 1;
+    return (int64_t)q;
+}
+
+static int64_t bucket_id(const orc_mesh *m, const int64_t *b)
+{
+    return b[0] + m->nb[0] * (b[1] + m->nb[1] * b[2]);
+}
+
+orc_mesh *orc_mesh_new(int32_t dim, int64_t n_nodes, const double *nodes, int64_t n_cells,
+                       const int32_t *cells, int32_t n_frames, double t_first, double dt_frame,
+                       const double *u)
+{
+    orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+    if (!m) return NULL;
+    m->dim = dim;
+    m->n_frames = n_frames;
+    m->n_nodes = n_nodes;
+    m->n_cells = n_cells;
+    m->nodes = nodes;
+    m->cells = cells;
+    m->t_first = t_first;
+    m->dt_frame = dt_frame;
+    m->u = u;
+    m->tol = 1e-12;
+    for (int a = 0; a < 3; ++a) {
+        m->lo[a] = 0.0;
+        m->hi[a] = 0.0;
+        m->nb[a] = 1;
+        m->bsize[a] = 1.0;
+    }
+    for (int a = 0; a < dim; ++a) {
+        m->lo[a] = INFINITY;
+        m->hi[a] = -INFINITY;
+    }
+    for (int64_t p = 0; p < n_nodes; ++p)
+        for (int a = 0; a < dim; ++a) {
+            double x = nodes[p * dim + a];
+            if (x < m->lo[a]) m->lo[a] = x;
+            if (x > m->hi[a]) m->hi[a] = x;
+        }
+    /* buckets of about two cells each */
+    double vol = 1.0;
+    for (int a = 0; a < dim; ++a) vol *= (m->hi[a] - m->lo[a]);
+    double edge = pow(2.0 * vol / (double)n_cells, 1.0 / (double)dim);
+    for (int a = 0; a < dim; ++a) {
+        double ext = m->hi[a] - m->lo[a];
+        int64_t k = (int64_t)ceil(ext / edge);
+        m->nb[a] = k < 1 ? 1 : k;
+        m->bsize[a] = ext / (double)m->nb[a];
+    }
+    int64_t nbt = m->nb[0] * m->nb[1] * m->nb[2];
+    m->bstart = (int64_t *)calloc((size_t)nbt + 1, sizeof(int64_t));
+    int64_t (*range)[2][3] = malloc((size_t)n_cells * sizeof(*range));
+    if (!m->bstart || !range) {
+        free(range);
+        free(m->bstart);
+        free(m);
+        return NULL;
+    }
+    for (int64_t c = 0; c < n_cells; ++c) {
+        for (int a = 0; a < 3; ++a) {
+            range[c][0][a] = 0;
+            range[c][1][a] = 0;
+        }
+        for (int a = 0; a < dim; ++a) {
+            double cmin = INFINITY, cmax = -INFINITY;
+            for (int i = 0; i <= dim; ++i) {
+                double x = mesh_node(m, c, i)[a];
+                if (x < cmin) cmin = x;
+                if (x > cmax) cmax = x;
+            }
+            double slack = 1e-9 * (m->hi[a] - m->lo[a]);
+            range[c][0][a] = bucket_axis(m, a, cmin - slack);
+            range[c][1][a] = bucket_axis(m, a, cmax + slack);
+        }
+        int64_t b[3];
+        for (b[2] = range[c][0][2]; b[2] <= range[c][1][2]; ++b[2])
+            for (b[1] = range[c][0][1]; b[1] <= range[c][1][1]; ++b[1])
+                for (b[0] = range[c][0][0]; b[0] <= range[c][1][0]; ++b[0])
+                    m->bstart[bucket_id(m, b) + 1] += 1;
+    }
+    for (int64_t q = 0; q < nbt; ++q) m->bstart[q + 1] += m->bstart[q];
+    m->bcells = (int32_t *)malloc((size_t)(m->bstart[nbt] > 0 ? m->bstart[nbt] : 1) * sizeof(int32_t));
+    int64_t *fill = (int64_t *)calloc((size_t)nbt, sizeof(int64_t));
+    if (!m->bcells || !fill) {
+        free(fill);
+        free(range);
+        free(m->bcells);
+        free(m->bstart);
+        free(m);
+        return NULL;
+    }
+    for (int64_t c = 0; c < n_cells; ++c) {     /* ascending cell ids in every bucket */
+        int64_t b[3];
+        for (b[2] = range[c][0][2]; b[2] <= range[c][1][2]; ++b[2])
+            for (b[1] = range[c][0][1]; b[1] <= range[c][1][1]; ++b[1])
+                for (b[0] = range[c][0][0]; b[0] <= range[c][1][0]; ++b[0]) {
+                    int64_t q = bucket_id(m, b);
+                    m->bcells[m->bstart[q] + fill[q]++] = (int32_t)c;
+                }
+    }
+    free(fill);
+    free(range);
+    return m;
+}
+
+void orc_mesh_free(orc_mesh *m)
+{
+    if (!m) return;
+    free(m->bcells);
+    free(m->bstart);
+    free(m);
+}
+
+/* The cell holding x: among the cells listed in x's bucket, the one whose
+ * smallest barycentric coordinate is largest (the most interior one; equal
+ * values go to the lower cell id), accepted if that coordinate is >= -tol.
+ * Returns the cell id and its barycentric coordinates, or -1 outside. */
+int64_t orc_mesh_locate(const orc_mesh *m, const double *x, double *lam_out)
+{
+    for (int a = 0; a < m->dim; ++a) {
+        if (!isfinite(x[a])) return -1;
+        double slack = 1e-9 * (m->hi[a] - m->lo[a]);
+        if (x[a] < m->lo[a] - slack || x[a] > m->hi[a] + slack) return -1;
+    }
+    int64_t b[3] = {0, 0, 0};
+    for (int a = 0; a < m->dim; ++a) b[a] = bucket_axis(m, a, x[a]);
+    int64_t q = bucket_id(m, b);
+    int64_t best = -1;
+    double best_min = -INFINITY, best_lam[4] = {0, 0, 0, 0};
+    for (int64_t s = m->bstart[q]; s < m->bstart[q + 1]; ++s) {
+        int64_t c = m->bcells[s];
+        double lam[4];
+        barycentric(m, c, x, lam);
+        double mn = lam[0];
+        for (int i = 1; i <= m->dim; ++i)
+            if (lam[i] < mn) mn = lam[i];
+        if (best < 0 || mn > best_min) {
+            best = c;
+            best_min = mn;
+            for (int i = 0; i < 4; ++i) best_lam[i] = lam[i];
+        }
+    }
+    if (best < 0 || !(best_min >= -m->tol)) return -1;
+    if (lam_out)
+        for (int i = 0; i < 4; ++i) lam_out[i] = best_lam[i];
+    return best;
+}
+
+void orc_mesh_locate_many(const orc_mesh *m, const double *x, int64_t n, int64_t *cell,
+                          double *lam)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double q[3] = {0, 0, 0}, l[4] = {0, 0, 0, 0};
+        for (int a = 0; a < m->dim; ++a) q[a] = x[a * n + p];
+        int64_t c = orc_mesh_locate(m, q, l);
+        cell[p] = c;
+        if (lam)
+            for (int i = 0; i <= m->dim; ++i) lam[i * n + p] = c >= 0 ? l[i] : NAN;
+    }
+}
+
+/* Frame pair bracketing t (same rule as on structured grids). */
+static void mesh_frame_pair(const orc_mesh *m, double t, int64_t *f, double *alpha)
+{
+    double q = floor((t - m->t_first) / m->dt_frame);
+    int64_t fi = (int64_t)q;
+    if (fi > m->n_frames - 2) fi = m->n_frames - 2;
+    if (fi < 0) fi = 0;
+    double tf = m->t_first + (double)fi * m->dt_frame;
+    *f = fi;
+    *alpha = (t - tf) / m->dt_frame;
+}
+
+/* u(x, t) = (1 - alpha) sum_i lambda_i u_f(node_i) + alpha sum_i lambda_i
+ * u_{f+1}(node_i).  Returns 0 (and leaves out untouched) if x is in no cell. */
+int orc_mesh_velocity_at(const orc_mesh *m, const double *x, double t, double *out)
+{
+    double lam[4];
+    int64_t c = orc_mesh_locate(m, x, lam);
+    if (c < 0) return 0;
+    int64_t f;
+    double alpha;
+    mesh_frame_pair(m, t, &f, &alpha);
+    int d = m->dim;
+    for (int k = 0; k < d; ++k) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i <= d; ++i) {
+            int64_t node = m->cells[c * (d + 1) + i];
+            s0 += lam[i] * m->u[(f * m->n_nodes + node) * d + k];
+            s1 += lam[i] * m->u[((f + 1) * m->n_nodes + node) * d + k];
+        }
+        out[k] = (1.0 - alpha) * s0 + alpha * s1;
+    }
+    return 1;
+}
+
+void orc_mesh_velocity_at_many(const orc_mesh *m, const double *x, const double *t, int64_t n,
+                               double *out, uint8_t *found)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        double q[3] = {0, 0, 0}, r[3] = {NAN, NAN, NAN};
+        for (int a = 0; a < m->dim; ++a) q[a] = x[a * n + p];
+        int ok = orc_mesh_velocity_at(m, q, t[p], r);
+        if (found) found[p] = (uint8_t)ok;
+        for (int a = 0; a < m->dim; ++a) out[a * n + p] = r[a];
+    }
+}
+
+/* Check a stage point or a new position: non-finite -> NONFINITE, in no cell
+ * of the mesh -> OUT.  margin (diagnostic): the smallest distance of a checked
+ * point to the mesh's bounding box, which is its distance to the boundary for
+ * the box-shaped meshes this oracle is used with. */
+static uint32_t mesh_check_point(const orc_mesh *m, const double *p, double *margin)
+{
+    if (!all_finite(p, m->dim)) return ORC_FLAG_NONFINITE;
+    if (margin)
+        for (int a = 0; a < m->dim; ++a) {
+            double d = fmin(p[a] - m->lo[a], m->hi[a] - p[a]);
+            if (d < *margin) *margin = d;
+        }
+    if (orc_mesh_locate(m, p, NULL) < 0) return ORC_FLAG_OUT;
+    return 0;
+}
+
+/* Classical RK4 step on the mesh field; the same exit reading as on
+ * structured grids (a rejected step leaves x unchanged). */
+static uint32_t mesh_rk4_step(const orc_mesh *m, double *x, double t, double dt, double *margin)
+{
+    int d = m->dim;
+    double k1[3], k2[3], k3[3], k4[3], p[3], xn[3];
+    uint32_t fl;
+
+    if (!orc_mesh_velocity_at(m, x, t, k1)) return ORC_FLAG_OUT;
+    if (!all_finite(k1, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k1[a];
+    if ((fl = mesh_check_point(m, p, margin))) return fl;
+    orc_mesh_velocity_at(m, p, t + 0.5 * dt, k2);
+    if (!all_finite(k2, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + 0.5 * dt * k2[a];
+    if ((fl = mesh_check_point(m, p, margin))) return fl;
+    orc_mesh_velocity_at(m, p, t + 0.5 * dt, k3);
+    if (!all_finite(k3, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a) p[a] = x[a] + dt * k3[a];
+    if ((fl = mesh_check_point(m, p, margin))) return fl;
+    orc_mesh_velocity_at(m, p, t + dt, k4);
+    if (!all_finite(k4, d)) return ORC_FLAG_NONFINITE;
+
+    for (int a = 0; a < d; ++a)
+        xn[a] = x[a] + (dt / 6.0) * (k1[a] + 2.0 * k2[a] + 2.0 * k3[a] + k4[a]);
+    if ((fl = mesh_check_point(m, xn, margin))) return fl;
+
+    for (int a = 0; a < d; ++a) x[a] = xn[a];
+    return 0;
+}
+
+static int mesh_time_span_ok(const orc_mesh *m, double t0, double T)
+{
+    double t_last = m->t_first + (double)(m->n_frames - 1) * m->dt_frame;
+    double t1 = t0 + T;
+    return t0 >= m->t_first && t0 <= t_last && t1 >= m->t_first && t1 <= t_last;
+}
+
+/* One tracer from x (in place): flags as on structured grids.  lam_margin
+ * (diagnostic): the smallest barycentric coordinate of the final position in
+ * its cell (how close it sits to a face), -inf if it is in no cell. */
+static uint32_t mesh_advect_one(const orc_mesh *m, double *x, double t0, double T, double dt,
+                                double *margin, int64_t *cell, double *lam_margin)
+{
+    uint32_t fl = mesh_time_span_ok(m, t0, T) ? mesh_check_point(m, x, margin) : ORC_FLAG_TIME_OUT;
+    int64_t nsteps = step_count(T, dt);
+    for (int64_t n = 0; n < nsteps && !fl; ++n)
+        fl = mesh_rk4_step(m, x, t0 + (double)n * dt, dt, margin);
+    double lam[4];
+    *cell = orc_mesh_locate(m, x, lam);
+    double mn = -INFINITY;
+    if (*cell >= 0) {
+        mn = lam[0];
+        for (int i = 1; i <= m->dim; ++i)
+            if (lam[i] < mn) mn = lam[i];
+    }
+    *lam_margin = mn;
+    return fl;
+}
+
+/* Advect the seeds of a (non-periodic) structured seed grid, or the listed
+ * ones (idx != NULL), from t0 over T with step dt.  Outputs as for
+ * orc_advect_seeds; cell = the mesh cell holding the final position (-1 if
+ * none).  Any output may be NULL. */
+void orc_mesh_advect_seeds(const orc_mesh *m, const orc_seed_grid *g, const int64_t *idx,
+                           int64_t n, double t0, double T, double dt, double *xf, int64_t *cell,
+                           uint8_t *flags, double *margin, double *lam_margin, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < n; ++p) {
+        double x[3] = {0, 0, 0};
+        seed_position(g, idx ? idx[p] : p, x);
+        double mg = INFINITY, lm;
+        int64_t c;
+        uint32_t fl = mesh_advect_one(m, x, t0, T, dt, &mg, &c, &lm);
+        if (xf)
+            for (int a = 0; a < m->dim; ++a) xf[a * n + p] = x[a];
+        if (cell) cell[p] = c;
+        if (flags) flags[p] = (uint8_t)fl;
+        if (margin) margin[p] = mg;
+        if (lam_margin) lam_margin[p] = lm;
+    }
+    (void)nthreads;
+}
+
+/* Advect arbitrary points x0 (dim x n), each from its own t0[p]. */
+void orc_mesh_advect_points(const orc_mesh *m, const double *x0, const double *t0, int64_t n,
+                            double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
+                            double *margin, double *lam_margin, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < n; ++p) {
+        double x[3] = {0, 0, 0};
+        for (int a = 0; a < m->dim; ++a) x[a] = x0[a * n + p];
+        double mg = INFINITY, lm;
+        int64_t c;
+        uint32_t fl = mesh_advect_one(m, x, t0[p], T, dt, &mg, &c, &lm);
+        if (xf)
+            for (int a = 0; a < m->dim; ++a) xf[a * n + p] = x[a];
+        if (cell) cell[p] = c;
+        if (flags) flags[p] = (uint8_t)fl;
+        if (margin) margin[p] = mg;
+        if (lam_margin) lam_margin[p] = lm;
+    }
+    (void)nthreads;
+}

@@ -440,3 +440,175 @@ def taylor_green_frames(n=64, n_frames=9, dt_frame=0.5, t_first=0.0, amp=0.5) ->
 
     return sample_field(fn, 2, (n, n), (0.0, 0.0), (h, h), (True, True), t_first, dt_frame,
                         n_frames)
+
+
+# ---------------------------------------------------------------------------
+# Unstructured meshes (triangles in 2D, tetrahedra in 3D) and nodal velocity
+# ---------------------------------------------------------------------------
+#
+# The paper's unstructured applications (a coronary stenosis, 2D; an aortic
+# aneurysm with about one million tetrahedra, 3D) are CFD data that is not
+# available.  Synthetic meshes stand in for them: a box cut into cells of a
+# lattice, every square split into two triangles along the same diagonal, every
+# cube into the six tetrahedra that share its main diagonal (Kuhn's split, which
+# is conforming across the lattice), with the interior nodes jittered so that
+# no two cells have the same shape.  Boundary nodes move only along the
+# boundary, so the union of the cells is exactly the box.
+
+
+@dataclass
+class Mesh:
+    """Conforming triangle (dim 2) or tetrahedron (dim 3) mesh on the host."""
+
+    dim: int
+    nodes: np.ndarray   # (n_nodes, dim) FP64 coordinates
+    cells: np.ndarray   # (n_cells, dim + 1) int32 node ids
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.nodes.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cells.shape[0])
+
+
+@dataclass
+class MeshFrames:
+    """Velocity at the nodes of a fixed mesh: u[f, node, c] is component c at
+    node ``node`` in frame f, the field at t_first + f*dt_frame."""
+
+    mesh: Mesh
+    t_first: float
+    dt_frame: float
+    u: np.ndarray       # (F, n_nodes, dim)
+
+    @property
+    def dim(self) -> int:
+        return self.mesh.dim
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.u.shape[0])
+
+
+def _signed_measure(nodes: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """Signed area (2D) or 6x signed volume (3D) of every cell (mesh checks)."""
+    v = [nodes[cells[:, i]] for i in range(cells.shape[1])]
+    e = [v[i] - v[0] for i in range(1, len(v))]
+    if nodes.shape[1] == 2:
+        return e[0][:, 0] * e[1][:, 1] - e[0][:, 1] * e[1][:, 0]
+    return np.einsum("ij,ij->i", e[0], np.cross(e[1], e[2]))
+
+
+def box_mesh(dim: int, cells_per_axis, lo, hi, jitter: float = 0.0, seed: int = 0,
+             shuffle: bool = False) -> Mesh:
+    """Lattice mesh of the box [lo, hi]: ``cells_per_axis`` squares or cubes per
+    axis, split into 2 triangles or 6 tetrahedra each.  ``jitter`` moves each
+    interior node coordinate by U(-jitter, jitter) lattice steps (boundary
+    nodes move only along the boundary).  ``shuffle`` renumbers nodes and cells
+    and permutes the vertex order inside each cell at random (the mesh is the
+    same; only its numbering becomes unstructured)."""
+    m = [int(c) for c in cells_per_axis][:dim]
+    lo = [float(v) for v in lo][:dim]
+    hi = [float(v) for v in hi][:dim]
+    h = [(hi[a] - lo[a]) / m[a] for a in range(dim)]
+    rng = np.random.default_rng(seed)
+    ax = [np.arange(m[a] + 1) for a in range(dim)]
+    grids = np.meshgrid(*ax, indexing="ij")            # axis 0 = x
+    ijk = np.stack([g.transpose(tuple(reversed(range(dim)))).ravel() for g in grids], axis=1)
+    nodes = np.stack([lo[a] + ijk[:, a] * h[a] for a in range(dim)], axis=1)
+    if jitter > 0.0:
+        d = rng.uniform(-jitter, jitter, size=nodes.shape)
+        interior = (ijk > 0) & (ijk < np.array(m)[None, :])
+        nodes = nodes + d * interior * np.array(h)[None, :]
+        for a in range(dim):                           # keep the walls exact
+            nodes[ijk[:, a] == 0, a] = lo[a]
+            nodes[ijk[:, a] == m[a], a] = hi[a]
+
+    def nid(i, j, k=0):
+        return i + (m[0] + 1) * (j + (m[1] + 1) * k)
+
+    if dim == 2:
+        j, i = np.meshgrid(np.arange(m[1]), np.arange(m[0]), indexing="ij")
+        i, j = i.ravel(), j.ravel()
+        c00, c10, c01, c11 = nid(i, j), nid(i + 1, j), nid(i, j + 1), nid(i + 1, j + 1)
+        tris = np.stack([np.stack([c00, c10, c11], 1), np.stack([c00, c11, c01], 1)], axis=1)
+        cells = tris.reshape(-1, 3)
+    else:
+        k, j, i = np.meshgrid(np.arange(m[2]), np.arange(m[1]), np.arange(m[0]), indexing="ij")
+        i, j, k = i.ravel(), j.ravel(), k.ravel()
+        corner = [nid(i + (b & 1), j + ((b >> 1) & 1), k + ((b >> 2) & 1)) for b in range(8)]
+        tets = []
+        for perm in ((0, 1, 2), (1, 2, 0), (2, 0, 1), (0, 2, 1), (2, 1, 0), (1, 0, 2)):
+            b1 = 1 << perm[0]
+            b2 = b1 | (1 << perm[1])
+            t = [corner[0], corner[b1], corner[b2], corner[7]]
+            if perm in ((0, 2, 1), (2, 1, 0), (1, 0, 2)):      # odd: restore orientation
+                t[1], t[2] = t[2], t[1]
+            tets.append(np.stack(t, 1))
+        cells = np.stack(tets, axis=1).reshape(-1, 4)
+    cells = cells.astype(np.int32)
+    meas = _signed_measure(nodes, cells)
+    if not np.all(meas > 0):
+        raise ValueError("jitter too large: a cell lost its orientation")
+    if shuffle:
+        pn = rng.permutation(nodes.shape[0])
+        inv = np.empty_like(pn)
+        inv[pn] = np.arange(pn.size)
+        nodes = nodes[pn]
+        cells = inv[cells].astype(np.int32)
+        cells = cells[rng.permutation(cells.shape[0])]
+        order = np.argsort(rng.random(cells.shape), axis=1)
+        cells = np.take_along_axis(cells, order, axis=1).astype(np.int32)
+    return Mesh(dim, np.ascontiguousarray(nodes), np.ascontiguousarray(cells))
+
+
+def mesh_sample(fn: Callable, mesh: Mesh, n_frames: int, t_first: float, dt_frame: float,
+                dtype=np.float64) -> MeshFrames:
+    """Sample ``fn(x, y[, z], t) -> components`` at the mesh nodes in FP64."""
+    u = np.empty((n_frames, mesh.n_nodes, mesh.dim), dtype=dtype)
+    coords = [mesh.nodes[:, a] for a in range(mesh.dim)]
+    for f in range(n_frames):
+        vals = fn(*coords, t_first + f * dt_frame)
+        for c in range(mesh.dim):
+            u[f, :, c] = np.broadcast_to(vals[c], (mesh.n_nodes,))
+    return MeshFrames(mesh, float(t_first), float(dt_frame), u)
+
+
+def box_cells_velocity(x, y, z, t, eps=0.5, omega=2 * math.pi / 4):
+    """Time-dependent cellular flow in the box [0, pi]^3: a Taylor-Green cell
+    rolling about z plus eps sin(omega t) times the same cell rolling about x.
+    Divergence-free, with no flow through any wall, chaotic mixing inside."""
+    s = eps * np.sin(omega * t)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z) + s * np.cos(x) * np.sin(y) * np.cos(z)
+    w = -s * np.cos(x) * np.cos(y) * np.sin(z)
+    return u, v, w
+
+
+def double_gyre_mesh_frames(cells=(200, 100), n_frames=21, dt_frame=1.0, jitter=0.15, seed=0,
+                            shuffle=False) -> MeshFrames:
+    """Double gyre on a jittered triangle mesh of [0,2] x [0,1] (stands in for
+    the 2D unstructured application)."""
+    mesh = box_mesh(2, cells, (0.0, 0.0), (2.0, 1.0), jitter=jitter, seed=seed, shuffle=shuffle)
+    return mesh_sample(double_gyre_velocity, mesh, n_frames, 0.0, dt_frame)
+
+
+def box_cells_mesh_frames(cells=64, n_frames=41, dt_frame=0.25, jitter=0.15, seed=0,
+                          shuffle=False) -> MeshFrames:
+    """Cellular box flow on a jittered tetrahedron mesh of [0, pi]^3 (stands in
+    for the 3D unstructured application)."""
+    c = (cells,) * 3 if np.isscalar(cells) else tuple(cells)
+    mesh = box_mesh(3, c, (0.0,) * 3, (math.pi,) * 3, jitter=jitter, seed=seed, shuffle=shuffle)
+    return mesh_sample(box_cells_velocity, mesh, n_frames, 0.0, dt_frame)
+
+
+WORKLOADS.update({
+    "double_gyre_trimesh_200x100x2_seeds256x128": dict(
+        field="double_gyre", mesh="tri", cells=(200, 100), frames=21, dt_frame=1.0,
+        seeds=(256, 128), t0=0.0, T=10.0, dt=0.05),
+    "box_cells_tetmesh_64cubed_x6_seeds192cubed": dict(
+        field="box_cells", mesh="tet", cells=64, frames=41, dt_frame=0.25,
+        seeds=(192, 192, 192), t0=0.0, T=8.0, dt=0.02),
+})

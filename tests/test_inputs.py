@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from paper_2209_13775_amd import inputs
 
@@ -56,3 +57,57 @@ def test_double_gyre_is_divergence_free_and_walls():
         assert np.abs(du + dv).max() < 1e-7
         assert np.abs(v[0]).max() < 1e-15 and np.abs(v[-1]).max() < 1e-15   # y walls
         assert np.abs(u[:, 0]).max() < 1e-15 and np.abs(u[:, -1]).max() < 1e-12  # x walls
+
+
+# ---------------------------------------------------------------------------
+# Unstructured meshes
+# ---------------------------------------------------------------------------
+
+
+def _faces(cells):
+    d1 = cells.shape[1]
+    f = np.concatenate([np.delete(cells, i, axis=1) for i in range(d1)], axis=0)
+    f = np.sort(f, axis=1)
+    _, counts = np.unique(f, axis=0, return_counts=True)
+    return counts
+
+
+@pytest.mark.parametrize("dim,cells,shuffle", [(2, (6, 4), False), (2, (6, 4), True),
+                                               (3, (4, 3, 2), False), (3, (4, 3, 2), True)])
+def test_box_mesh_is_conforming_and_fills_the_box(dim, cells, shuffle):
+    from paper_2209_13775_amd import inputs as I
+    hi = (2.0, 1.0, 1.5)[:dim]
+    m = I.box_mesh(dim, cells, (0.0,) * dim, hi, jitter=0.2, seed=2, shuffle=shuffle)
+    meas = np.abs(I._signed_measure(m.nodes, m.cells)) / (2 if dim == 2 else 6)
+    assert meas.min() > 0
+    assert abs(meas.sum() - np.prod(hi)) < 1e-12
+    counts = _faces(m.cells)
+    assert counts.max() == 2                       # every face in at most two cells
+    if dim == 2:
+        want_boundary = 2 * (cells[0] + cells[1])
+    else:
+        nx, ny, nz = cells
+        want_boundary = 4 * (nx * ny + ny * nz + nx * nz)
+    assert (counts == 1).sum() == want_boundary
+    # the walls stay exact
+    for a in range(dim):
+        x = m.nodes[:, a]
+        assert x.min() == 0.0 and x.max() == hi[a]
+
+
+def test_box_cells_field_is_divergence_free_and_wall_tangent():
+    from paper_2209_13775_amd import inputs as I
+    rng = np.random.default_rng(0)
+    p = rng.uniform(0.1, math.pi - 0.1, (3, 500))
+    t, h = 0.7, 1e-5
+    div = 0.0
+    for a in range(3):
+        e = np.zeros((3, 1))
+        e[a] = h
+        div = div + (I.box_cells_velocity(*(p + e), t)[a] - I.box_cells_velocity(*(p - e), t)[a]) / (2 * h)
+    assert np.abs(div).max() < 1e-8
+    for a in range(3):
+        for wall in (0.0, math.pi):
+            q = p.copy()
+            q[a] = wall
+            assert np.abs(I.box_cells_velocity(*q, t)[a]).max() < 1e-15
