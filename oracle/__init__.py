@@ -74,6 +74,8 @@ def lib():
             "orc_lambda_max": (D, [C.c_int, P]),
             "orc_ftle": (None, [C.c_int, I64, P, D, P, P, C.c_int]),
             "orc_max_threads": (C.c_int, []),
+            "orc_advect_seeds_ab": (None, [P, P, P, I64, D, D, D, C.c_int, P, P, P, P, C.c_int]),
+            "orc_advect_points_ab": (None, [P, P, P, I64, D, D, C.c_int, P, P, P, P, C.c_int]),
             "orc_mesh_new": (P, [C.c_int32, I64, P, I64, P, C.c_int32, D, D, P]),
             "orc_mesh_free": (None, [P]),
             "orc_mesh_locate_many": (None, [P, P, I64, P, P]),
@@ -218,6 +220,44 @@ def advect_seeds(vel: Velocity, g, t0: float, T: float, dt: float, idx=None, thr
     mg = np.empty(m) if margin else None
     lib().orc_advect_seeds(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(T), float(dt),
                            _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg), threads or default_threads())
+    return (xf, cell, flags, mg) if margin else (xf, cell, flags)
+
+
+def advect_seeds_ab(vel: Velocity, g, t0: float, T: float, dt: float, order: int = 4, idx=None,
+                    threads=None, margin: bool = False):
+    """Adams-Bashforth (order 2-4, RK4 start-up) flow map of the seed grid:
+    (xf, cell, flags[, margin])."""
+    assert order in (2, 3, 4)
+    sg = _seeds(g)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+    else:
+        m = g.count
+    xf = np.empty((g.dim, m), dtype=np.float64)
+    cell = np.empty(m, dtype=np.int64)
+    flags = np.empty(m, dtype=np.uint8)
+    mg = np.empty(m) if margin else None
+    lib().orc_advect_seeds_ab(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(T), float(dt),
+                              int(order), _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg),
+                              threads or default_threads())
+    return (xf, cell, flags, mg) if margin else (xf, cell, flags)
+
+
+def advect_points_ab(vel: Velocity, x0: np.ndarray, t0, T: float, dt: float, order: int = 4,
+                     threads=None, margin: bool = False):
+    """Adams-Bashforth flow map of arbitrary points: (xf, cell, flags[, margin])."""
+    assert order in (2, 3, 4)
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    m = x0.shape[1]
+    tt = np.ascontiguousarray(np.broadcast_to(np.asarray(t0, dtype=np.float64), (m,)))
+    xf = np.empty_like(x0)
+    cell = np.empty(m, dtype=np.int64)
+    flags = np.empty(m, dtype=np.uint8)
+    mg = np.empty(m) if margin else None
+    lib().orc_advect_points_ab(vel.ref, _ptr(x0), _ptr(tt), m, float(T), float(dt), int(order),
+                               _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg),
+                               threads or default_threads())
     return (xf, cell, flags, mg) if margin else (xf, cell, flags)
 
 
