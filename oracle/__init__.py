@@ -74,6 +74,8 @@ def lib():
             "orc_lambda_max": (D, [C.c_int, P]),
             "orc_ftle": (None, [C.c_int, I64, P, D, P, P, C.c_int]),
             "orc_max_threads": (C.c_int, []),
+            "orc_aux_points": (None, [P, P, I64, P, P]),
+            "orc_cg_aux": (None, [C.c_int, I64, P, P, P, P, P]),
             "orc_advect_seeds_ab": (None, [P, P, P, I64, D, D, D, C.c_int, P, P, P, P, C.c_int]),
             "orc_advect_points_ab": (None, [P, P, P, I64, D, D, C.c_int, P, P, P, P, C.c_int]),
             "orc_mesh_new": (P, [C.c_int32, I64, P, I64, P, C.c_int32, D, D, P]),
@@ -221,6 +223,45 @@ def advect_seeds(vel: Velocity, g, t0: float, T: float, dt: float, idx=None, thr
     lib().orc_advect_seeds(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(T), float(dt),
                            _ptr(xf), _ptr(cell), _ptr(flags), _ptr(mg), threads or default_threads())
     return (xf, cell, flags, mg) if margin else (xf, cell, flags)
+
+
+def aux_points(g, delta, idx=None) -> np.ndarray:
+    """Auxiliary points x0 -+ delta_b e_b of the seeds idx (all if None):
+    array (dim, 2*dim*m), point q = 2b + side of seed p at column q*m + p."""
+    sg = _seeds(g)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+    else:
+        m = g.count
+    dl = np.zeros(3)
+    dl[: g.dim] = delta
+    x = np.empty((g.dim, 2 * g.dim * m))
+    lib().orc_aux_points(C.byref(sg), _ptr(idx), m, _ptr(dl), _ptr(x))
+    return x
+
+
+def cg_aux(dim: int, delta, xf: np.ndarray, flags: Optional[np.ndarray] = None):
+    """(C (nq x m), stencil flags (m,)) from the final auxiliary positions
+    xf (dim, 2*dim*m) laid out as aux_points returns them."""
+    xf = np.ascontiguousarray(xf, dtype=np.float64)
+    m = xf.shape[1] // (2 * dim)
+    dl = np.zeros(3)
+    dl[:dim] = delta
+    Cm = np.empty((dim * (dim + 1) // 2, m))
+    sfl = np.empty(m, dtype=np.uint8)
+    if flags is not None:
+        flags = np.ascontiguousarray(flags, dtype=np.uint8)
+    lib().orc_cg_aux(dim, m, _ptr(dl), _ptr(xf), _ptr(flags), _ptr(Cm), _ptr(sfl))
+    return Cm, sfl
+
+
+def advect_aux(vel: Velocity, g, delta, t0: float, T: float, dt: float, idx=None, threads=None):
+    """Auxiliary-point flow map and C: (xf_aux, flags_aux, margin_aux, C, sflags)."""
+    x = aux_points(g, delta, idx)
+    xf, _, flags, mg = advect_points(vel, x, t0, T, dt, threads=threads, margin=True)
+    Cm, sfl = cg_aux(g.dim, delta, xf, flags)
+    return xf, flags, mg, Cm, sfl
 
 
 def advect_seeds_ab(vel: Velocity, g, t0: float, T: float, dt: float, order: int = 4, idx=None,

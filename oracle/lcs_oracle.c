@@ -404,6 +404,66 @@ void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64
 }
 
 /* ------------------------------------------------------------------------ */
+/* Auxiliary points                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Auxiliary points about each seed (Sec. 2 Seed filter) for the flow-map
+ * gradient (Sec. 2 Cauchy-Green filter): around seed x0, for every axis b < dim
+ * one point at x0 - delta_b e_b (side 0) and one at x0 + delta_b e_b (side 1).
+ * Output x is dim x (2 dim m): component a of auxiliary point q = 2b + side of
+ * the p-th listed seed at x[a*(2 dim m) + q*m + p]. */
+void orc_aux_points(const orc_seed_grid *g, const int64_t *idx, int64_t m, const double *delta,
+                    double *x)
+{
+    int d = g->dim;
+    int64_t w = 2 * (int64_t)d * m;
+    for (int64_t p = 0; p < m; ++p) {
+        double x0[3] = {0, 0, 0};
+        seed_position(g, idx ? idx[p] : p, x0);
+        for (int b = 0; b < d; ++b)
+            for (int side = 0; side < 2; ++side) {
+                int64_t q = 2 * b + side;
+                for (int a = 0; a < d; ++a) {
+                    double v = x0[a];
+                    if (a == b) v = side ? x0[a] + delta[b] : x0[a] - delta[b];
+                    x[a * w + q * m + p] = v;
+                }
+            }
+    }
+}
+
+/* Flow-map gradient from the final positions of the auxiliary points:
+ *   J[a][b] = (F_a(x0 + delta_b e_b) - F_a(x0 - delta_b e_b)) / (2 delta_b),
+ * C = J^T J packed as orc_cg_point.  xf is laid out as orc_aux_points' x;
+ * flags (2 dim m, or NULL) are the auxiliary tracers' flags, and a seed whose
+ * auxiliary points include a flagged one gets STENCIL_OUT. */
+void orc_cg_aux(int dim, int64_t m, const double *delta, const double *xf, const uint8_t *flags,
+                double *C, uint8_t *sflags)
+{
+    int64_t w = 2 * (int64_t)dim * m;
+    int nq = dim * (dim + 1) / 2;
+    for (int64_t p = 0; p < m; ++p) {
+        double J[3][3] = {{0}};
+        uint8_t bad = 0;
+        for (int b = 0; b < dim; ++b) {
+            int64_t qm = 2 * b, qp = 2 * b + 1;
+            for (int a = 0; a < dim; ++a)
+                J[a][b] = (xf[a * w + qp * m + p] - xf[a * w + qm * m + p]) / (2.0 * delta[b]);
+            if (flags && (flags[qm * m + p] || flags[qp * m + p])) bad = 1;
+        }
+        int k = 0;
+        for (int r = 0; r < dim; ++r)
+            for (int s = r; s < dim; ++s) {
+                double acc = 0.0;
+                for (int a = 0; a < dim; ++a) acc += J[a][r] * J[a][s];
+                C[(int64_t)k++ * m + p] = acc;
+            }
+        (void)nq;
+        if (sflags) sflags[p] = bad ? ORC_FLAG_STENCIL_OUT : 0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adams-Bashforth multistep integration                                      */
 /* ------------------------------------------------------------------------ */
 
