@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-window, random-Fourier and surrogate workloads")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux",
+                    help="comma-separated extra workloads to run after the main step")
     ap.add_argument("--strategy", default=None,
                     help="advection strategy of the main workload ('tiles' or 'sorted:S'); "
                          "default: autotuned")
@@ -206,6 +208,209 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
                          "achieved": 768 * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": 768 * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "bytes_per_unit": 768, "unit_of_work": "3D tracer-RK4-step"}}
+
+
+MESH_BYTES_PER_STEP_3D = 640   # 4 x (cell map 48 B + node ids 16 B + 2 frames x 4 nodes x 12 B)
+MESH_BYTES_PER_STEP_2D = 256   # 4 x (cell map 24 B + node ids 16 B + 2 frames x 3 nodes x 8 B)
+
+
+def bench_mesh(torch, lcs, inputs, reps=3, cpu_sample=0):
+    """Velocity on unstructured meshes: the 3D workload (time-dependent cellular
+    box flow on 64^3 x 6 jittered tetrahedra, 192^3 seeds, T = 8, dt = 0.02) and
+    the 2D one (double gyre on 200 x 100 x 2 jittered triangles, 256 x 128
+    seeds, T = 10, dt = 0.05)."""
+    out = {}
+    cases = [("box_cells_tetmesh_64cubed_x6_seeds192cubed", 3),
+             ("double_gyre_trimesh_200x100x2_seeds256x128", 2)]
+    for name, dim in cases:
+        w = inputs.WORKLOADS[name]
+        if dim == 3:
+            mf = inputs.box_cells_mesh_frames(cells=w["cells"], n_frames=w["frames"],
+                                              dt_frame=w["dt_frame"])
+            g = inputs.linspace_seeds(3, w["seeds"], (0.0,) * 3, (math.pi,) * 3)
+        else:
+            mf = inputs.double_gyre_mesh_frames(w["cells"], n_frames=w["frames"],
+                                                dt_frame=w["dt_frame"])
+            g = inputs.linspace_seeds(2, w["seeds"], (0.0, 0.0), (2.0, 1.0))
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        gm = lcs.Mesh(mf.mesh, stream=stream)
+        torch.cuda.synchronize()
+        create_ms = (time.perf_counter() - t) * 1e3
+        fr = lcs.MeshFrames(mf)
+        ns = g.count
+        xf = torch.empty((dim, ns), dtype=torch.float32, device="cuda")
+        cell = torch.empty(ns, dtype=torch.int64, device="cuda")
+        flags = torch.empty(ns, dtype=torch.uint8, device="cuda")
+        sig = torch.empty(ns, dtype=torch.float64, device="cuda")
+        t0, T, dt = w["t0"], w["T"], w["dt"]
+        lcs.lcs_mesh_advect(gm, fr, g, t0, T, dt, xf, cell, flags, stream=stream)
+        ta, tc = [], []
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            lcs.lcs_mesh_advect(gm, fr, g, t0, T, dt, xf, cell, flags, stream=stream)
+            e[1].record(stream)
+            lcs.lcs_cg_ftle(g, xf, T, flags=flags, ftle=sig, stream=stream)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            ta.append(e[0].elapsed_time(e[1]))
+            tc.append(e[1].elapsed_time(e[2]))
+        lcs.lcs_sync_status()
+        adv, cgf = float(np.median(ta)), float(np.median(tc))
+        steps = ns * int(round(T / dt))
+        bps = MESH_BYTES_PER_STEP_3D if dim == 3 else MESH_BYTES_PER_STEP_2D
+        fl = flags.cpu().numpy()
+        rec = {"workload": name, "cells": gm.n_cells, "nodes": gm.n_nodes, "seeds": ns,
+               "mesh_create_ms": create_ms, "advect_ms": adv, "cg_ftle_ms": cgf,
+               "tracer_steps": steps, "tracer_steps_per_s": steps / ((adv + cgf) * 1e-3),
+               "tracer_steps_per_s_advect_kernel": steps / (adv * 1e-3),
+               "ftle_points_per_s": ns / (cgf * 1e-3), "mean_ftle": float(sig.mean().item()),
+               "flagged_tracers": int((fl != 0).sum()), "lost_tracers": int(((fl & 16) != 0).sum()),
+               "roofline": {"kernel": "mesh_advect_grid_kernel<%d>" % dim, "bound": "hbm",
+                            "achieved": bps * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s",
+                            "frac": bps * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "bytes_per_unit": bps, "unit_of_work": "%dD mesh tracer-RK4-step" % dim}}
+        if cpu_sample and dim == 3:
+            import oracle
+            mv = oracle.MeshVelocity(mf)
+            idx = np.random.default_rng(0).choice(ns, size=cpu_sample, replace=False)
+            thr = oracle.default_threads()
+            t = time.perf_counter()
+            mv.advect_seeds(g, t0, T, dt, idx=idx, threads=thr)
+            sec = time.perf_counter() - t
+            rec["cpu_baseline"] = {"value": cpu_sample * int(round(T / dt)) / sec,
+                                   "unit": "tracer-RK4-steps/s", "cores": thr, "kind": "oracle",
+                                   "sample": "%d seeds drawn from the grid (seed 0), full T, FP64, "
+                                             "%.1f s" % (cpu_sample, sec)}
+        out[name] = rec
+        gm.close()
+        del fr, xf, cell, flags, sig
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_ab(torch, lcs, inputs, reps=2):
+    """Adams-Bashforth (AB4, RK4 start-up) on the ABC 128^3 / 256^3-seed / T = 8
+    workload: time per call and FTLE error against a fine-step RK4 reference
+    (dt = 0.005), beside RK4 at the benchmark step dt = 0.02."""
+    fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
+    L = 2 * math.pi
+    g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
+    frames = lcs.DeviceFrames(fs)
+    ns = g.count
+    T = 8.0
+    stream = torch.cuda.current_stream()
+    xf = torch.empty((3, ns), dtype=torch.float32, device="cuda")
+    flags = torch.empty(ns, dtype=torch.uint8, device="cuda")
+    sig = torch.empty(ns, dtype=torch.float64, device="cuda")
+    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                     device="cuda")
+    lcs.lcs_advect_sorted(frames, g, 0.0, T, 0.005, 200, xf, None, flags, ws, want_cell=False,
+                          stream=stream)
+    lcs.lcs_cg_ftle(g, xf, T, flags=flags, ftle=sig, stream=stream)
+    ref = sig.clone()
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        lcs.lcs_cg_ftle(g, xf, T, flags=flags, ftle=sig, stream=stream)
+        err = (sig - ref).abs()
+        return float(np.median(ms)), float(err.mean().item()), float(err.max().item())
+
+    runs = []
+    ms, em, ex = timed(lambda: lcs.lcs_advect_sorted(frames, g, 0.0, T, 0.02, 50, xf, None, flags,
+                                                     ws, want_cell=False, stream=stream))
+    runs.append({"method": "rk4 (re-bundled, segments of 50)", "dt": 0.02, "ms": ms,
+                 "ftle_err_mean": em, "ftle_err_max": ex})
+    ab_ms = None
+    for dt in (0.02, 0.01, 0.005):
+        ms, em, ex = timed(lambda: lcs.lcs_advect_ab(frames, g, 0.0, T, dt, order=4, xf=xf,
+                                                     want_cell=False, flags=flags, stream=stream))
+        if dt == 0.02:
+            ab_ms = ms
+        runs.append({"method": "ab4", "dt": dt, "ms": ms, "ftle_err_mean": em, "ftle_err_max": ex})
+    lcs.lcs_sync_status()
+    steps = ns * 400
+    del ws, frames
+    return {"workload": "abc_128cubed_seeds256cubed_ab4", "reference": "rk4 dt=0.005",
+            "runs": runs, "tracer_steps_per_s_ab4_dt0.02": steps / (ab_ms * 1e-3),
+            "velocity_evaluations_per_step": {"rk4": 4, "ab4": 1},
+            "roofline": {"kernel": "advect_ab_grid_kernel<3, 4>", "bound": "hbm",
+                         "achieved": 192 * steps / (ab_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": 192 * steps / (ab_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "bytes_per_unit": 192, "unit_of_work": "3D tracer-AB4-step"}}
+
+
+def bench_aux(torch, lcs, inputs, reps=2):
+    """Auxiliary-point gradient against seed-grid differences on the ABC field
+    (128^3 nodes, T = 8, dt = 0.02), FTLE at 128^3 seeds: error of (a) grid
+    differences on the 128^3 seeds, (b) grid differences on 256^3 seeds read at
+    the same points, (c) auxiliary points with delta = h/10 -- each against
+    auxiliary points with delta = h/100 -- and the time of each."""
+    fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
+    L = 2 * math.pi
+    g = inputs.periodic_seeds(3, (128, 128, 128), (L, L, L))
+    g2 = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
+    frames = lcs.DeviceFrames(fs)
+    T, dt = 8.0, 0.02
+    h = L / 128
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        out = fn()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return out, float(np.median(ms))
+
+    def aux(delta):
+        hi, lo, fl = lcs.lcs_advect_aux(frames, g, [delta] * 3, 0.0, T, dt, stream=stream)
+        Cm, sfl = lcs.lcs_cg_aux(g, [delta] * 3, hi, lo, fl, stream=stream)
+        _, sig = lcs.lcs_ftle(3, Cm, T, want_lambda=False, stream=stream)
+        return sig
+
+    def grid(gg):
+        xf, _, fl = lcs.lcs_advect(frames, gg, 0.0, T, dt, want_cell=False, stream=stream)
+        _, sig, _ = lcs.lcs_cg_ftle(gg, xf, T, flags=fl, stream=stream)
+        return sig
+
+    ref, ms_ref = timed(lambda: aux(h / 100))
+    s_aux, ms_aux = timed(lambda: aux(h / 10))
+    s_g1, ms_g1 = timed(lambda: grid(g))
+    s_g2, ms_g2 = timed(lambda: grid(g2))
+    s_g2 = s_g2.reshape(256, 256, 256)[::2, ::2, ::2].reshape(-1)
+    lcs.lcs_sync_status()
+
+    def err(x):
+        e = (x - ref).abs()
+        return {"ftle_err_mean": float(e.mean().item()), "ftle_err_p99": float(torch.quantile(
+            e[::17].float(), 0.99).item()), "ftle_err_max": float(e.max().item())}
+
+    ns = g.count
+    return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "reference":
+            "auxiliary points, delta = h/100", "seed_spacing_h": h,
+            "grid_128cubed": dict(ms=ms_g1, tracers=ns, **err(s_g1)),
+            "grid_256cubed_subsampled": dict(ms=ms_g2, tracers=8 * ns, **err(s_g2)),
+            "aux_delta_h_over_10": dict(ms=ms_aux, tracers=6 * ns, **err(s_aux)),
+            "aux_reference_ms": ms_ref,
+            "aux_tracer_steps_per_s": 6 * ns * 400 / (ms_aux * 1e-3)}
 
 
 def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
@@ -401,19 +606,37 @@ def main():
     }
     del frames, xf, cell, flags, Cm, sfl, lam, sig, ws
     if not args.no_extra:
-        torch.cuda.empty_cache()
-        print("bench: batched double gyre windows", file=sys.stderr, flush=True)
-        extra = {"batched": bench_batched(torch, lcs, inputs)}
-        torch.cuda.empty_cache()
-        print("bench: random-Fourier forward/backward", file=sys.stderr, flush=True)
+        want = set(x.strip() for x in args.extras.split(",") if x.strip())
+        if args.no_surrogate:
+            want.discard("surrogate")
+        extra = {}
         keep = {}
-        extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs, keep=keep)
         torch.cuda.empty_cache()
-        if not args.no_surrogate:
+        if "batched" in want:
+            print("bench: batched double gyre windows", file=sys.stderr, flush=True)
+            extra["batched"] = bench_batched(torch, lcs, inputs)
+            torch.cuda.empty_cache()
+        if "random_fourier" in want or "surrogate" in want:
+            print("bench: random-Fourier forward/backward", file=sys.stderr, flush=True)
+            extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs, keep=keep)
+            torch.cuda.empty_cache()
+        if "surrogate" in want:
             print("bench: surrogate (train, compose, check, fallback)", file=sys.stderr, flush=True)
             extra["surrogate"] = bench_surrogate(torch, lcs, keep)
         keep.clear()
         torch.cuda.empty_cache()
+        if "mesh" in want:
+            print("bench: unstructured meshes", file=sys.stderr, flush=True)
+            extra["mesh"] = bench_mesh(torch, lcs, inputs,
+                                       cpu_sample=0 if args.no_cpu_baseline else 10000)
+        if "ab" in want:
+            print("bench: Adams-Bashforth", file=sys.stderr, flush=True)
+            extra["adams_bashforth"] = bench_ab(torch, lcs, inputs)
+            torch.cuda.empty_cache()
+        if "aux" in want:
+            print("bench: auxiliary points", file=sys.stderr, flush=True)
+            extra["auxiliary_points"] = bench_aux(torch, lcs, inputs)
+            torch.cuda.empty_cache()
         out["extra_workloads"] = extra
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on a sample", file=sys.stderr, flush=True)

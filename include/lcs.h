@@ -58,7 +58,8 @@ enum {
     LCS_FLAG_OUT = 1u,         /* a stage point or new position left the closed domain */
     LCS_FLAG_NONFINITE = 2u,   /* a position or sampled velocity was not finite         */
     LCS_FLAG_STENCIL_OUT = 4u, /* (C / FTLE) a tracer of the difference stencil is flagged */
-    LCS_FLAG_TIME_OUT = 8u     /* (points) the tracer's interval leaves the frame span  */
+    LCS_FLAG_TIME_OUT = 8u,    /* (points) the tracer's interval leaves the frame span  */
+    LCS_FLAG_LOST = 16u        /* (meshes) the local cell search hit its step limit     */
 };
 
 /*
@@ -380,6 +381,208 @@ lcs_status lcs_surrogate_check(const lcs_velocity_t *vel, const lcs_seed_grid_t 
 lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
                             double T, double dt, const uint8_t *tile_fail, float *xf,
                             int64_t *cell, uint8_t *flags, void *stream);
+
+/*
+ * lcs_advect_ab -- as lcs_advect with an explicit Adams-Bashforth multistep
+ * method of order 2, 3 or 4 instead of RK4 (Sec. 2 Flow Map filter: single
+ * step and multistep methods):
+ *   x_{n+1} = x_n + dt * sum_{j<order} b_j u(x_{n-j}, t_{n-j})
+ * with b = (3, -1)/2, (23, -16, 5)/12, (55, -59, 37, -9)/24; the first
+ * order-1 steps are classical RK4 steps.  One velocity evaluation per step
+ * (RK4 takes four).  The exit rule is lcs_advect's, applied to the RK4 stage
+ * points of the start-up steps and to every new position.
+ * Errors: as lcs_advect, and LCS_E_ARG for an order outside 2..4.
+ */
+lcs_status lcs_advect_ab(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, int32_t order,
+                         double t0, double T, double dt, float *xf, int64_t *cell, uint8_t *flags,
+                         void *stream);
+
+/*
+ * lcs_advect_aux -- flow map of auxiliary points about every seed (Sec. 2
+ * Seed filter: highly localised auxiliary points; Cauchy-Green filter: the
+ * gradient from differences of auxiliary points).  For every seed x0 and
+ * axis b < dim, point q = 2b starts at x0 - delta[b] e_b and point q = 2b+1 at
+ * x0 + delta[b] e_b (FP64, carried as two-floats); each is advected exactly as
+ * lcs_advect advects a seed (RK4, exit rule, flags).
+ *
+ * delta   [host] dim doubles > 0 (typically well below the seed spacing).
+ * xa_hi,  [device] FP32, each dim x (2*dim) x Ns: component a of point q of
+ * xa_lo   seed s at [(a*2*dim + q)*Ns + s]; the final position is
+ *         xa_hi + xa_lo (a two-float, exact in FP64).
+ * flags   [device] uint8, (2*dim) x Ns, or NULL: [q*Ns + s].
+ * Errors: as lcs_advect (seeds must lie in the domain; an auxiliary point
+ * that starts outside it is flagged LCS_FLAG_OUT and not moved).
+ */
+lcs_status lcs_advect_aux(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                          const double *delta, double t0, double T, double dt, float *xa_hi,
+                          float *xa_lo, uint8_t *flags, void *stream);
+
+/*
+ * lcs_cg_aux -- Cauchy-Green tensor from auxiliary points (Eq. 1; Sec. 2
+ * Cauchy-Green filter): J[a][b] = (F_a(x0 + delta_b e_b) - F_a(x0 - delta_b e_b))
+ * / (2 delta_b) in FP64 from the exact two-float positions, C = J^T J packed as
+ * lcs_cg_tensor.  stencil_flags (or NULL) gets LCS_FLAG_STENCIL_OUT where a
+ * point of the seed is flagged (flags may be NULL).
+ */
+lcs_status lcs_cg_aux(const lcs_seed_grid_t *seeds, const double *delta, const float *xa_hi,
+                      const float *xa_lo, const uint8_t *flags, double *C, uint8_t *stencil_flags,
+                      void *stream);
+
+/* ======================================================================== */
+/* Unstructured velocity data: triangle (2D) and tetrahedron (3D) meshes      */
+/* ======================================================================== */
+/*
+ * Sec. 3.2: unstructured velocity data is tetrahedralised (triangulated in
+ * 2D) so that one cell search and one interpolation kernel serve every grid
+ * topology; the cell holding a point is found by a local search that starts
+ * from the cell that held the tracer before.  Inside a cell the velocity is
+ * the piecewise-linear interpolant sum_i lambda_i u(node_i), lambda the
+ * barycentric coordinates of the point; in time it is linear between the two
+ * frames that bracket t, as on structured grids.
+ *
+ * Local search: from a start cell, compute the barycentric coordinates of the
+ * point; if the smallest is >= -LCS_MESH_EPS the point is in that cell,
+ * otherwise step to the neighbour across the face opposite the vertex with the
+ * smallest coordinate.  Reaching a boundary face means the point is outside
+ * the mesh (LCS_FLAG_OUT); more than LCS_MESH_MAX_WALK steps set
+ * LCS_FLAG_LOST.  A point's first cell comes from a uniform grid of buckets
+ * over the mesh's bounding box, each holding one cell near it.
+ */
+
+/* Containment tolerance on barycentric coordinates and step limit of the
+ * local cell search. */
+#define LCS_MESH_EPS 3.814697265625e-06 /* 2^-18 */
+#define LCS_MESH_MAX_WALK 1024
+
+/*
+ * Mesh description, read by lcs_mesh_create only.
+ *
+ * dim      2 (triangles) or 3 (tetrahedra).
+ * n_nodes  1 <= n_nodes < 2^28.   n_cells  1 <= n_cells < 2^31.
+ * nodes    [device] FP64, [n_nodes][dim] node coordinates (x fastest).
+ * cells    [device] int32, [n_cells][dim+1] node ids of each cell, any
+ *          vertex order.  The mesh must be conforming: a face is shared by at
+ *          most two cells, and no cell is degenerate.
+ */
+typedef struct {
+    int32_t dim;
+    int32_t reserved;         /* must be 0 */
+    int64_t n_nodes;
+    int64_t n_cells;
+    const double *nodes;
+    const int32_t *cells;
+} lcs_mesh_desc_t;
+
+/* Opaque mesh: the library's device copy of the cell geometry (the affine
+ * map of every cell to barycentric coordinates, FP32), the node ids and face
+ * neighbours of every cell, and the bucket grid for first location. */
+typedef struct lcs_mesh *lcs_mesh_t;
+
+/* Mesh facts (host struct filled by lcs_mesh_info). */
+typedef struct {
+    int32_t dim;
+    int32_t reserved;
+    int64_t n_nodes;
+    int64_t n_cells;
+    int64_t n_boundary_faces; /* faces with no neighbouring cell */
+    int64_t buckets[3];       /* bucket grid of the first-location search */
+    double lo[3], hi[3];      /* bounding box of the nodes */
+    int64_t device_bytes;     /* device memory the mesh object holds */
+} lcs_mesh_info_t;
+
+/*
+ * Velocity at the mesh nodes for a series of frames (Sec. 2 Interpolator:
+ * frames resident in GPU memory).
+ *
+ * n_frames  >= 2; frame f holds the field at t_first + f*dt_frame,
+ *           dt_frame > 0.
+ * u         [device] FP32, [n_frames][n_nodes][S] with S = 2 in 2D and S = 4
+ *           in 3D (x, y, z and one unused value): the components of a node
+ *           sit together so that one 8- or 16-byte load reads them.
+ */
+typedef struct {
+    int32_t n_frames;
+    int32_t reserved;         /* must be 0 */
+    double t_first;
+    double dt_frame;
+    const float *u;
+} lcs_mesh_frames_t;
+
+/*
+ * lcs_mesh_create -- build the device mesh object (Sec. 2 Seed and Reader
+ * filters: a one-time preparation of the velocity mesh).  Computes, on the
+ * device, the face neighbours of every cell (through a node-to-cell adjacency
+ * list), every cell's affine map to barycentric coordinates (in FP64, stored
+ * as FP32 relative to an FP32 reference point with an FP64-exact offset) and
+ * the bucket grid.  Allocates device memory owned by the mesh object and
+ * synchronises the stream before it returns.
+ * Errors: LCS_E_ARG (NULL, dim), LCS_E_SHAPE (counts, a node id out of range,
+ * a degenerate cell, a face shared by more than two cells), LCS_E_HIP.
+ */
+lcs_status lcs_mesh_create(const lcs_mesh_desc_t *desc, lcs_mesh_t *out, void *stream);
+
+/* lcs_mesh_destroy -- frees the mesh object (NULL is ignored); waits for the
+ * device first. */
+void lcs_mesh_destroy(lcs_mesh_t mesh);
+
+/* lcs_mesh_info -- facts about a mesh object.  info: [host]. */
+lcs_status lcs_mesh_info(lcs_mesh_t mesh, lcs_mesh_info_t *info);
+
+/*
+ * lcs_mesh_locate -- cell holding each point (first location: bucket start
+ * cell, then the local search).
+ * x     [device] FP32, dim x n.
+ * cell  [device] int64, n: cell id, -1 outside the mesh (or non-finite x),
+ *       -2 if the search hit its step limit.
+ * lam   [device] FP32, (dim+1) x n, or NULL: barycentric coordinates in that
+ *       cell (unspecified where cell < 0).
+ */
+lcs_status lcs_mesh_locate(lcs_mesh_t mesh, const float *x, int64_t n, int64_t *cell, float *lam,
+                           void *stream);
+
+/*
+ * lcs_mesh_velocity_at -- u(x, t) at points (each with its own t, inside the
+ * frame span, else LCS_E_TIME_RANGE is not detected: t is clamped to the span).
+ * x [device] FP32 dim x n; t [device] FP64 n; u [device] FP32 dim x n (NaN
+ * outside the mesh); cell [device] int64 n or NULL (as lcs_mesh_locate).
+ */
+lcs_status lcs_mesh_velocity_at(lcs_mesh_t mesh, const lcs_mesh_frames_t *frames, const float *x,
+                                const double *t, int64_t n, float *u, int64_t *cell, void *stream);
+
+/*
+ * lcs_mesh_advect -- flow map of a structured seed grid through velocity on a
+ * mesh (Eq. 2; Sec. 2 Seed and Flow Map filters; Sec. 3.1 RK4; Sec. 3.2 local
+ * cell search).  N = T/dt classical RK4 steps, t_n = t0 + n*dt; the four
+ * stage points and the new position are located by the local search started
+ * from the cell of the previous one, so each tracer carries its cell from step
+ * to step.  A seed outside the mesh is flagged LCS_FLAG_OUT and not moved (an
+ * unstructured domain rarely fills the seed grid's box).  A stage point or new
+ * position outside the mesh rejects the step and freezes the tracer
+ * (LCS_FLAG_OUT), as do non-finite values (LCS_FLAG_NONFINITE) and a search
+ * past its step limit (LCS_FLAG_LOST).
+ *
+ * seeds  non-periodic seed grid of the mesh's dim (else LCS_E_UNSUPPORTED /
+ *        LCS_E_ARG).
+ * xf     [device] FP32, dim x Ns, final positions.
+ * cell   [device] int64, Ns, or NULL: mesh cell holding the final position
+ *        (-1 for a seed outside the mesh).
+ * flags  [device] uint8, Ns, or NULL.
+ * Errors: LCS_E_ARG, LCS_E_TIME_RANGE, LCS_E_STEP, LCS_E_HIP.
+ */
+lcs_status lcs_mesh_advect(lcs_mesh_t mesh, const lcs_mesh_frames_t *frames,
+                           const lcs_seed_grid_t *seeds, double t0, double T, double dt,
+                           float *xf, int64_t *cell, uint8_t *flags, void *stream);
+
+/*
+ * lcs_mesh_advect_points -- as lcs_mesh_advect for arbitrary points x0
+ * ([device] FP32 dim x n) with their own start times t0 ([device] FP64 n);
+ * a point whose interval [t0, t0+T] leaves the frame span is not moved and is
+ * flagged LCS_FLAG_TIME_OUT.
+ */
+lcs_status lcs_mesh_advect_points(lcs_mesh_t mesh, const lcs_mesh_frames_t *frames,
+                                  const float *x0, const double *t0, int64_t n, double T,
+                                  double dt, float *xf, int64_t *cell, uint8_t *flags,
+                                  void *stream);
 
 /* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
 lcs_status lcs_sync_status(void *stream);

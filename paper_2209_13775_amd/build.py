@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblcs_hip.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "api_mlp.hip", "advect.hip", "cgftle.hip", "mlp.hip"]
+SOURCES = ["api.hip", "api_mlp.hip", "api_mesh.hip", "advect.hip", "cgftle.hip", "mlp.hip",
+           "mesh.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

@@ -14,6 +14,7 @@
 // round.
 
 #include "lcs_internal.h"
+#include "device_common.h"
 
 // Occupancy hint of the advection kernels (minimum waves per SIMD; 0 = let
 // the compiler choose the register budget).
@@ -32,14 +33,6 @@ namespace {
 constexpr uint32_t kOut = LCS_FLAG_OUT;
 constexpr uint32_t kNonFinite = LCS_FLAG_NONFINITE;
 constexpr uint32_t kTimeOut = LCS_FLAG_TIME_OUT;
-
-// Error-free sum: s + e == a + b exactly (Knuth's TwoSum).
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
-{
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
 
 // Lower node, upper node and local coordinate of the two-float point
 // xh + xl along one axis.  s = (x - origin)/h is formed in two-float
@@ -191,44 +184,6 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
     return 0;
 }
 
-template <int D>
-__device__ __forceinline__ bool finite_vec(const float *k)
-{
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < D; ++a) ok = ok && isfinite(k[a]);
-    return ok;
-}
-
-// Step-size constants as two-floats, so that the FP32 rounding of dt does not
-// bias every step the same way.
-struct StepConsts {
-    float hh, hl;   // dt/2
-    float fh, fl;   // dt
-    float sh, sl;   // dt/6
-};
-
-__device__ __forceinline__ StepConsts step_consts(double dt)
-{
-    StepConsts c;
-    c.hh = (float)(0.5 * dt); c.hl = (float)(0.5 * dt - (double)c.hh);
-    c.fh = (float)dt;         c.fl = (float)(dt - (double)c.fh);
-    c.sh = (float)(dt / 6.0); c.sl = (float)(dt / 6.0 - (double)c.sh);
-    return c;
-}
-
-// Stage point (ph + pl) = (xh + xl) + (ch + cl) k, renormalised.
-template <int D>
-__device__ __forceinline__ void stage_point(const float *xh, const float *xl, float ch, float cl,
-                                            const float *k, float *ph, float *pl)
-{
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const float inc = fmaf(ch, k[a], cl * k[a]);
-        two_sum(xh[a], xl[a] + inc, ph[a], pl[a]);
-    }
-}
-
 // Integrate one tracer in place over steps n_begin <= n < n_end of classical
 // RK4 from t0 with step dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
@@ -333,51 +288,6 @@ __device__ long long cell_index(const VelDev &v, const float *x)
     return idx;
 }
 
-// XCD-aware block order: workgroups are dealt round-robin to the 8 XCDs, so
-// block b runs on XCD b % 8.  Give each XCD a contiguous run of the curve:
-// XCDs < r take q+1 consecutive positions, the others q (q, r = divmod(B, 8)).
-__device__ __forceinline__ int xcd_remap(int b, int nblocks)
-{
-    constexpr int kXcd = 8;
-    const int q = nblocks / kXcd, r = nblocks % kXcd;
-    const int x = b % kXcd, local = b / kXcd;
-    return (x < r) ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
-}
-
-// Seed of this lane for Morton tile index m, or -1 if the tile or the lane
-// falls outside the seed grid.  Morton decode with per-axis bit counts (an
-// axis that runs out of bits drops out of the interleave); within the tile,
-// waves and lanes are laid out as wg x wt seeds.
-template <int D>
-__device__ __forceinline__ long long seed_of(const SeedTiling &g, int m, int t, int *sc)
-{
-    int tc[3] = {0, 0, 0};
-    int pos = 0;
-    for (int l = 0; l < g.max_bits; ++l)
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-            if (l < g.bits[a]) tc[a] |= ((m >> (pos++)) & 1) << l;
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-        if (tc[a] >= g.ntiles[a]) return -1;
-    const int w = t / kWave, l = t % kWave;
-    int wc[3], lc[3];
-    wc[0] = w % g.wg[0];
-    wc[1] = (w / g.wg[0]) % g.wg[1];
-    wc[2] = w / (g.wg[0] * g.wg[1]);
-    lc[0] = l % g.wt[0];
-    lc[1] = (l / g.wt[0]) % g.wt[1];
-    lc[2] = l / (g.wt[0] * g.wt[1]);
-    sc[0] = sc[1] = sc[2] = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        sc[a] = (tc[a] * g.wg[a] + wc[a]) * g.wt[a] + lc[a];
-        if (sc[a] >= g.sn[a]) return -1;
-    }
-    return (long long)sc[0] + (long long)g.sn[0] * ((long long)sc[1] +
-           (long long)g.sn[1] * (long long)sc[2]);
-}
-
 // Advect the seed with integer coordinates sc from t0 and write its outputs at
 // linear index s of the given output arrays.
 template <int D>
@@ -411,6 +321,150 @@ __global__ LCS_ADVECT_BOUNDS void advect_grid_kernel(AdvectArgs A)
     const long long s = seed_of<D>(A.g, m, threadIdx.x, sc);
     if (s < 0) return;
     advect_seed<D>(A.v, A.g, sc, s, A.t0, A.dt, A.nsteps, A.ns, A.xf, A.cell, A.flags);
+}
+
+// ---------------------------------------------------------------------------
+// Adams-Bashforth multistep advection (the Flow Map filter admits multistep
+// methods, Sec. 2): one velocity evaluation per step instead of RK4's four.
+// x_{n+1} = x_n + (dt/den) sum_j num_j f_{n-j} with integer numerators
+// (3, -1)/2, (23, -16, 5)/12, (55, -59, 37, -9)/24, the combination formed in
+// FP32 (exact integer weights) and scaled by dt/den as a two-float.  The first
+// S-1 steps are classical RK4 steps whose first stage is f_n.  The past
+// velocities stay in registers.
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ float ab_num(int j)
+{
+    if constexpr (S == 2) return j == 0 ? 3.0f : -1.0f;
+    else if constexpr (S == 3) return j == 0 ? 23.0f : (j == 1 ? -16.0f : 5.0f);
+    else return j == 0 ? 55.0f : (j == 1 ? -59.0f : (j == 2 ? 37.0f : -9.0f));
+}
+
+template <int S>
+constexpr double ab_den() { return S == 2 ? 2.0 : (S == 3 ? 12.0 : 24.0); }
+
+template <int D, int S>
+__device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                    int nsteps)
+{
+    uint32_t fl = 0;
+    const StepConsts sc = step_consts(dt);
+    const double cab = dt / ab_den<S>();
+    const float ch = (float)cab, cl = (float)(cab - (double)ch);
+    float hist[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    for (int n = 0; n < nsteps; ++n) {
+        const double t = t0 + (double)n * dt;
+        long long b1;
+        float al1;
+        frame_at_uniform(v, t, b1, al1);
+        float k1[3];
+        velocity<D>(v, xh, xl, b1, al1, k1);
+        if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
+        float nh[3], nl[3];
+        if (n < S - 1) {
+            long long b2, b4;
+            float al2, al4;
+            frame_at_uniform(v, t + 0.5 * dt, b2, al2);
+            frame_at_uniform(v, t + dt, b4, al4);
+            float k2[3], k3[3], k4[3], ph[3], pl[3];
+            stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
+            if ((fl = check_point<D>(v, ph))) break;
+            velocity<D>(v, ph, pl, b2, al2, k2);
+            if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
+            stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
+            if ((fl = check_point<D>(v, ph))) break;
+            velocity<D>(v, ph, pl, b2, al2, k3);
+            if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
+            stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
+            if ((fl = check_point<D>(v, ph))) break;
+            velocity<D>(v, ph, pl, b4, al4, k4);
+            if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const float sum = (k1[a] + k4[a]) + 2.0f * (k2[a] + k3[a]);
+                const float inc = fmaf(sc.sh, sum, sc.sl * sum);
+                two_sum(xh[a], xl[a] + inc, nh[a], nl[a]);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                float sum = ab_num<S>(0) * k1[a];
+#pragma unroll
+                for (int j = 1; j < S; ++j) sum = fmaf(ab_num<S>(j), hist[j - 1][a], sum);
+                const float inc = fmaf(ch, sum, cl * sum);
+                two_sum(xh[a], xl[a] + inc, nh[a], nl[a]);
+            }
+        }
+        if ((fl = check_point<D>(v, nh))) break;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xh[a] = nh[a];
+            xl[a] = nl[a];
+            hist[2][a] = hist[1][a];
+            hist[1][a] = hist[0][a];
+            hist[0][a] = k1[a];
+        }
+    }
+    return fl;
+}
+
+template <int D, int S>
+__global__ LCS_ADVECT_BOUNDS void advect_ab_grid_kernel(AdvectArgs A)
+{
+    const int m = xcd_remap((int)blockIdx.x, A.g.n_blocks);
+    int sc[3];
+    const long long s = seed_of<D>(A.g, m, threadIdx.x, sc);
+    if (s < 0) return;
+    float xh[3], xl[3], x[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double x0 = A.g.s_origin[a] + (double)sc[a] * A.g.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+    uint32_t fl = check_point<D>(A.v, xh);
+    if (!fl) fl = advect_steps_ab<D, S>(A.v, xh, xl, A.t0, A.dt, A.nsteps);
+#pragma unroll
+    for (int a = 0; a < D; ++a) x[a] = xh[a] + xl[a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) A.xf[a * A.ns + s] = x[a];
+    if (A.cell) A.cell[s] = cell_index<D>(A.v, x);
+    if (A.flags) A.flags[s] = (uint8_t)fl;
+}
+
+// Auxiliary points (Sec. 2 Seed and Cauchy-Green filters): a block advects
+// point q = 2b + side of every seed of one tile, which starts at
+// x0 - delta_b e_b (side 0) or x0 + delta_b e_b (side 1), formed in FP64 and
+// carried as a two-float.  The 2*dim blocks of a tile are consecutive in the
+// XCD-remapped order, so they run together on one XCD and share its L2 (their
+// trajectories stay within about delta of each other).  Outputs keep the
+// two-float (hi, lo) so that the gradient can difference exact FP64 positions.
+template <int D>
+__global__ LCS_ADVECT_BOUNDS void advect_aux_kernel(AuxArgs A)
+{
+    const int r = xcd_remap((int)blockIdx.x, A.a.g.n_blocks * 2 * D);
+    const int m = r / (2 * D);
+    const int q = r - m * (2 * D);
+    const int b = q >> 1, side = q & 1;
+    int sc[3];
+    const long long s = seed_of<D>(A.a.g, m, threadIdx.x, sc);
+    if (s < 0) return;
+    float xh[3], xl[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double x0 = A.a.g.s_origin[a] + (double)sc[a] * A.a.g.s_spacing[a];
+        if (a == b) x0 = side ? x0 + A.delta[a] : x0 - A.delta[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+    const uint32_t fl = advect_tracer<D>(A.a.v, xh, xl, A.a.t0, A.a.dt, A.a.nsteps);
+    const long long ns = A.a.ns;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        A.xa_hi[((long long)a * 2 * D + q) * ns + s] = xh[a];
+        A.xa_lo[((long long)a * 2 * D + q) * ns + s] = xl[a];
+    }
+    if (A.a.flags) A.a.flags[(long long)q * ns + s] = (uint8_t)fl;
 }
 
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
@@ -731,6 +785,22 @@ __global__ __launch_bounds__(256) void scatter_kernel(SegmentArgs A, TracerState
 
 }  // namespace
 
+long long exclusive_scan_sums_needed(long long n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+// In-place exclusive prefix sum of n uint32 values; block_sums holds
+// exclusive_scan_sums_needed(n) values of scratch.
+hipError_t launch_exclusive_scan_u32(uint32_t *data, long long n, uint32_t *block_sums,
+                                     hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const long long nb = exclusive_scan_sums_needed(n);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(256), 0, s, data, n, block_sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, block_sums, nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, data,
+                       n, block_sums);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
@@ -758,12 +828,8 @@ hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
 hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s)
 {
     const long long nk = a.sk.n_keys;
-    const long long nb = (nk + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(256), 0, s, a.sk.counts, nk,
-                       a.sk.block_sums);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, a.sk.block_sums, nb);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
-                       a.sk.counts, nk, a.sk.block_sums);
+    const hipError_t e = launch_exclusive_scan_u32(a.sk.counts, nk, a.sk.block_sums, s);
+    if (e != hipSuccess) return e;
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     if (dim == 2) hipLaunchKernelGGL(scatter_kernel<2>, grid, block, 0, s, a, dst);
     else hipLaunchKernelGGL(scatter_kernel<3>, grid, block, 0, s, a, dst);
@@ -800,6 +866,29 @@ hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s)
         hipLaunchKernelGGL(advect_grid_kernel<2>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(advect_grid_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_ab(int dim, int order, const AdvectArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.g.n_blocks), block(256);
+    if (dim == 2) {
+        if (order == 2) hipLaunchKernelGGL((advect_ab_grid_kernel<2, 2>), grid, block, 0, s, a);
+        else if (order == 3) hipLaunchKernelGGL((advect_ab_grid_kernel<2, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((advect_ab_grid_kernel<2, 4>), grid, block, 0, s, a);
+    } else {
+        if (order == 2) hipLaunchKernelGGL((advect_ab_grid_kernel<3, 2>), grid, block, 0, s, a);
+        else if (order == 3) hipLaunchKernelGGL((advect_ab_grid_kernel<3, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((advect_ab_grid_kernel<3, 4>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)(a.a.g.n_blocks * 2 * dim)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(advect_aux_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(advect_aux_kernel<3>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

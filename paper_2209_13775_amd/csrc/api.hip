@@ -314,6 +314,102 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, d
     return lcs::clear_error();
 }
 
+lcs_status lcs_advect_ab(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, int32_t order,
+                         double t0, double T, double dt, float *xf, int64_t *cell, uint8_t *flags,
+                         void *stream)
+{
+    lcs_status st;
+    if (order < 2 || order > 4) return lcs::set_error(LCS_E_ARG, "order must be 2, 3 or 4");
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf) return lcs::set_error(LCS_E_ARG, "xf is NULL");
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + T;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                    vel->t_first, t_last);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    lcs::AdvectArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = make_vel(vel);
+    A.g = make_tiling(seeds);
+    A.t0 = t0;
+    A.dt = dt;
+    A.nsteps = nsteps;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.xf = xf;
+    A.cell = reinterpret_cast<long long *>(cell);
+    A.flags = flags;
+    hipError_t e = lcs::launch_advect_ab(vel->dim, order, A, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_ab launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_advect_aux(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                          const double *delta, double t0, double T, double dt, float *xa_hi,
+                          float *xa_lo, uint8_t *flags, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!delta) return lcs::set_error(LCS_E_ARG, "delta is NULL");
+    for (int a = 0; a < vel->dim; ++a)
+        if (!finite_pos(delta[a])) return lcs::set_error(LCS_E_ARG, "delta[%d] must be > 0", a);
+    if (!xa_hi || !xa_lo) return lcs::set_error(LCS_E_ARG, "xa_hi and xa_lo must not be NULL");
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + T;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                    vel->t_first, t_last);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    lcs::AuxArgs A;
+    memset(&A, 0, sizeof(A));
+    A.a.v = make_vel(vel);
+    A.a.g = make_tiling(seeds);
+    A.a.t0 = t0;
+    A.a.dt = dt;
+    A.a.nsteps = nsteps;
+    A.a.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.a.flags = flags;
+    for (int a = 0; a < vel->dim; ++a) A.delta[a] = delta[a];
+    A.xa_hi = xa_hi;
+    A.xa_lo = xa_lo;
+    hipError_t e = lcs::launch_advect_aux(vel->dim, A, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_aux launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_cg_aux(const lcs_seed_grid_t *seeds, const double *delta, const float *xa_hi,
+                      const float *xa_lo, const uint8_t *flags, double *C, uint8_t *stencil_flags,
+                      void *stream)
+{
+    if (!seeds) return lcs::set_error(LCS_E_ARG, "seed grid descriptor is NULL");
+    lcs_status st;
+    if ((st = check_seeds(seeds, seeds->dim)) != LCS_OK) return st;
+    if (seeds->dim != 2 && seeds->dim != 3) return lcs::set_error(LCS_E_ARG, "dim must be 2 or 3");
+    if (!delta) return lcs::set_error(LCS_E_ARG, "delta is NULL");
+    for (int a = 0; a < seeds->dim; ++a)
+        if (!finite_pos(delta[a])) return lcs::set_error(LCS_E_ARG, "delta[%d] must be > 0", a);
+    if (!xa_hi || !xa_lo || !C) return lcs::set_error(LCS_E_ARG, "xa_hi, xa_lo and C must not be NULL");
+    lcs::CgAuxArgs A;
+    memset(&A, 0, sizeof(A));
+    A.dim = seeds->dim;
+    A.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    for (int a = 0; a < seeds->dim; ++a) A.delta[a] = delta[a];
+    A.xa_hi = xa_hi;
+    A.xa_lo = xa_lo;
+    A.flags = flags;
+    A.C = C;
+    A.sflags = stencil_flags;
+    hipError_t e = lcs::launch_cg_aux(A, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "cg_aux launch");
+    return lcs::clear_error();
+}
+
 lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
                               const lcs_seed_grid_t *seeds, const lcs_window_t *windows,
                               int32_t n_windows, double dt, float *xf, int64_t *cell,

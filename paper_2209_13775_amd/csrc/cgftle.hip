@@ -109,6 +109,45 @@ __device__ __forceinline__ int nbr(int i, int dir, int n, bool per, double L, do
     return j;
 }
 
+// Flow-map gradient from auxiliary points: one thread per seed,
+//   J[a][b] = (F_a(x0 + delta_b e_b) - F_a(x0 - delta_b e_b)) / (2 delta_b),
+// with each final position hi + lo summed exactly in FP64; C = J^T J packed.
+// No contraction, so identical positions give the oracle's C bit for bit.
+template <int D>
+__global__ __launch_bounds__(256) void cg_aux_kernel(CgAuxArgs A)
+{
+#pragma clang fp contract(off)
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.ns) return;
+    const long long ns = A.ns;
+    double J[3][3];
+    uint8_t bad = 0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        const int qm = 2 * b, qp = 2 * b + 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const long long im = ((long long)a * 2 * D + qm) * ns + p;
+            const long long ip = ((long long)a * 2 * D + qp) * ns + p;
+            const double xm = (double)A.xa_hi[im] + (double)A.xa_lo[im];
+            const double xp = (double)A.xa_hi[ip] + (double)A.xa_lo[ip];
+            J[a][b] = (xp - xm) / (2.0 * A.delta[b]);
+        }
+        if (A.flags && (A.flags[(long long)qm * ns + p] || A.flags[(long long)qp * ns + p])) bad = 1;
+    }
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int c = r; c < D; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) acc += J[a][r] * J[a][c];
+            A.C[(long long)(k++) * ns + p] = acc;
+        }
+    if (A.sflags) A.sflags[p] = bad ? (uint8_t)LCS_FLAG_STENCIL_OUT : (uint8_t)0;
+}
+
 template <int D, bool FUSED>
 __global__ __launch_bounds__(256) void cg_kernel(CgArgs A)
 {
@@ -244,6 +283,14 @@ __global__ __launch_bounds__(256) void ftle_kernel(FtleArgs A)
 }
 
 }  // namespace
+
+hipError_t launch_cg_aux(const CgAuxArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.ns + 255) / 256)), block(256);
+    if (a.dim == 2) hipLaunchKernelGGL(cg_aux_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(cg_aux_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_cg(const CgArgs &a, bool fused, hipStream_t s)
 {

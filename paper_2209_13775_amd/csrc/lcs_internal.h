@@ -79,6 +79,25 @@ struct CgArgs {
     double inv_two_T;         // 1 / (2|T|)
 };
 
+// Auxiliary-point advection: the seed tiling of `a` times 2*dim points.
+struct AuxArgs {
+    AdvectArgs a;
+    double delta[3];
+    float *xa_hi;             // [dim][2*dim][Ns]
+    float *xa_lo;
+};
+
+struct CgAuxArgs {
+    int dim;
+    long long ns;
+    double delta[3];
+    const float *xa_hi;
+    const float *xa_lo;
+    const uint8_t *flags;     // [2*dim][Ns] or null
+    double *C;
+    uint8_t *sflags;
+};
+
 struct FtleArgs {
     long long n;
     const double *C;
@@ -269,6 +288,9 @@ hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s);
 hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s);
 hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
+long long exclusive_scan_sums_needed(long long n);
+hipError_t launch_exclusive_scan_u32(uint32_t *data, long long n, uint32_t *block_sums,
+                                     hipStream_t s);
 
 // host-side validation and descriptor conversion (api.hip)
 lcs_status validate_velocity(const lcs_velocity_t *v);
@@ -284,11 +306,91 @@ lcs_status clear_error();
 lcs_status hip_error(hipError_t e, const char *where);
 
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
+hipError_t launch_advect_ab(int dim, int order, const AdvectArgs &a, hipStream_t s);
+hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s);
+hipError_t launch_cg_aux(const CgAuxArgs &a, hipStream_t s);
 hipError_t launch_reset_counter(int *counter, hipStream_t s);
 hipError_t launch_advect_batched(int dim, const BatchArgs &a, int grid_blocks, hipStream_t s);
 int batched_blocks_per_cu(int dim);
 hipError_t launch_advect_points(int dim, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_cg(const CgArgs &a, bool fused, hipStream_t s);
 hipError_t launch_ftle(int dim, const FtleArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Unstructured meshes (triangles / tetrahedra)
+// ---------------------------------------------------------------------------
+// Per-cell affine map to barycentric coordinates, relative to an FP32
+// reference point r (the FP32 rounding of vertex 0) with an offset c that
+// carries the FP64 difference r - v0:
+//   lambda_{k+1} = M_k . (x - r) + c_k  (k < dim),  lambda_0 = 1 - sum_k lambda_{k+1}.
+// 3D, 4 float4 per cell: (r.xyz, c0), (M0.xyz, c1), (M1.xyz, c2), (M2.xyz, 0)
+// 2D, 2 float4 per cell: (r.xy, c0, c1), (M0.xy, M1.xy)
+template <int D> struct MeshGeo { static constexpr int G = (D == 3) ? 4 : 2; };
+
+struct MeshDev {
+    const float4 *geo;        // [n_cells][G]
+    const int4 *nbr;          // [n_cells] neighbour across the face opposite vertex i (-1 boundary)
+    const int4 *conn;         // [n_cells] node ids (.w = -1 in 2D)
+    const int *loc;           // [nb0*nb1*nb2] first-location start cell per bucket (-1 none)
+    int nb[3];
+    float lo[3];
+    float inv_bs[3];
+    float eps;
+    int max_walk;
+};
+
+struct MeshFramesDev {
+    const float *u;           // [n_frames][n_nodes][S]
+    long long frame_stride;   // n_nodes * S floats
+    int n_frames;
+    double t_first;
+    double inv_dt_frame;
+    double t_last;
+};
+
+struct MeshAdvectArgs {
+    MeshDev m;
+    MeshFramesDev f;
+    SeedTiling g;             // seed-grid mode
+    double t0, dt;
+    int nsteps;
+    long long ns;
+    float *xf;
+    long long *cell;
+    uint8_t *flags;
+    const float *x0;          // points mode
+    const double *t0v;
+    double T;
+};
+
+struct MeshLocGrid {          // bucket grid in FP64 (built once)
+    double lo[3];
+    double bs[3];
+    int nb[3];
+};
+
+// mesh preparation (error bits: 1 node id out of range, 2 degenerate cell,
+// 4 face shared by more than two cells)
+hipError_t launch_mesh_degree(int dim, const int32_t *cells, long long n_cells, long long n_nodes,
+                              uint32_t *deg, int *err, hipStream_t s);
+hipError_t launch_mesh_adjacency(int dim, const int32_t *cells, long long n_cells,
+                                 long long n_nodes, uint32_t *off, int32_t *adj, hipStream_t s);
+hipError_t launch_mesh_cells(int dim, const double *nodes, const int32_t *cells, long long n_cells,
+                             const uint32_t *off, const int32_t *adj, float4 *geo, int4 *nbr,
+                             int4 *conn, int *err, unsigned long long *n_boundary, hipStream_t s);
+hipError_t launch_mesh_bbox(int dim, const double *nodes, long long n_nodes, double *part,
+                            int n_parts, double *out, hipStream_t s);
+hipError_t launch_mesh_raster(int dim, const double *nodes, const int32_t *cells, long long n_cells,
+                              const MeshLocGrid &g, int *contain, int *touch, hipStream_t s);
+hipError_t launch_mesh_locator_finish(const int *contain, const int *touch, long long n,
+                                      int *loc, hipStream_t s);
+// queries and advection
+hipError_t launch_mesh_locate(int dim, const MeshDev &m, const float *x, long long n,
+                              long long *cell, float *lam, hipStream_t s);
+hipError_t launch_mesh_velocity(int dim, const MeshDev &m, const MeshFramesDev &f, const float *x,
+                                const double *t, long long n, float *u, long long *cell,
+                                hipStream_t s);
+hipError_t launch_mesh_advect(int dim, const MeshAdvectArgs &a, hipStream_t s);
+hipError_t launch_mesh_advect_points(int dim, const MeshAdvectArgs &a, hipStream_t s);
 
 }  // namespace lcs

@@ -90,11 +90,22 @@ def _load(path: str = LIB_PATH):
         "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
         "lcs_sub": [P, P, I64, P, P],
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
+        "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
+        "lcs_advect_aux": [P, P, P, D, D, D, P, P, P, P],
+        "lcs_cg_aux": [P, P, P, P, P, P, P, P],
+        "lcs_mesh_create": [P, P, P],
+        "lcs_mesh_info": [P, P],
+        "lcs_mesh_locate": [P, P, I64, P, P, P],
+        "lcs_mesh_velocity_at": [P, P, P, P, I64, P, P, P],
+        "lcs_mesh_advect": [P, P, P, D, D, D, P, P, P, P],
+        "lcs_mesh_advect_points": [P, P, P, P, I64, D, D, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
         fn.restype = C.c_int
         fn.argtypes = args
+    L.lcs_mesh_destroy.restype = None
+    L.lcs_mesh_destroy.argtypes = [P]
     L.lcs_last_error.restype = C.c_char_p
     L.lcs_last_error.argtypes = []
     L.lcs_version.restype = C.c_int32
@@ -252,6 +263,76 @@ def lcs_advect(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
     _check(_lib.lcs_advect(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
                            _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
     return xf, cell, flags
+
+
+def lcs_advect_ab(frames: DeviceFrames, seeds, t0: float, T: float, dt: float, order: int = 4,
+                  xf=None, cell=None, flags=None, want_cell=True, want_flags=True, stream=None):
+    """Adams-Bashforth (order 2-4, RK4 start-up) flow map of a seed grid."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_ab(frames.ref, C.byref(sd), int(order), float(t0), float(T), float(dt),
+                              _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_advect_aux(frames: DeviceFrames, seeds, delta, t0: float, T: float, dt: float,
+                   xa_hi=None, xa_lo=None, flags=None, want_flags=True, stream=None):
+    """Flow map of the 2*dim auxiliary points x0 -+ delta_b e_b of every seed:
+    (xa_hi, xa_lo, flags), positions [dim][2*dim][Ns] as two-floats."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xa_hi is None:
+        xa_hi = torch.empty((d, 2 * d, ns), dtype=torch.float32, device=dev)
+    if xa_lo is None:
+        xa_lo = torch.empty((d, 2 * d, ns), dtype=torch.float32, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty((2 * d, ns), dtype=torch.uint8, device=dev)
+    _need(xa_hi, torch.float32, (d, 2 * d, ns), "xa_hi")
+    _need(xa_lo, torch.float32, (d, 2 * d, ns), "xa_lo")
+    _need(flags, torch.uint8, (2 * d, ns), "flags")
+    dl = (C.c_double * 3)(*([float(x) for x in delta] + [0.0] * (3 - len(delta))))
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_aux(frames.ref, C.byref(sd), dl, float(t0), float(T), float(dt),
+                               _ptr(xa_hi), _ptr(xa_lo), _ptr(flags), _stream_handle(stream)))
+    return xa_hi, xa_lo, flags
+
+
+def lcs_cg_aux(seeds, delta, xa_hi, xa_lo, flags=None, C_out=None, stencil_flags=None,
+               want_stencil=True, stream=None):
+    """C (packed, FP64) and stencil flags from auxiliary-point positions."""
+    torch = _torch()
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    dev = xa_hi.device
+    _need(xa_hi, torch.float32, (d, 2 * d, ns), "xa_hi")
+    _need(xa_lo, torch.float32, (d, 2 * d, ns), "xa_lo")
+    _need(flags, torch.uint8, (2 * d, ns), "flags")
+    nq = d * (d + 1) // 2
+    if C_out is None:
+        C_out = torch.empty((nq, ns), dtype=torch.float64, device=dev)
+    if stencil_flags is None and want_stencil:
+        stencil_flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(C_out, torch.float64, (nq, ns), "C")
+    _need(stencil_flags, torch.uint8, (ns,), "stencil_flags")
+    dl = (C.c_double * 3)(*([float(x) for x in delta] + [0.0] * (3 - len(delta))))
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_cg_aux(C.byref(sd), dl, _ptr(xa_hi), _ptr(xa_lo), _ptr(flags), _ptr(C_out),
+                           _ptr(stencil_flags), _stream_handle(stream)))
+    return C_out, stencil_flags
 
 
 def lcs_advect_sorted_workspace_bytes(frames: DeviceFrames, seeds) -> int:
@@ -623,3 +704,178 @@ def lcs_sub(a, b, out=None, stream=None):
     _need(out, torch.float32, tuple(a.shape), "out")
     _check(_lib.lcs_sub(_ptr(a), _ptr(b), int(a.numel()), _ptr(out), _stream_handle(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Unstructured meshes
+# ---------------------------------------------------------------------------
+
+LCS_FLAG_LOST = 16
+
+
+class lcs_mesh_desc_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("reserved", C.c_int32), ("n_nodes", C.c_int64),
+                ("n_cells", C.c_int64), ("nodes", C.c_void_p), ("cells", C.c_void_p)]
+
+
+class lcs_mesh_info_t(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("reserved", C.c_int32), ("n_nodes", C.c_int64),
+                ("n_cells", C.c_int64), ("n_boundary_faces", C.c_int64),
+                ("buckets", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("device_bytes", C.c_int64)]
+
+
+class lcs_mesh_frames_t(C.Structure):
+    _fields_ = [("n_frames", C.c_int32), ("reserved", C.c_int32), ("t_first", C.c_double),
+                ("dt_frame", C.c_double), ("u", C.c_void_p)]
+
+
+class Mesh:
+    """Device mesh object (lcs_mesh_create) built from a host mesh with
+    ``dim``, ``nodes`` (n_nodes x dim) and ``cells`` (n_cells x dim+1)."""
+
+    def __init__(self, mesh, device="cuda", stream=None):
+        torch = _torch()
+        self.dim = int(mesh.dim)
+        nodes = torch.from_numpy(np.ascontiguousarray(mesh.nodes, dtype=np.float64)).to(device)
+        cells = torch.from_numpy(np.ascontiguousarray(mesh.cells, dtype=np.int32)).to(device)
+        d = lcs_mesh_desc_t()
+        d.dim = self.dim
+        d.reserved = 0
+        d.n_nodes = int(nodes.shape[0])
+        d.n_cells = int(cells.shape[0])
+        d.nodes = nodes.data_ptr()
+        d.cells = cells.data_ptr()
+        self.n_nodes = int(d.n_nodes)
+        self.n_cells = int(d.n_cells)
+        self.device = nodes.device
+        h = C.c_void_p()
+        _check(_lib.lcs_mesh_create(C.byref(d), C.byref(h), _stream_handle(stream)))
+        self.h = h
+
+    def info(self) -> dict:
+        i = lcs_mesh_info_t()
+        _check(_lib.lcs_mesh_info(self.h, C.byref(i)))
+        return dict(dim=i.dim, n_nodes=i.n_nodes, n_cells=i.n_cells,
+                    n_boundary_faces=i.n_boundary_faces, buckets=list(i.buckets),
+                    lo=list(i.lo), hi=list(i.hi), device_bytes=i.device_bytes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.lcs_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MeshFrames:
+    """Nodal velocity frames of a mesh in the layout lcs_mesh_frames_t reads:
+    [n_frames][n_nodes][S] FP32, S = 4 in 3D (one unused value), 2 in 2D."""
+
+    def __init__(self, mf, device="cuda", tensor=None):
+        torch = _torch()
+        dim = mf.mesh.dim
+        S = 4 if dim == 3 else 2
+        if tensor is None:
+            a = np.zeros((mf.n_frames, mf.mesh.n_nodes, S), dtype=np.float32)
+            a[..., :dim] = mf.u
+            tensor = torch.from_numpy(a).to(device)
+        _need(tensor, torch.float32, (mf.n_frames, mf.mesh.n_nodes, S), "mesh frames")
+        self.u = tensor
+        self.mf = mf
+        d = lcs_mesh_frames_t()
+        d.n_frames = int(mf.n_frames)
+        d.reserved = 0
+        d.t_first = float(mf.t_first)
+        d.dt_frame = float(mf.dt_frame)
+        d.u = tensor.data_ptr()
+        self.desc = d
+
+    @property
+    def ref(self):
+        return C.byref(self.desc)
+
+
+def lcs_mesh_locate(mesh: Mesh, x, cell=None, lam=None, want_lam=True, stream=None):
+    """Cell (int64; -1 outside, -2 search limit) and barycentric coordinates of points x (dim x n)."""
+    torch = _torch()
+    d, n = mesh.dim, int(x.shape[1])
+    _need(x, torch.float32, (d, n), "x")
+    if cell is None:
+        cell = torch.empty(n, dtype=torch.int64, device=x.device)
+    if lam is None and want_lam:
+        lam = torch.empty((d + 1, n), dtype=torch.float32, device=x.device)
+    _need(cell, torch.int64, (n,), "cell")
+    _need(lam, torch.float32, (d + 1, n), "lam")
+    _check(_lib.lcs_mesh_locate(mesh.h, _ptr(x), n, _ptr(cell), _ptr(lam), _stream_handle(stream)))
+    return cell, lam
+
+
+def lcs_mesh_velocity_at(mesh: Mesh, frames: MeshFrames, x, t, u=None, cell=None, stream=None):
+    """u(x, t) on the mesh (NaN outside) and the cell of every point."""
+    torch = _torch()
+    d, n = mesh.dim, int(x.shape[1])
+    _need(x, torch.float32, (d, n), "x")
+    if not isinstance(t, torch.Tensor):
+        t = torch.full((n,), float(t), dtype=torch.float64, device=x.device)
+    _need(t, torch.float64, (n,), "t")
+    if u is None:
+        u = torch.empty((d, n), dtype=torch.float32, device=x.device)
+    if cell is None:
+        cell = torch.empty(n, dtype=torch.int64, device=x.device)
+    _need(u, torch.float32, (d, n), "u")
+    _need(cell, torch.int64, (n,), "cell")
+    _check(_lib.lcs_mesh_velocity_at(mesh.h, frames.ref, _ptr(x), _ptr(t), n, _ptr(u), _ptr(cell),
+                                     _stream_handle(stream)))
+    return u, cell
+
+
+def lcs_mesh_advect(mesh: Mesh, frames: MeshFrames, seeds, t0: float, T: float, dt: float,
+                    xf=None, cell=None, flags=None, want_cell=True, want_flags=True, stream=None):
+    """Flow map of a (non-periodic) seed grid through mesh velocity frames."""
+    torch = _torch()
+    dev = frames.u.device
+    d = mesh.dim
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_mesh_advect(mesh.h, frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                                _ptr(xf), _ptr(cell), _ptr(flags), _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_mesh_advect_points(mesh: Mesh, frames: MeshFrames, x0, t0, T: float, dt: float, xf=None,
+                           cell=None, flags=None, want_cell=True, want_flags=True, stream=None):
+    """Flow map of points x0 (dim x n, FP32) with start times t0 (FP64) on the mesh."""
+    torch = _torch()
+    d, n = mesh.dim, int(x0.shape[1])
+    dev = x0.device
+    if not isinstance(t0, torch.Tensor):
+        t0 = torch.full((n,), float(t0), dtype=torch.float64, device=dev)
+    if xf is None:
+        xf = torch.empty((d, n), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(n, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(n, dtype=torch.uint8, device=dev)
+    _need(x0, torch.float32, (d, n), "x0")
+    _need(t0, torch.float64, (n,), "t0")
+    _need(xf, torch.float32, (d, n), "xf")
+    _need(cell, torch.int64, (n,), "cell")
+    _need(flags, torch.uint8, (n,), "flags")
+    _check(_lib.lcs_mesh_advect_points(mesh.h, frames.ref, _ptr(x0), _ptr(t0), n, float(T),
+                                       float(dt), _ptr(xf), _ptr(cell), _ptr(flags),
+                                       _stream_handle(stream)))
+    return xf, cell, flags

@@ -110,3 +110,34 @@ def oracle_sampled_ftle(orc, vel, g, idx, t0, T, dt):
     sel = np.array([pos[int(s)] for s in idx])
     return dict(xf=xf[:, sel], cell=cell[sel], flags=flags[sel], margin=margin[sel],
                 lam=lam, ftle=sig, stencil_bad=bad)
+
+
+def oracle_sampled_ftle_mesh(mv, g, idx, t0, T, dt):
+    """As oracle_sampled_ftle, for velocity on a mesh (oracle MeshVelocity)."""
+    import oracle as orc
+    c, im, ip = neighbour_indices(g, idx)
+    allidx = np.unique(np.concatenate([idx] + im + ip))
+    xf, cell, flags, margin, lam_margin = mv.advect_seeds(g, t0, T, dt, idx=allidx)
+    pos = {int(k): p for p, k in enumerate(allidx)}
+    C = np.empty((g.dim * (g.dim + 1) // 2, idx.size))
+    bad = np.zeros(idx.size, dtype=bool)
+    for q, s in enumerate(idx):
+        ps = pos[int(s)]
+        xm = [xf[:, pos[int(im[b][q])]] for b in range(g.dim)]
+        xp = [xf[:, pos[int(ip[b][q])]] for b in range(g.dim)]
+        C[:, q] = orc.cg_point(g, c[:, q], xf[:, ps], xm, xp)
+        used = [ps] + [pos[int(im[b][q])] for b in range(g.dim)] + [pos[int(ip[b][q])] for b in range(g.dim)]
+        bad[q] = bool(np.any(flags[used]))
+    lam, sig = orc.ftle(g.dim, C, T)
+    sel = np.array([pos[int(s)] for s in idx])
+    return dict(xf=xf[:, sel], cell=cell[sel], flags=flags[sel], margin=margin[sel],
+                lam_margin=lam_margin[sel], lam=lam, ftle=sig, stencil_bad=bad)
+
+
+def mesh_barycentric(mesh, cell: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """FP64 barycentric coordinates (dim+1, m) of points x (dim, m) in the
+    given cells of a host mesh, by a linear solve per point."""
+    v = mesh.nodes[mesh.cells[cell]]                       # (m, dim+1, dim)
+    E = np.transpose(v[:, 1:, :] - v[:, :1, :], (0, 2, 1))
+    mu = np.linalg.solve(E, (x.T - v[:, 0, :])[..., None])[..., 0]
+    return np.concatenate([1.0 - mu.sum(axis=1, keepdims=True), mu], axis=1).T

@@ -135,3 +135,38 @@ def test_batched_validation():
                                 None, None) == lcs.LCS_E_STEP
     assert L.lcs_plan_create(None) == lcs.LCS_E_ARG
     assert L.lcs_plan_destroy(None) == lcs.LCS_OK
+
+
+def test_mesh_entry_points_validate():
+    """Mesh calls reject bad arguments on the host, before any device work."""
+    L = lcs.lib()
+    d = lcs.lcs_mesh_desc_t()
+    out = C.c_void_p()
+    assert L.lcs_mesh_create(None, C.byref(out), None) == lcs.LCS_E_ARG
+    assert L.lcs_mesh_create(C.byref(d), None, None) == lcs.LCS_E_ARG
+    d.dim, d.n_nodes, d.n_cells, d.nodes, d.cells = 4, 4, 1, 0x10, 0x20
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_ARG
+    d.dim = 3
+    d.reserved = 1
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_ARG
+    d.reserved = 0
+    d.n_nodes = 0
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_SHAPE
+    d.n_nodes, d.n_cells = 1 << 28, 1
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_SHAPE
+    d.n_nodes, d.n_cells = 4, 1 << 30
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_SHAPE
+    d.n_cells, d.cells = 1, None
+    assert L.lcs_mesh_create(C.byref(d), C.byref(out), None) == lcs.LCS_E_ARG
+    assert out.value is None
+    info = lcs.lcs_mesh_info_t()
+    assert L.lcs_mesh_info(None, C.byref(info)) == lcs.LCS_E_ARG
+    f = lcs.lcs_mesh_frames_t()
+    s = lcs.lcs_seed_grid_t()
+    assert L.lcs_mesh_advect(None, C.byref(f), C.byref(s), 0.0, 1.0, 0.1, 0x10, None, None,
+                             None) == lcs.LCS_E_ARG
+    assert L.lcs_mesh_advect_points(None, C.byref(f), 0x10, 0x20, 4, 1.0, 0.1, 0x30, None, None,
+                                    None) == lcs.LCS_E_ARG
+    assert L.lcs_mesh_locate(None, 0x10, 4, 0x20, None, None) == lcs.LCS_E_ARG
+    assert L.lcs_mesh_velocity_at(None, C.byref(f), 0x10, 0x20, 4, 0x30, None, None) == lcs.LCS_E_ARG
+    L.lcs_mesh_destroy(None)
