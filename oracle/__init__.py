@@ -75,6 +75,9 @@ def lib():
             "orc_ftle": (None, [C.c_int, I64, P, D, P, P, C.c_int]),
             "orc_max_threads": (C.c_int, []),
             "orc_aux_points": (None, [P, P, I64, P, P]),
+            "orc_eig_many": (None, [C.c_int, I64, P, P, P]),
+            "orc_advect_seeds_snap": (None, [P, P, P, I64, D, D, C.c_int, P, P, P, P, C.c_int]),
+            "orc_ftle_early": (None, [P, P, P, I64, D, D, P, P, P, P, C.c_int]),
             "orc_cg_aux": (None, [C.c_int, I64, P, P, P, P, P]),
             "orc_advect_seeds_ab": (None, [P, P, P, I64, D, D, D, C.c_int, P, P, P, P, C.c_int]),
             "orc_advect_points_ab": (None, [P, P, P, I64, D, D, C.c_int, P, P, P, P, C.c_int]),
@@ -337,6 +340,57 @@ def lambda_max(dim: int, Cpacked: np.ndarray) -> float:
     c = np.zeros(6)
     c[: dim * (dim + 1) // 2] = Cpacked
     return float(lib().orc_lambda_max(dim, _ptr(c)))
+
+
+def advect_seeds_snap(vel: Velocity, g, t0: float, dt: float, snap_steps, idx=None,
+                      threads=None):
+    """Positions after each of snap_steps RK4 steps: (xf (n_snap, dim, m),
+    flags (n_snap, m), steps_done (m,))."""
+    sg = _seeds(g)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+    else:
+        m = g.count
+    st = np.ascontiguousarray(snap_steps, dtype=np.int64)
+    assert st.size >= 1 and st[0] >= 1 and np.all(np.diff(st) > 0)
+    xf = np.empty((st.size, g.dim, m))
+    fl = np.empty((st.size, m), dtype=np.uint8)
+    done = np.empty(m, dtype=np.int64)
+    lib().orc_advect_seeds_snap(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(dt),
+                                int(st.size), _ptr(st), _ptr(xf), _ptr(fl), _ptr(done),
+                                threads or default_threads())
+    return xf, fl, done
+
+
+def ftle_early(vel: Velocity, g, t0: float, dt: float, steps_done, idx=None, threads=None):
+    """(lambda_max, ftle, t_eff) with early evaluation for seeds whose stencil
+    left the domain, at the seeds idx (all if None); steps_done covers every seed."""
+    sg = _seeds(g)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        m = idx.size
+    else:
+        m = g.count
+    done = np.ascontiguousarray(steps_done, dtype=np.int64)
+    assert done.size == g.count
+    lam = np.empty(m)
+    sig = np.empty(m)
+    te = np.empty(m)
+    lib().orc_ftle_early(vel.ref, C.byref(sg), _ptr(idx), m, float(t0), float(dt), _ptr(done),
+                         _ptr(lam), _ptr(sig), _ptr(te), threads or default_threads())
+    return lam, sig, te
+
+
+def eig(dim: int, Cm: np.ndarray):
+    """(evals (dim x n) ascending, evecs (dim, dim, n): evecs[k, a] = component a
+    of eigenvector k, sign-normalised) of packed symmetric tensors (nq x n)."""
+    Cm = np.ascontiguousarray(Cm, dtype=np.float64)
+    n = Cm.shape[1]
+    ev = np.empty((dim, n))
+    V = np.empty((dim, dim, n))
+    lib().orc_eig_many(dim, n, _ptr(Cm), _ptr(ev), _ptr(V))
+    return ev, V
 
 
 def ftle(dim: int, Cm: np.ndarray, T: float, threads=None):

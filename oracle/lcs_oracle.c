@@ -74,6 +74,11 @@ typedef struct {
 
 static int axis_periodic(uint32_t mask, int a) { return (int)((mask >> a) & 1u); }
 
+/* defined with the gradient and eigenvalue code below */
+void orc_cg_point(const orc_seed_grid *g, const int64_t *ijk, const double *xc,
+                  const double *const *xm, const double *const *xp, double *Cpacked);
+double orc_lambda_max(int dim, const double *Cpacked);
+
 /* ------------------------------------------------------------------------ */
 /* Spatial location (reading: cell of a point along one axis)                */
 /* ------------------------------------------------------------------------ */
@@ -399,6 +404,133 @@ void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64
             for (int a = 0; a < v->dim; ++a) xf[a * m + p] = x[a];
         if (cell) cell[p] = orc_cell_index(v, x);
         if (flags) flags[p] = (uint8_t)fl;
+    }
+    (void)nthreads;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time-resolved and early Cauchy-Green evaluation                            */
+/* ------------------------------------------------------------------------ */
+
+/* Flow map at several integration times (Sec. 3.1: the CG tensor can be
+ * evaluated at any step of the interval; Sec. 4: the CG tensor at various
+ * times).  snap_steps (n_snap values, strictly increasing, >= 1): the step
+ * counts at which positions are recorded; xf[(k*dim + a)*m + p] and
+ * flags[k*m + p] hold snapshot k (a tracer frozen earlier keeps its frozen
+ * position and its flag); steps_done[p] = accepted steps before the tracer
+ * froze (the last snapshot's step count if it never did). */
+void orc_advect_seeds_snap(const orc_velocity *v, const orc_seed_grid *g, const int64_t *idx,
+                           int64_t m, double t0, double dt, int n_snap, const int64_t *snap_steps,
+                           double *xf, uint8_t *flags, int64_t *steps_done, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < m; ++p) {
+        double x[3] = {0, 0, 0};
+        seed_position(g, idx ? idx[p] : p, x);
+        uint32_t fl = check_point(v, x, NULL);
+        int64_t nacc = 0;
+        int k = 0;
+        int64_t last = snap_steps[n_snap - 1];
+        for (int64_t n = 0; n < last; ++n) {
+            if (!fl) {
+                fl = rk4_step(v, x, t0 + (double)n * dt, dt, NULL);
+                if (!fl) nacc = n + 1;
+            }
+            if (n + 1 == snap_steps[k]) {
+                for (int a = 0; a < v->dim; ++a) xf[((int64_t)k * v->dim + a) * m + p] = x[a];
+                flags[(int64_t)k * m + p] = (uint8_t)fl;
+                ++k;
+            }
+        }
+        if (steps_done) steps_done[p] = nacc;
+    }
+    (void)nthreads;
+}
+
+/* Seeds whose final positions the gradient at seed (ijk) uses (the seed itself
+ * and its lower/upper neighbours along each axis, as orc_cg_point differences
+ * them); returns their count and writes their linear indices. */
+static int stencil_members(const orc_seed_grid *g, const int64_t *ijk, int64_t *out)
+{
+    int k = 0;
+    out[k++] = ijk[0] + g->n[0] * (ijk[1] + g->n[1] * ijk[2]);
+    for (int b = 0; b < g->dim; ++b) {
+        int64_t n = g->n[b];
+        int per = axis_periodic(g->periodic_mask, b);
+        for (int dir = -1; dir <= 1; dir += 2) {
+            int64_t c[3] = {ijk[0], ijk[1], ijk[2]};
+            int64_t j = c[b] + dir;
+            if (per) j = (j + n) % n;
+            else if (j < 0 || j >= n) continue;   /* one-sided: the seed itself */
+            c[b] = j;
+            out[k++] = c[0] + g->n[0] * (c[1] + g->n[1] * c[2]);
+        }
+    }
+    return k;
+}
+
+/* Early evaluation (Sec. 2 Flow Map filter: when a trajectory leaves the
+ * domain, the CG tensor is evaluated early at every location that relies on
+ * it).  Reading: for seed s, n_s = the smallest steps_done over the seeds its
+ * gradient uses; its members are advected n_s steps from t0, C is formed from
+ * those positions by orc_cg_point and sigma = ln(lambda_max) / (2 n_s |dt|),
+ * t_eff = n_s dt.  n_s = 0 gives NaN.  For seeds whose stencil never left,
+ * n_s = nsteps and the result is the ordinary FTLE.  Outputs for the seeds
+ * idx (all if NULL, m = seed count); lam, ftle, t_eff may be NULL. */
+void orc_ftle_early(const orc_velocity *v, const orc_seed_grid *g, const int64_t *idx, int64_t m,
+                    double t0, double dt, const int64_t *steps_done, double *lam, double *ftle,
+                    double *t_eff, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+#endif
+    for (int64_t p = 0; p < m; ++p) {
+        int64_t s = idx ? idx[p] : p;
+        int64_t ijk[3] = {s % g->n[0], (s / g->n[0]) % g->n[1], s / (g->n[0] * g->n[1])};
+        int64_t mem[7];
+        int nm = stencil_members(g, ijk, mem);
+        int64_t ns = steps_done[mem[0]];
+        for (int q = 1; q < nm; ++q)
+            if (steps_done[mem[q]] < ns) ns = steps_done[mem[q]];
+        double l = NAN, f = NAN;
+        if (ns > 0) {
+            /* positions of the seed and its neighbours after ns steps */
+            double xc[3] = {0, 0, 0}, xmv[3][3], xpv[3][3];
+            const double *xm[3], *xp[3];
+            seed_position(g, s, xc);
+            advect_one(v, xc, t0, ns, dt, NULL);
+            for (int b = 0; b < g->dim; ++b) {
+                for (int side = 0; side < 2; ++side) {
+                    int64_t c[3] = {ijk[0], ijk[1], ijk[2]};
+                    int64_t n = g->n[b];
+                    int64_t j = c[b] + (side ? 1 : -1);
+                    double *dst = side ? xpv[b] : xmv[b];
+                    if (axis_periodic(g->periodic_mask, b)) j = (j + n) % n;
+                    if (j < 0 || j >= n) {          /* unused by the one-sided formula */
+                        for (int a = 0; a < 3; ++a) dst[a] = xc[a];
+                        continue;
+                    }
+                    c[b] = j;
+                    double x[3] = {0, 0, 0};
+                    seed_position(g, c[0] + g->n[0] * (c[1] + g->n[1] * c[2]), x);
+                    advect_one(v, x, t0, ns, dt, NULL);
+                    for (int a = 0; a < 3; ++a) dst[a] = x[a];
+                }
+                xm[b] = xmv[b];
+                xp[b] = xpv[b];
+            }
+            double C[6];
+            orc_cg_point(g, ijk, xc, xm, xp, C);
+            l = orc_lambda_max(g->dim, C);
+            f = (l > 0.0) ? log(l) / (2.0 * fabs((double)ns * dt)) : -INFINITY;
+        }
+        if (lam) lam[p] = l;
+        if (ftle) ftle[p] = f;
+        if (t_eff) t_eff[p] = (double)ns * dt;
     }
     (void)nthreads;
 }
@@ -764,6 +896,99 @@ static double eig_max_sym3(const double *c)
 double orc_lambda_max(int dim, const double *Cpacked)
 {
     return dim == 2 ? eig_max_sym2(Cpacked) : eig_max_sym3(Cpacked);
+}
+
+/* Eigenvalues and eigenvectors of the symmetric C (Sec. 2 Cauchy-Green filter:
+ * eigenvalue/eigenvector fields for LCS detection).  Cyclic Jacobi on the
+ * dim x dim matrix with the rotations accumulated, V <- V R, each product formed
+ * explicitly; then the pairs are sorted by ascending eigenvalue and every
+ * eigenvector is normalised in sign so that its component of largest magnitude
+ * (the first such on a tie) is positive -- the reading that makes the otherwise
+ * sign-free eigenvectors comparable.  evals[k], evecs[k*dim + a] = component a
+ * of eigenvector k. */
+void orc_eig_sym(int dim, const double *c, double *evals, double *evecs)
+{
+    double A[3][3] = {{0}}, V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    int k = 0;
+    for (int i = 0; i < dim; ++i)
+        for (int j = i; j < dim; ++j) A[i][j] = A[j][i] = c[k++];
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < dim; ++i) {
+            dia += A[i][i] * A[i][i];
+            for (int j = i + 1; j < dim; ++j) off += A[i][j] * A[i][j];
+        }
+        if (off == 0.0 || off <= 1e-36 * dia) break;
+        for (int p = 0; p < dim; ++p)
+            for (int q = p + 1; q < dim; ++q) {
+                if (A[p][q] == 0.0) continue;
+                double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (tau >= 0.0) ? 1.0 / (tau + hypot(1.0, tau))
+                                        : 1.0 / (tau - hypot(1.0, tau));
+                double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+                double R[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+                R[p][p] = cs;
+                R[q][q] = cs;
+                R[p][q] = sn;
+                R[q][p] = -sn;
+                double T1[3][3], B[3][3], W[3][3];
+                for (int i = 0; i < dim; ++i)
+                    for (int j = 0; j < dim; ++j) {
+                        double a1 = 0.0, a2 = 0.0;
+                        for (int m = 0; m < dim; ++m) {
+                            a1 += A[i][m] * R[m][j];
+                            a2 += V[i][m] * R[m][j];
+                        }
+                        T1[i][j] = a1;
+                        W[i][j] = a2;
+                    }
+                for (int i = 0; i < dim; ++i)
+                    for (int j = 0; j < dim; ++j) {
+                        double acc = 0.0;
+                        for (int m = 0; m < dim; ++m) acc += R[m][i] * T1[m][j];
+                        B[i][j] = acc;
+                    }
+                for (int i = 0; i < dim; ++i)
+                    for (int j = 0; j < dim; ++j) {
+                        A[i][j] = (i <= j) ? B[i][j] : B[j][i];
+                        V[i][j] = W[i][j];
+                    }
+                A[p][q] = A[q][p] = 0.0;
+            }
+    }
+    int order[3] = {0, 1, 2};
+    for (int i = 0; i < dim; ++i)          /* ascending eigenvalues (stable) */
+        for (int j = i + 1; j < dim; ++j)
+            if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
+                int t = order[i];
+                order[i] = order[j];
+                order[j] = t;
+            }
+    for (int e = 0; e < dim; ++e) {
+        int col = order[e];
+        evals[e] = A[col][col];
+        int big = 0;
+        for (int a = 1; a < dim; ++a)
+            if (fabs(V[a][col]) > fabs(V[big][col])) big = a;
+        double sgn = (V[big][col] < 0.0) ? -1.0 : 1.0;
+        for (int a = 0; a < dim; ++a) evecs[e * dim + a] = sgn * V[a][col];
+    }
+}
+
+/* orc_eig_sym over n packed tensors (nq x n): evals[k*n + p],
+ * evecs[(k*dim + a)*n + p]. */
+void orc_eig_many(int dim, int64_t n, const double *C, double *evals, double *evecs)
+{
+    int nq = dim * (dim + 1) / 2;
+    for (int64_t p = 0; p < n; ++p) {
+        double c[6], ev[3], V[9];
+        for (int q = 0; q < nq; ++q) c[q] = C[q * n + p];
+        orc_eig_sym(dim, c, ev, V);
+        for (int k = 0; k < dim; ++k) {
+            evals[k * n + p] = ev[k];
+            for (int a = 0; a < dim; ++a) evecs[(k * dim + a) * n + p] = V[k * dim + a];
+        }
+    }
 }
 
 /* FTLE (reading: the standard definition of the cited FTLE work)
