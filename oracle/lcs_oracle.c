@@ -245,13 +245,14 @@ static uint32_t check_point(const orc_velocity *v, const double *p, double *marg
 {
     if (!all_finite(p, v->dim)) return ORC_FLAG_NONFINITE;
     if (margin) {
-        /* diagnostic only: smallest distance of a checked point to the
-         * boundary of the closed domain (negative outside) */
+        /* diagnostic only: smallest distance, inside or outside, of a checked
+         * point to a wall of the closed domain -- how close an in/out decision
+         * came to going the other way */
         for (int a = 0; a < v->dim; ++a) {
             if (axis_periodic(v->periodic_mask, a)) continue;
             double lo = v->origin[a];
             double hi = v->origin[a] + (double)(v->n[a] - 1) * v->spacing[a];
-            double d = fmin(p[a] - lo, hi - p[a]);
+            double d = fmin(fabs(p[a] - lo), fabs(hi - p[a]));
             if (d < *margin) *margin = d;
         }
     }
@@ -334,9 +335,10 @@ static int64_t step_count(double T, double dt) { return (int64_t)llround(T / dt)
 
 /* Advect arbitrary points x0 (dim x m, SoA), each from its own t0[p], over
  * the same duration T with step dt.  Outputs (any may be NULL): xf (dim x m),
- * cell (m), flags (m), margin (m): the smallest distance of any checked stage
- * point or position to the boundary of the closed domain (a diagnostic used
- * to tell which tracers sit too close to a wall for an FP32 run to agree). */
+ * cell (m), flags (m), margin (m): the smallest distance, inside or outside,
+ * of any checked stage point or position to a wall of the closed domain (a
+ * diagnostic used to tell which tracers came too close to a wall for an FP32
+ * run to take the same in/out decisions). */
 void orc_advect_points(const orc_velocity *v, const double *x0, const double *t0, int64_t m,
                        double T, double dt, double *xf, int64_t *cell, uint8_t *flags,
                        double *margin, int nthreads)
@@ -1317,15 +1319,16 @@ void orc_mesh_velocity_at_many(const orc_mesh *m, const double *x, const double 
 }
 
 /* Check a stage point or a new position: non-finite -> NONFINITE, in no cell
- * of the mesh -> OUT.  margin (diagnostic): the smallest distance of a checked
- * point to the mesh's bounding box, which is its distance to the boundary for
- * the box-shaped meshes this oracle is used with. */
+ * of the mesh -> OUT.  margin (diagnostic): the smallest distance, inside or
+ * outside, of a checked point to a face of the mesh's bounding box, which is
+ * its distance to the boundary for the box-shaped meshes this oracle is used
+ * with. */
 static uint32_t mesh_check_point(const orc_mesh *m, const double *p, double *margin)
 {
     if (!all_finite(p, m->dim)) return ORC_FLAG_NONFINITE;
     if (margin)
         for (int a = 0; a < m->dim; ++a) {
-            double d = fmin(p[a] - m->lo[a], m->hi[a] - p[a]);
+            double d = fmin(fabs(p[a] - m->lo[a]), fabs(m->hi[a] - p[a]));
             if (d < *margin) *margin = d;
         }
     if (orc_mesh_locate(m, p, NULL) < 0) return ORC_FLAG_OUT;
