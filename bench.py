@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-window, random-Fourier and surrogate workloads")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
-    ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux",
+    ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux,time_resolved",
                     help="comma-separated extra workloads to run after the main step")
     ap.add_argument("--strategy", default=None,
                     help="advection strategy of the main workload ('tiles' or 'sorted:S'); "
@@ -262,7 +262,13 @@ def bench_mesh(torch, lcs, inputs, reps=3, cpu_sample=0):
         steps = ns * int(round(T / dt))
         bps = MESH_BYTES_PER_STEP_3D if dim == 3 else MESH_BYTES_PER_STEP_2D
         fl = flags.cpu().numpy()
+        c = g.coords_of(np.arange(ns))
+        on_wall = np.zeros(ns, dtype=bool)
+        for a in range(dim):
+            on_wall |= (c[a] == 0) | (c[a] == g.n[a] - 1)
         rec = {"workload": name, "cells": gm.n_cells, "nodes": gm.n_nodes, "seeds": ns,
+               "flagged_wall_seeds": int(((fl != 0) & on_wall).sum()),
+               "flagged_interior_seeds": int(((fl != 0) & ~on_wall).sum()),
                "mesh_create_ms": create_ms, "advect_ms": adv, "cg_ftle_ms": cgf,
                "tracer_steps": steps, "tracer_steps_per_s": steps / ((adv + cgf) * 1e-3),
                "tracer_steps_per_s_advect_kernel": steps / (adv * 1e-3),
@@ -333,20 +339,31 @@ def bench_ab(torch, lcs, inputs, reps=2):
                                                      ws, want_cell=False, stream=stream))
     runs.append({"method": "rk4 (re-bundled, segments of 50)", "dt": 0.02, "ms": ms,
                  "ftle_err_mean": em, "ftle_err_max": ex})
+    ms, em, ex = timed(lambda: lcs.lcs_advect_ab(frames, g, 0.0, T, 0.02, order=4, xf=xf,
+                                                 want_cell=False, flags=flags, stream=stream))
+    runs.append({"method": "ab4 (single launch)", "dt": 0.02, "ms": ms, "ftle_err_mean": em,
+                 "ftle_err_max": ex})
+    del ws
+    ws = torch.empty(lcs.lcs_advect_ab_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                     device="cuda")
     ab_ms = None
     for dt in (0.02, 0.01, 0.005):
-        ms, em, ex = timed(lambda: lcs.lcs_advect_ab(frames, g, 0.0, T, dt, order=4, xf=xf,
-                                                     want_cell=False, flags=flags, stream=stream))
+        seg = int(round(1.0 / dt))
+        ms, em, ex = timed(lambda: lcs.lcs_advect_ab_sorted(
+            frames, g, 0.0, T, dt, order=4, segment_steps=seg, xf=xf, flags=flags, workspace=ws,
+            want_cell=False, stream=stream))
         if dt == 0.02:
             ab_ms = ms
-        runs.append({"method": "ab4", "dt": dt, "ms": ms, "ftle_err_mean": em, "ftle_err_max": ex})
+        runs.append({"method": "ab4 (re-bundled every 1.0 time unit)", "dt": dt, "ms": ms,
+                     "ftle_err_mean": em, "ftle_err_max": ex})
     lcs.lcs_sync_status()
     steps = ns * 400
     del ws, frames
     return {"workload": "abc_128cubed_seeds256cubed_ab4", "reference": "rk4 dt=0.005",
             "runs": runs, "tracer_steps_per_s_ab4_dt0.02": steps / (ab_ms * 1e-3),
             "velocity_evaluations_per_step": {"rk4": 4, "ab4": 1},
-            "roofline": {"kernel": "advect_ab_grid_kernel<3, 4>", "bound": "hbm",
+            "roofline": {"kernel": "ab4 re-bundled call (rebundle_segment_kernel<3, 4> + sorts)",
+                         "bound": "hbm",
                          "achieved": 192 * steps / (ab_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": 192 * steps / (ab_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "bytes_per_unit": 192, "unit_of_work": "3D tracer-AB4-step"}}
@@ -411,6 +428,71 @@ def bench_aux(torch, lcs, inputs, reps=2):
             "aux_delta_h_over_10": dict(ms=ms_aux, tracers=6 * ns, **err(s_aux)),
             "aux_reference_ms": ms_ref,
             "aux_tracer_steps_per_s": 6 * ns * 400 / (ms_aux * 1e-3)}
+
+
+def bench_time_resolved(torch, lcs, inputs, reps=2):
+    """Time-resolved FTLE on the ABC 128^3 / 256^3-seed workload (8 snapshots at
+    T = 1..8 in one launch, an FTLE field per snapshot) and early evaluation on a
+    truncated ABC box (the field sampled on the closed box [0, 2pi]^3, 128^3 seeds,
+    T = 4: tracers near the faces leave, their stencils are evaluated early)."""
+    stream = torch.cuda.current_stream()
+    L = 2 * math.pi
+    fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
+    g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
+    frames = lcs.DeviceFrames(fs)
+    ns = g.count
+    steps = [50 * k for k in range(1, 9)]
+    xs = torch.empty((8, 3, ns), dtype=torch.float32, device="cuda")
+    done = torch.empty(ns, dtype=torch.int32, device="cuda")
+    sig = torch.empty(ns, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    def snap_all():
+        lcs.lcs_advect_snapshots(frames, g, 0.0, 0.02, steps, xf=xs, steps_done=done,
+                                 want_flags=False, stream=stream)
+        for k in range(8):
+            lcs.lcs_cg_ftle(g, xs[k], steps[k] * 0.02, ftle=sig, stream=stream)
+
+    ms_snap = timed(snap_all)
+    xf = torch.empty((3, ns), dtype=torch.float32, device="cuda")
+    ms_one = timed(lambda: lcs.lcs_advect(frames, g, 0.0, 8.0, 0.02, xf=xf, want_cell=False,
+                                          want_flags=False, stream=stream))
+    del xs, xf, frames
+    torch.cuda.empty_cache()
+    ft = inputs.sample_field(inputs.abc_velocity, 3, (129, 129, 129), (0.0,) * 3, (L / 128,) * 3,
+                             (False,) * 3, 0.0, 0.5, 17).astype(np.float32)
+    frames = lcs.DeviceFrames(ft)
+    gt = inputs.linspace_seeds(3, (128, 128, 128), (0.0,) * 3, (L,) * 3)
+    nt = gt.count
+    x1 = torch.empty((1, 3, nt), dtype=torch.float32, device="cuda")
+    d1 = torch.empty(nt, dtype=torch.int32, device="cuda")
+    lcs.lcs_advect_snapshots(frames, gt, 0.0, 0.02, [200], xf=x1, steps_done=d1, want_flags=False,
+                             stream=stream)
+    ws = torch.empty(lcs.lcs_ftle_early_workspace_bytes(gt), dtype=torch.uint8, device="cuda")
+    lam = torch.empty(nt, dtype=torch.float64, device="cuda")
+    se = torch.empty(nt, dtype=torch.float64, device="cuda")
+    te = torch.empty(nt, dtype=torch.float64, device="cuda")
+    ms_early = timed(lambda: lcs.lcs_ftle_early(frames, gt, 0.0, 0.02, 200, x1[0], d1, lam, se, te,
+                                                ws, stream=stream))
+    lcs.lcs_sync_status()
+    early = int((te < 4.0 - 1e-12).sum().item())
+    return {"workload": "abc_128cubed_seeds256cubed_8_snapshots",
+            "snapshot_steps": steps, "ms_8_snapshots_and_8_ftle_fields": ms_snap,
+            "ms_single_lcs_advect_tiles": ms_one,
+            "truncated_box": {"workload": "abc_closed_box_129cubed_seeds128cubed_T4",
+                              "seeds": nt, "early_seeds": early, "ms_ftle_early": ms_early}}
 
 
 def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
@@ -636,6 +718,10 @@ def main():
         if "aux" in want:
             print("bench: auxiliary points", file=sys.stderr, flush=True)
             extra["auxiliary_points"] = bench_aux(torch, lcs, inputs)
+            torch.cuda.empty_cache()
+        if "time_resolved" in want:
+            print("bench: time-resolved and early FTLE", file=sys.stderr, flush=True)
+            extra["time_resolved"] = bench_time_resolved(torch, lcs, inputs)
             torch.cuda.empty_cache()
         out["extra_workloads"] = extra
     if not args.no_cpu_baseline:

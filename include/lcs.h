@@ -122,6 +122,9 @@ typedef struct lcs_plan *lcs_plan_t;
 /* Maximum number of windows of one lcs_advect_batched call. */
 #define LCS_MAX_WINDOWS 192
 
+/* Maximum number of snapshots of one lcs_advect_snapshots call. */
+#define LCS_MAX_SNAPSHOTS 64
+
 /*
  * lcs_advect -- flow map F_{t0}^{t0+T} of a structured seed grid (Eq. 2;
  * Sec. 2 Seed and Flow Map filters; Sec. 3.1 RK4).
@@ -398,6 +401,20 @@ lcs_status lcs_advect_ab(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds
                          void *stream);
 
 /*
+ * lcs_advect_ab_sorted -- lcs_advect_ab with the tracers re-bundled by position
+ * between segments of segment_steps steps, as lcs_advect_sorted does for RK4
+ * (the past velocities travel with each tracer).  Results equal
+ * lcs_advect_ab's bit for bit.  workspace: [device], at least
+ * lcs_advect_ab_sorted_workspace_bytes(vel, seeds) bytes (valid for every order).
+ */
+int64_t lcs_advect_ab_sorted_workspace_bytes(const lcs_velocity_t *vel,
+                                             const lcs_seed_grid_t *seeds);
+lcs_status lcs_advect_ab_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                int32_t order, double t0, double T, double dt,
+                                int32_t segment_steps, float *xf, int64_t *cell, uint8_t *flags,
+                                void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
  * lcs_advect_aux -- flow map of auxiliary points about every seed (Sec. 2
  * Seed filter: highly localised auxiliary points; Cauchy-Green filter: the
  * gradient from differences of auxiliary points).  For every seed x0 and
@@ -427,6 +444,65 @@ lcs_status lcs_advect_aux(const lcs_velocity_t *vel, const lcs_seed_grid_t *seed
 lcs_status lcs_cg_aux(const lcs_seed_grid_t *seeds, const double *delta, const float *xa_hi,
                       const float *xa_lo, const uint8_t *flags, double *C, uint8_t *stencil_flags,
                       void *stream);
+
+/*
+ * lcs_cg_eig -- eigenvalues and eigenvectors of the packed symmetric tensors
+ * C (Sec. 2 Cauchy-Green filter: eigenvalue and eigenvector fields for LCS
+ * detection), FP64 cyclic Jacobi per point.
+ * C       [device] FP64, (dim(dim+1)/2) x n, packed as lcs_cg_tensor writes it.
+ * evals   [device] FP64, dim x n, ascending: evals[k*n + p]; or NULL.
+ * evecs   [device] FP64, dim x dim x n: component a of the eigenvector of
+ *         evals[k] at [(k*dim + a)*n + p], unit length, signed so that its
+ *         largest component is positive; or NULL.
+ */
+lcs_status lcs_cg_eig(int32_t dim, int64_t n, const double *C, double *evals, double *evecs,
+                      void *stream);
+
+/*
+ * lcs_advect_snapshots -- the flow map at several times of one integration
+ * (Sec. 3.1: the CG tensor can be evaluated at any step; Sec. 4: the CG
+ * tensor at various integration times).  As lcs_advect from t0 with step dt
+ * (no periodic-domain restriction beyond lcs_advect's), recording every tracer
+ * after each of the n_snap step counts snap_steps[k] (host, strictly
+ * increasing, >= 1, 1 <= n_snap <= LCS_MAX_SNAPSHOTS); the interval
+ * [t0, t0 + snap_steps[n_snap-1]*dt] must lie in the frame span.
+ * xf          [device] FP32, n_snap x dim x Ns: [(k*dim + a)*Ns + s]; a tracer
+ *             frozen earlier keeps its frozen position.
+ * flags       [device] uint8, n_snap x Ns, or NULL: the flag as of snapshot k.
+ * steps_done  [device] int32, Ns, or NULL: steps taken before the tracer froze
+ *             (snap_steps[n_snap-1] if it never did).
+ * The FTLE at snapshot k is lcs_cg_ftle on xf + k*dim*Ns with
+ * T = snap_steps[k]*dt.
+ */
+lcs_status lcs_advect_snapshots(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                                double dt, int32_t n_snap, const int32_t *snap_steps, float *xf,
+                                uint8_t *flags, int32_t *steps_done, void *stream);
+
+/* Workspace of lcs_ftle_early for seeds: room for every seed at once (smaller
+ * workspaces process the listed seeds in chunks). */
+int64_t lcs_ftle_early_workspace_bytes(const lcs_seed_grid_t *seeds);
+
+/*
+ * lcs_ftle_early -- FTLE with early evaluation (Sec. 2 Flow Map filter: when a
+ * trajectory leaves the domain, the CG tensor is evaluated early at every
+ * location that relies on it).  For seed s, n_s = the smallest steps_done over
+ * the seeds its gradient uses (itself and its grid neighbours as
+ * lcs_cg_tensor differences them).  n_s = nsteps: the ordinary FTLE from xf.
+ * 0 < n_s < nsteps: its stencil is re-advected n_s steps from t0 and
+ * sigma = ln(lambda_max) / (2 n_s |dt|).  n_s = 0: NaN.
+ * xf          [device] FP32, dim x Ns: positions after nsteps (lcs_advect or
+ *             the last snapshot).
+ * steps_done  [device] int32, Ns (lcs_advect_snapshots).
+ * lambda_max  [device] FP64, Ns, or NULL.  ftle [device] FP64, Ns.
+ * t_eff       [device] FP64, Ns, or NULL: n_s * dt.
+ * workspace   [device], >= 8*Ns + 2048 bytes (lcs_ftle_early_workspace_bytes
+ *             for a single pass).
+ * Synchronises the stream (the number of listed seeds decides the passes).
+ */
+lcs_status lcs_ftle_early(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                          double dt, int32_t nsteps, const float *xf, const int32_t *steps_done,
+                          double *lambda_max, double *ftle, double *t_eff, void *workspace,
+                          int64_t workspace_bytes, void *stream);
 
 /* ======================================================================== */
 /* Unstructured velocity data: triangle (2D) and tetrahedron (3D) meshes      */
@@ -541,8 +617,10 @@ lcs_status lcs_mesh_locate(lcs_mesh_t mesh, const float *x, int64_t n, int64_t *
                            void *stream);
 
 /*
- * lcs_mesh_velocity_at -- u(x, t) at points (each with its own t, inside the
- * frame span, else LCS_E_TIME_RANGE is not detected: t is clamped to the span).
+ * lcs_mesh_velocity_at -- u(x, t) at points, each with its own time (Sec. 3.2:
+ * cell search, then piecewise-linear interpolation in space and linear in
+ * time).  A time outside the frame span is clamped to it (the values are not
+ * read on the host, so no error is reported for them).
  * x [device] FP32 dim x n; t [device] FP64 n; u [device] FP32 dim x n (NaN
  * outside the mesh); cell [device] int64 n or NULL (as lcs_mesh_locate).
  */

@@ -343,16 +343,17 @@ __device__ __forceinline__ float ab_num(int j)
 template <int S>
 constexpr double ab_den() { return S == 2 ? 2.0 : (S == 3 ? 12.0 : 24.0); }
 
+// Steps n_begin <= n < n_end; hist[j] = f_{n-1-j} on entry and is updated, so
+// an integration can be resumed from a saved (position, history) state.
 template <int D, int S>
-__device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, double t0, double dt,
-                                    int nsteps)
+__device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float (*hist)[3],
+                                    double t0, double dt, int n_begin, int n_end)
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
     const double cab = dt / ab_den<S>();
     const float ch = (float)cab, cl = (float)(cab - (double)ch);
-    float hist[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
-    for (int n = 0; n < nsteps; ++n) {
+    for (int n = n_begin; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1;
         float al1;
@@ -423,7 +424,8 @@ __global__ LCS_ADVECT_BOUNDS void advect_ab_grid_kernel(AdvectArgs A)
         xl[a] = (float)(x0 - (double)xh[a]);
     }
     uint32_t fl = check_point<D>(A.v, xh);
-    if (!fl) fl = advect_steps_ab<D, S>(A.v, xh, xl, A.t0, A.dt, A.nsteps);
+    float hist[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    if (!fl) fl = advect_steps_ab<D, S>(A.v, xh, xl, hist, A.t0, A.dt, 0, A.nsteps);
 #pragma unroll
     for (int a = 0; a < D; ++a) x[a] = xh[a] + xl[a];
 #pragma unroll
@@ -465,6 +467,79 @@ __global__ LCS_ADVECT_BOUNDS void advect_aux_kernel(AuxArgs A)
         A.xa_lo[((long long)a * 2 * D + q) * ns + s] = xl[a];
     }
     if (A.a.flags) A.a.flags[(long long)q * ns + s] = (uint8_t)fl;
+}
+
+// Time-resolved flow map (Sec. 3.1: the CG tensor at any step of the
+// interval): the grid kernel's integration, writing the position and flag of
+// every tracer after each listed step count, and the number of steps it took
+// before it froze.
+template <int D>
+__global__ LCS_ADVECT_BOUNDS void advect_snap_kernel(SnapArgs A)
+{
+    const int m = xcd_remap((int)blockIdx.x, A.a.g.n_blocks);
+    int sc[3];
+    const long long s = seed_of<D>(A.a.g, m, threadIdx.x, sc);
+    if (s < 0) return;
+    float xh[3], xl[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double x0 = A.a.g.s_origin[a] + (double)sc[a] * A.a.g.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+    uint32_t fl = check_point<D>(A.a.v, xh);
+    int nacc = 0, k = 0;
+    const int last = A.steps[A.n_snap - 1];
+    const long long ns = A.a.ns;
+    for (int n = 0; n < last; ++n) {
+        if (!fl) {
+            fl = advect_steps<D, true>(A.a.v, xh, xl, A.a.t0, A.a.dt, n, n + 1);
+            if (!fl) nacc = n + 1;
+        }
+        if (n + 1 == A.steps[k]) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) A.xf[((long long)k * D + a) * ns + s] = xh[a] + xl[a];
+            if (A.flags) A.flags[(long long)k * ns + s] = (uint8_t)fl;
+            ++k;
+        }
+    }
+    if (A.steps_done) A.steps_done[s] = nacc;
+}
+
+// Early evaluation: re-advect the stencil members of listed seeds for their
+// n_s steps.  Work item w = entry * 7 + slot; slot 0 is the seed, slot
+// 1 + 2b + side its lower (side 0) / upper neighbour along b.  Slots past the
+// grid's dimension or past a non-periodic edge have no member.  Positions
+// are written in FP64 (two-float sum).
+template <int D>
+__global__ LCS_ADVECT_BOUNDS void early_advect_kernel(EarlyAdvArgs A, int first, int count)
+{
+    const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = (int)(w / 7), slot = (int)(w % 7);
+    if (e >= count) return;
+    const long long s = A.list[2 * (first + e)];
+    const int nsd = A.list[2 * (first + e) + 1];
+    int c[3] = {(int)(s % A.n[0]), (int)((s / A.n[0]) % A.n[1]),
+                (int)(s / ((long long)A.n[0] * A.n[1]))};
+    if (slot > 0) {
+        const int b = (slot - 1) >> 1, dir = ((slot - 1) & 1) ? 1 : -1;
+        if (b >= D) return;
+        int j = c[b] + dir;
+        if ((A.periodic_mask >> b) & 1u) j = (j + A.n[b]) % A.n[b];
+        else if (j < 0 || j >= A.n[b]) return;
+        c[b] = j;
+    }
+    float xh[3], xl[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double x0 = A.s_origin[a] + (double)c[a] * A.s_spacing[a];
+        xh[a] = (float)x0;
+        xl[a] = (float)(x0 - (double)xh[a]);
+    }
+    (void)advect_tracer<D>(A.v, xh, xl, A.t0, A.dt, nsd);
+    double *P = A.pos + ((long long)e * 7 + slot) * 3;
+#pragma unroll
+    for (int a = 0; a < D; ++a) P[a] = (double)xh[a] + (double)xl[a];
 }
 
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
@@ -660,6 +735,9 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
     }
     A.st.idx[p] = (int)p;
     A.st.flag[p] = (uint8_t)check_point<D>(A.v, xh);
+    if (A.st.hist[0])
+#pragma unroll
+        for (int q = 0; q < 3 * D; ++q) A.st.hist[q][p] = 0.0f;
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
     atomicAdd(&A.sk.counts[key], 1u);
@@ -667,7 +745,7 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
 
 // Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
 // segment) or the state in place plus its new key and the histogram.
-template <int D>
+template <int D, int S>
 __global__ LCS_ADVECT_BOUNDS void rebundle_segment_kernel(SegmentArgs A)
 {
     const int nblocks = (int)gridDim.x;
@@ -680,7 +758,16 @@ __global__ LCS_ADVECT_BOUNDS void rebundle_segment_kernel(SegmentArgs A)
         xl[a] = A.st.xl[a][p];
     }
     uint32_t fl = A.st.flag[p];
-    if (!fl) fl = advect_steps<D>(A.v, xh, xl, A.t0, A.dt, A.n_begin, A.n_end);
+    float hist[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    if constexpr (S > 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int a = 0; a < D; ++a) hist[j][a] = A.st.hist[j * D + a][p];
+        if (!fl) fl = advect_steps_ab<D, S>(A.v, xh, xl, hist, A.t0, A.dt, A.n_begin, A.n_end);
+    } else {
+        if (!fl) fl = advect_steps<D>(A.v, xh, xl, A.t0, A.dt, A.n_begin, A.n_end);
+    }
     if (A.last) {
         const long long s = A.st.idx[p];
         float x[3] = {0, 0, 0};
@@ -699,6 +786,12 @@ __global__ LCS_ADVECT_BOUNDS void rebundle_segment_kernel(SegmentArgs A)
         A.st.xl[a][p] = xl[a];
     }
     A.st.flag[p] = (uint8_t)fl;
+    if constexpr (S > 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int a = 0; a < D; ++a) A.st.hist[j * D + a][p] = hist[j][a];
+    }
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
     atomicAdd(&A.sk.counts[key], 1u);
@@ -781,6 +874,9 @@ __global__ __launch_bounds__(256) void scatter_kernel(SegmentArgs A, TracerState
     }
     dst.idx[q] = A.st.idx[p];
     dst.flag[q] = A.st.flag[p];
+    if (A.st.hist[0])
+#pragma unroll
+        for (int r = 0; r < 3 * D; ++r) dst.hist[r][q] = A.st.hist[r][p];
 }
 
 }  // namespace
@@ -818,8 +914,21 @@ hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s)
 hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
-    if (dim == 2) hipLaunchKernelGGL(rebundle_segment_kernel<2>, grid, block, 0, s, a);
-    else hipLaunchKernelGGL(rebundle_segment_kernel<3>, grid, block, 0, s, a);
+    if (dim == 2) {
+        switch (a.order) {
+        case 2: hipLaunchKernelGGL((rebundle_segment_kernel<2, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((rebundle_segment_kernel<2, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((rebundle_segment_kernel<2, 4>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((rebundle_segment_kernel<2, 0>), grid, block, 0, s, a);
+        }
+    } else {
+        switch (a.order) {
+        case 2: hipLaunchKernelGGL((rebundle_segment_kernel<3, 2>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((rebundle_segment_kernel<3, 3>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((rebundle_segment_kernel<3, 4>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((rebundle_segment_kernel<3, 0>), grid, block, 0, s, a);
+        }
+    }
     return hipGetLastError();
 }
 
@@ -889,6 +998,23 @@ hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s)
     dim3 grid((unsigned)(a.a.g.n_blocks * 2 * dim)), block(256);
     if (dim == 2) hipLaunchKernelGGL(advect_aux_kernel<2>, grid, block, 0, s, a);
     else hipLaunchKernelGGL(advect_aux_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_snap(int dim, const SnapArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)a.a.g.n_blocks), block(256);
+    if (dim == 2) hipLaunchKernelGGL(advect_snap_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(advect_snap_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_early_advect(int dim, const EarlyAdvArgs &a, int first, int count, hipStream_t s)
+{
+    const long long work = (long long)count * 7;
+    dim3 grid((unsigned)((work + 255) / 256)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(early_advect_kernel<2>, grid, block, 0, s, a, first, count);
+    else hipLaunchKernelGGL(early_advect_kernel<3>, grid, block, 0, s, a, first, count);
     return hipGetLastError();
 }
 

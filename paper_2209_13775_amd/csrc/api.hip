@@ -410,6 +410,146 @@ lcs_status lcs_cg_aux(const lcs_seed_grid_t *seeds, const double *delta, const f
     return lcs::clear_error();
 }
 
+lcs_status lcs_cg_eig(int32_t dim, int64_t n, const double *C, double *evals, double *evecs,
+                      void *stream)
+{
+    if (dim != 2 && dim != 3) return lcs::set_error(LCS_E_ARG, "dim must be 2 or 3");
+    if (n < 0 || n > kMaxSeeds) return lcs::set_error(LCS_E_SHAPE, "n out of range");
+    if (!C) return lcs::set_error(LCS_E_ARG, "C is NULL");
+    if (!evals && !evecs) return lcs::set_error(LCS_E_ARG, "evals and evecs are both NULL");
+    if (n == 0) return lcs::clear_error();
+    hipError_t e = lcs::launch_eig(dim, n, C, evals, evecs, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "eig launch");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_advect_snapshots(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                                double dt, int32_t n_snap, const int32_t *snap_steps, float *xf,
+                                uint8_t *flags, int32_t *steps_done, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf || !snap_steps) return lcs::set_error(LCS_E_ARG, "xf and snap_steps must not be NULL");
+    if (n_snap < 1 || n_snap > LCS_MAX_SNAPSHOTS)
+        return lcs::set_error(LCS_E_SHAPE, "n_snap must be in [1, %d]", LCS_MAX_SNAPSHOTS);
+    for (int k = 0; k < n_snap; ++k)
+        if (snap_steps[k] < 1 || (k > 0 && snap_steps[k] <= snap_steps[k - 1]))
+            return lcs::set_error(LCS_E_ARG, "snap_steps must be >= 1 and strictly increasing");
+    if (!isfinite(dt) || dt == 0.0) return lcs::set_error(LCS_E_STEP, "dt must be finite and non-zero");
+    const double T = dt * (double)snap_steps[n_snap - 1];
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + T;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                    vel->t_first, t_last);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    lcs::SnapArgs A;
+    memset(&A, 0, sizeof(A));
+    A.a.v = make_vel(vel);
+    A.a.g = make_tiling(seeds);
+    A.a.t0 = t0;
+    A.a.dt = dt;
+    A.a.nsteps = snap_steps[n_snap - 1];
+    A.a.ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    A.n_snap = n_snap;
+    for (int k = 0; k < n_snap; ++k) A.steps[k] = snap_steps[k];
+    A.xf = xf;
+    A.flags = flags;
+    A.steps_done = steps_done;
+    hipError_t e = lcs::launch_advect_snap(vel->dim, A, (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "advect_snapshots launch");
+    return lcs::clear_error();
+}
+
+namespace {
+constexpr long long kEarlyHeader = 1024;         // counter (aligned region)
+constexpr long long kEarlyEntryBytes = 7 * 3 * 8;
+
+long long early_list_bytes(long long ns) { return ((8 * ns + 255) / 256) * 256; }
+}  // namespace
+
+int64_t lcs_ftle_early_workspace_bytes(const lcs_seed_grid_t *seeds)
+{
+    if (!seeds || check_seeds(seeds, seeds->dim) != LCS_OK) return -1;
+    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    return kEarlyHeader + early_list_bytes(ns) + kEarlyEntryBytes * ns;
+}
+
+lcs_status lcs_ftle_early(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                          double dt, int32_t nsteps, const float *xf, const int32_t *steps_done,
+                          double *lambda_max, double *ftle, double *t_eff, void *workspace,
+                          int64_t workspace_bytes, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    if (!xf || !steps_done || !ftle || !workspace)
+        return lcs::set_error(LCS_E_ARG, "xf, steps_done, ftle and workspace must not be NULL");
+    if (nsteps < 1) return lcs::set_error(LCS_E_STEP, "nsteps must be >= 1");
+    if (!isfinite(dt) || dt == 0.0) return lcs::set_error(LCS_E_STEP, "dt must be finite and non-zero");
+    const double t_last = vel->t_first + (double)(vel->n_frames - 1) * vel->dt_frame;
+    const double t1 = t0 + dt * (double)nsteps;
+    if (!(isfinite(t0) && t0 >= vel->t_first && t0 <= t_last && t1 >= vel->t_first && t1 <= t_last))
+        return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
+                    vel->t_first, t_last);
+    if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
+    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    const long long fixed = kEarlyHeader + early_list_bytes(ns);
+    if (workspace_bytes < fixed + kEarlyEntryBytes)
+        return lcs::set_error(LCS_E_ARG, "workspace needs at least %lld bytes",
+                              fixed + kEarlyEntryBytes);
+    long long chunk = (workspace_bytes - fixed) / kEarlyEntryBytes;
+    if (chunk > ns) chunk = ns;
+    char *base = static_cast<char *>(workspace);
+    lcs::EarlyArgs E;
+    memset(&E, 0, sizeof(E));
+    E.dim = seeds->dim;
+    for (int a = 0; a < 3; ++a) {
+        E.n[a] = (int)seeds->n[a];
+        E.h[a] = seeds->spacing[a];
+    }
+    E.periodic_mask = seeds->periodic_mask;
+    E.ns = ns;
+    E.nsteps = nsteps;
+    E.dt = dt;
+    E.xf = xf;
+    E.steps_done = steps_done;
+    E.lam = lambda_max;
+    E.ftle = ftle;
+    E.t_eff = t_eff;
+    E.counter = reinterpret_cast<int *>(base);
+    E.list = reinterpret_cast<int *>(base + kEarlyHeader);
+    E.pos = reinterpret_cast<double *>(base + fixed);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = lcs::launch_fill_u32(reinterpret_cast<uint32_t *>(E.counter), 1, 0u, s);
+    if (e == hipSuccess) e = lcs::launch_early_mark(E, s);
+    int count = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&count, E.counter, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return lcs::hip_error(e, "ftle_early mark");
+    lcs::EarlyAdvArgs A;
+    memset(&A, 0, sizeof(A));
+    A.v = make_vel(vel);
+    for (int a = 0; a < 3; ++a) {
+        A.s_origin[a] = seeds->origin[a];
+        A.s_spacing[a] = seeds->spacing[a];
+        A.n[a] = (int)seeds->n[a];
+    }
+    A.periodic_mask = seeds->periodic_mask;
+    A.t0 = t0;
+    A.dt = dt;
+    A.list = E.list;
+    A.pos = E.pos;
+    for (long long first = 0; first < count; first += chunk) {
+        const int c = (int)((count - first < chunk) ? count - first : chunk);
+        e = lcs::launch_early_advect(vel->dim, A, (int)first, c, s);
+        if (e == hipSuccess) e = lcs::launch_early_cg(E, (int)first, c, s);
+        if (e != hipSuccess) return lcs::hip_error(e, "ftle_early pass");
+    }
+    return lcs::clear_error();
+}
+
 lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
                               const lcs_seed_grid_t *seeds, const lcs_window_t *windows,
                               int32_t n_windows, double dt, float *xf, int64_t *cell,
@@ -519,7 +659,8 @@ long long align256(long long x) { return (x + 255) / 256 * 256; }
 
 // Bin geometry and workspace size of lcs_advect_sorted; with base != NULL the
 // state buffers and sort arrays are carved from it.
-SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, lcs::TracerState *st)
+SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, lcs::TracerState *st,
+                           int order = 0)
 {
     SortedLayout L;
     memset(&L, 0, sizeof(L));
@@ -558,6 +699,10 @@ SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, l
             st[b].idx = reinterpret_cast<int *>(pi);
             st[b].flag = reinterpret_cast<uint8_t *>(pf);
         }
+        for (int q = 0; q < 9; ++q) {
+            char *ph = (order > 0 && q < 3 * vel->dim) ? take(4 * n) : nullptr;
+            if (st) st[b].hist[q] = reinterpret_cast<float *>(ph);
+        }
     }
     L.sk.keys = reinterpret_cast<uint32_t *>(take(4 * n));
     L.sk.counts = reinterpret_cast<uint32_t *>(take(4 * nk));
@@ -577,9 +722,22 @@ int64_t lcs_advect_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_s
     return sorted_layout(vel, n, nullptr, nullptr).bytes;
 }
 
-lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
-                             double T, double dt, int32_t segment_steps, float *xf, int64_t *cell,
-                             uint8_t *flags, void *workspace, int64_t workspace_bytes, void *stream)
+int64_t lcs_advect_ab_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds)
+{
+    if (check_velocity(vel) != LCS_OK || check_seeds(seeds, vel->dim) != LCS_OK) return 0;
+    const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    return sorted_layout(vel, n, nullptr, nullptr, 4).bytes;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Re-bundled advection with RK4 (order 0) or Adams-Bashforth (order 2..4).
+lcs_status advect_sorted_impl(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, int order,
+                              double t0, double T, double dt, int32_t segment_steps, float *xf,
+                              int64_t *cell, uint8_t *flags, void *workspace,
+                              int64_t workspace_bytes, void *stream)
 {
     lcs_status st;
     if ((st = check_velocity(vel)) != LCS_OK) return st;
@@ -597,12 +755,12 @@ lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
     const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
     lcs::TracerState bufs[2];
     memset(bufs, 0, sizeof(bufs));
-    const SortedLayout need = sorted_layout(vel, n, nullptr, nullptr);
+    const SortedLayout need = sorted_layout(vel, n, nullptr, nullptr, order);
     if (workspace_bytes < need.bytes)
         return lcs::set_error(LCS_E_SHAPE, "workspace of %lld bytes is smaller than the %lld needed",
                               (long long)workspace_bytes, need.bytes);
     if (need.sk.n_keys > (1LL << 30)) return lcs::set_error(LCS_E_SHAPE, "velocity grid too large to bin");
-    const SortedLayout L = sorted_layout(vel, n, static_cast<char *>(workspace), bufs);
+    const SortedLayout L = sorted_layout(vel, n, static_cast<char *>(workspace), bufs, order);
     const int seg = segment_steps > 0 ? segment_steps : 50;
     hipStream_t s = (hipStream_t)stream;
 
@@ -617,6 +775,7 @@ lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
     A.xf = xf;
     A.cell = reinterpret_cast<long long *>(cell);
     A.flags = flags;
+    A.order = order;
     A.st = bufs[0];
     hipError_t e = lcs::launch_fill_u32(L.sk.counts, L.sk.n_keys, 0u, s);
     if (e == hipSuccess) e = lcs::launch_rebundle_init(vel->dim, A, s);
@@ -635,6 +794,28 @@ lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
     }
     if (e != hipSuccess) return lcs::hip_error(e, "advect_sorted launch");
     return lcs::clear_error();
+}
+
+}  // namespace
+
+extern "C" {
+
+lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
+                             double T, double dt, int32_t segment_steps, float *xf, int64_t *cell,
+                             uint8_t *flags, void *workspace, int64_t workspace_bytes, void *stream)
+{
+    return advect_sorted_impl(vel, seeds, 0, t0, T, dt, segment_steps, xf, cell, flags, workspace,
+                              workspace_bytes, stream);
+}
+
+lcs_status lcs_advect_ab_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                int32_t order, double t0, double T, double dt,
+                                int32_t segment_steps, float *xf, int64_t *cell, uint8_t *flags,
+                                void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (order < 2 || order > 4) return lcs::set_error(LCS_E_ARG, "order must be 2, 3 or 4");
+    return advect_sorted_impl(vel, seeds, order, t0, T, dt, segment_steps, xf, cell, flags,
+                              workspace, workspace_bytes, stream);
 }
 
 lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0, int64_t n,

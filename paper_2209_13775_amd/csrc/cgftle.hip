@@ -282,7 +282,286 @@ __global__ __launch_bounds__(256) void ftle_kernel(FtleArgs A)
     if (A.ftle) A.ftle[p] = ftle_of(lam, A.inv_two_T);
 }
 
+
+// Eigenpairs of a symmetric dim x dim matrix (Sec. 2 Cauchy-Green filter:
+// eigenvalue and eigenvector fields).  Cyclic Jacobi: each rotation zeroes
+// A[p][q] (two-sided on A, one-sided on V), sweeps until the off-diagonal mass
+// is negligible; then ascending order and the sign of every eigenvector fixed
+// so that its largest component (the first on a tie) is positive.
+template <int D>
+__device__ void eig_sym(const double *c, double *ev, double (*vec)[3])
+{
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            A[i][j] = c[k];
+            A[j][i] = c[k];
+            ++k;
+        }
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, dia = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            dia += A[i][i] * A[i][i];
+#pragma unroll
+            for (int j = i + 1; j < D; ++j) off += A[i][j] * A[i][j];
+        }
+        if (off == 0.0 || off <= 1e-36 * dia) break;
+#pragma unroll
+        for (int p = 0; p < D; ++p)
+#pragma unroll
+            for (int q = p + 1; q < D; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (tau >= 0.0) ? 1.0 / (tau + hypot(1.0, tau))
+                                              : 1.0 / (tau - hypot(1.0, tau));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+                // A <- R^T A R with R = I except R[p][p] = R[q][q] = cs, R[p][q] = sn, R[q][p] = -sn
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const double aip = A[i][p], aiq = A[i][q];
+                    A[i][p] = cs * aip - sn * aiq;
+                    A[i][q] = sn * aip + cs * aiq;
+                    const double vip = V[i][p], viq = V[i][q];
+                    V[i][p] = cs * vip - sn * viq;
+                    V[i][q] = sn * vip + cs * viq;
+                }
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    const double apj = A[p][j], aqj = A[q][j];
+                    A[p][j] = cs * apj - sn * aqj;
+                    A[q][j] = sn * apj + cs * aqj;
+                }
+                A[p][q] = 0.0;
+                A[q][p] = 0.0;
+            }
+    }
+    int order[3] = {0, 1, 2};
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i + 1; j < D; ++j)
+            if (A[order[j]][order[j]] < A[order[i]][order[i]]) {
+                const int t = order[i];
+                order[i] = order[j];
+                order[j] = t;
+            }
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        const int col = order[e];
+        ev[e] = A[col][col];
+        int big = 0;
+#pragma unroll
+        for (int a = 1; a < D; ++a)
+            if (fabs(V[a][col]) > fabs(V[big][col])) big = a;
+        const double sg = (V[big][col] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) vec[e][a] = sg * V[a][col];
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void eig_kernel(long long n, const double *C, double *evals,
+                                                  double *evecs)
+{
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    constexpr int NQ = D * (D + 1) / 2;
+    double c[6], ev[3], vec[3][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) c[q] = C[q * n + p];
+    eig_sym<D>(c, ev, vec);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        if (evals) evals[k * n + p] = ev[k];
+        if (evecs)
+#pragma unroll
+            for (int a = 0; a < D; ++a) evecs[(k * D + a) * n + p] = vec[k][a];
+    }
+}
+
+// ---- early Cauchy-Green evaluation ----------------------------------------
+
+// Neighbour of seed coordinate c along axis b in direction dir: the wrapped
+// index on a periodic axis, -1 past a non-periodic edge.
+__device__ __forceinline__ int nb_index(const EarlyArgs &A, int b, int c, int dir)
+{
+    const int n = A.n[b];
+    int j = c + dir;
+    if ((A.periodic_mask >> b) & 1u) return (j + n) % n;
+    return (j < 0 || j >= n) ? -1 : j;
+}
+
+__device__ __forceinline__ long long lin(const EarlyArgs &A, const int *c)
+{
+    return (long long)c[0] + (long long)A.n[0] * ((long long)c[1] + (long long)A.n[1] * c[2]);
+}
+
+// Gradient of the flow map at seed c from FP64 positions of the seed (xc) and
+// its lower/upper neighbours (xm[b], xp[b]): central in the interior and on
+// periodic axes (seam shift by the period), one-sided at non-periodic edges;
+// C = J^T J packed; returns lambda_max.
+template <int D>
+__device__ double grad_lam(const EarlyArgs &A, const int *c, const double *xc, const double (*xm)[3],
+                           const double (*xp)[3], double *Cp)
+{
+#pragma clang fp contract(off)
+    double J[3][3];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        const int n = A.n[b];
+        const double h = A.h[b];
+        if ((A.periodic_mask >> b) & 1u) {
+            const double L = (double)n * h;
+            const double sp = (c[b] + 1 >= n) ? L : 0.0;
+            const double sm = (c[b] - 1 < 0) ? -L : 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double fp = xp[b][a] + (a == b ? sp : 0.0);
+                const double fm = xm[b][a] + (a == b ? sm : 0.0);
+                J[a][b] = (fp - fm) / (2.0 * h);
+            }
+        } else if (c[b] == 0) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) J[a][b] = (xp[b][a] - xc[a]) / h;
+        } else if (c[b] == n - 1) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) J[a][b] = (xc[a] - xm[b][a]) / h;
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a) J[a][b] = (xp[b][a] - xm[b][a]) / (2.0 * h);
+        }
+    }
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int q = r; q < D; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) acc += J[a][r] * J[a][q];
+            Cp[k++] = acc;
+        }
+    if constexpr (D == 2) return lam_max2(Cp[0], Cp[1], Cp[2]);
+    else return lam_max3(Cp[0], Cp[1], Cp[2], Cp[3], Cp[4], Cp[5]);
+}
+
+__device__ __forceinline__ void seed_coords(const EarlyArgs &A, long long s, int *c)
+{
+    c[0] = (int)(s % A.n[0]);
+    c[1] = (int)((s / A.n[0]) % A.n[1]);
+    c[2] = (int)(s / ((long long)A.n[0] * A.n[1]));
+}
+
+// Earliest exit in each seed's stencil.  Seeds whose stencil ran the whole
+// interval get the ordinary FTLE from xf here; the others are listed (their
+// stencil is re-advected), n_s = 0 gives NaN.
+template <int D>
+__global__ __launch_bounds__(256) void early_mark_kernel(EarlyArgs A)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.ns) return;
+    int c[3];
+    seed_coords(A, s, c);
+    int nsd = A.steps_done[s];
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+#pragma unroll
+        for (int dir = -1; dir <= 1; dir += 2) {
+            const int j = nb_index(A, b, c[b], dir);
+            if (j < 0) continue;
+            int cc[3] = {c[0], c[1], c[2]};
+            cc[b] = j;
+            nsd = min(nsd, A.steps_done[lin(A, cc)]);
+        }
+    if (A.t_eff) A.t_eff[s] = (double)nsd * A.dt;
+    if (nsd >= A.nsteps) {
+        double xc[3] = {0, 0, 0}, xm[3][3], xp[3][3], Cp[6];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xc[a] = (double)A.xf[a * A.ns + s];
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                double *dst = side ? xp[b] : xm[b];
+                const int j = nb_index(A, b, c[b], side ? 1 : -1);
+                int cc[3] = {c[0], c[1], c[2]};
+                if (j >= 0) cc[b] = j;
+                const long long t = lin(A, cc);
+#pragma unroll
+                for (int a = 0; a < D; ++a) dst[a] = (double)A.xf[a * A.ns + t];
+            }
+        const double lam = grad_lam<D>(A, c, xc, xm, xp, Cp);
+        if (A.lam) A.lam[s] = lam;
+        A.ftle[s] = (lam > 0.0) ? log(lam) / (2.0 * fabs((double)A.nsteps * A.dt)) : -INFINITY;
+    } else if (nsd <= 0) {
+        if (A.lam) A.lam[s] = __builtin_nan("");
+        A.ftle[s] = __builtin_nan("");
+    } else {
+        const int q = atomicAdd(A.counter, 1);
+        A.list[2 * q] = (int)s;
+        A.list[2 * q + 1] = nsd;
+    }
+}
+
+// Gradient of the listed seeds [first, first + count) from the re-advected
+// stencil positions (FP64, [entry][slot][3], slot 0 = the seed, 1 + 2b + side
+// = its neighbour along b), with T = n_s dt.
+template <int D>
+__global__ __launch_bounds__(256) void early_cg_kernel(EarlyArgs A, int first, int count)
+{
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= count) return;
+    const long long s = A.list[2 * (first + e)];
+    const int nsd = A.list[2 * (first + e) + 1];
+    int c[3];
+    seed_coords(A, s, c);
+    const double *P = A.pos + (long long)e * 7 * 3;
+    double xc[3], xm[3][3], xp[3][3], Cp[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xc[a] = P[a];
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xm[b][a] = P[(1 + 2 * b) * 3 + a];
+            xp[b][a] = P[(2 + 2 * b) * 3 + a];
+        }
+    const double lam = grad_lam<D>(A, c, xc, xm, xp, Cp);
+    if (A.lam) A.lam[s] = lam;
+    A.ftle[s] = (lam > 0.0) ? log(lam) / (2.0 * fabs((double)nsd * A.dt)) : -INFINITY;
+}
+
 }  // namespace
+
+hipError_t launch_eig(int dim, long long n, const double *C, double *evals, double *evecs,
+                      hipStream_t s)
+{
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (dim == 2) hipLaunchKernelGGL(eig_kernel<2>, grid, block, 0, s, n, C, evals, evecs);
+    else hipLaunchKernelGGL(eig_kernel<3>, grid, block, 0, s, n, C, evals, evecs);
+    return hipGetLastError();
+}
+
+hipError_t launch_early_mark(const EarlyArgs &a, hipStream_t s)
+{
+    dim3 grid((unsigned)((a.ns + 255) / 256)), block(256);
+    if (a.dim == 2) hipLaunchKernelGGL(early_mark_kernel<2>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(early_mark_kernel<3>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_early_cg(const EarlyArgs &a, int first, int count, hipStream_t s)
+{
+    dim3 grid((unsigned)((count + 255) / 256)), block(256);
+    if (a.dim == 2) hipLaunchKernelGGL(early_cg_kernel<2>, grid, block, 0, s, a, first, count);
+    else hipLaunchKernelGGL(early_cg_kernel<3>, grid, block, 0, s, a, first, count);
+    return hipGetLastError();
+}
 
 hipError_t launch_cg_aux(const CgAuxArgs &a, hipStream_t s)
 {

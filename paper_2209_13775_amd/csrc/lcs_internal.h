@@ -98,6 +98,48 @@ struct CgAuxArgs {
     uint8_t *sflags;
 };
 
+// Time-resolved flow map: positions after each listed step count.
+constexpr int kMaxSnapshots = LCS_MAX_SNAPSHOTS;
+
+struct SnapArgs {
+    AdvectArgs a;
+    int n_snap;
+    int steps[kMaxSnapshots];  // strictly increasing, >= 1
+    float *xf;                 // [n_snap][dim][Ns]
+    uint8_t *flags;            // [n_snap][Ns] or null
+    int *steps_done;           // [Ns] or null
+};
+
+// Early Cauchy-Green evaluation (list of seeds whose stencil left the domain).
+struct EarlyArgs {
+    int dim;
+    int n[3];
+    uint32_t periodic_mask;
+    double h[3];
+    long long ns;
+    int nsteps;
+    double dt;
+    const float *xf;           // [dim][Ns] after nsteps
+    const int *steps_done;     // [Ns]
+    double *lam;               // may be null
+    double *ftle;
+    double *t_eff;             // may be null
+    int *counter;
+    int *list;                 // [2*Ns]: (seed, n_s)
+    double *pos;               // [chunk][7][3] re-advected stencil positions
+};
+
+struct EarlyAdvArgs {
+    VelDev v;
+    double s_origin[3];
+    double s_spacing[3];
+    int n[3];
+    uint32_t periodic_mask;
+    double t0, dt;
+    const int *list;
+    double *pos;
+};
+
 struct FtleArgs {
     long long n;
     const double *C;
@@ -256,6 +298,7 @@ struct TracerState {
     float *xl[3];
     int *idx;                         // seed index (natural order)
     uint8_t *flag;
+    float *hist[9];                   // multistep: past velocities [j*dim + a] (null for RK4)
 };
 
 struct SortKeys {
@@ -279,6 +322,7 @@ struct SegmentArgs {
     TracerState st;
     SortKeys sk;
     int last;                         // 1: write outputs instead of state + keys
+    int order;                        // 0: RK4; 2..4: Adams-Bashforth
     float *xf;
     long long *cell;
     uint8_t *flags;
@@ -308,6 +352,12 @@ lcs_status hip_error(hipError_t e, const char *where);
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_advect_ab(int dim, int order, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s);
+hipError_t launch_advect_snap(int dim, const SnapArgs &a, hipStream_t s);
+hipError_t launch_early_advect(int dim, const EarlyAdvArgs &a, int first, int count, hipStream_t s);
+hipError_t launch_early_mark(const EarlyArgs &a, hipStream_t s);
+hipError_t launch_early_cg(const EarlyArgs &a, int first, int count, hipStream_t s);
+hipError_t launch_eig(int dim, long long n, const double *C, double *evals, double *evecs,
+                      hipStream_t s);
 hipError_t launch_cg_aux(const CgAuxArgs &a, hipStream_t s);
 hipError_t launch_reset_counter(int *counter, hipStream_t s);
 hipError_t launch_advect_batched(int dim, const BatchArgs &a, int grid_blocks, hipStream_t s);

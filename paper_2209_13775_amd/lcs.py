@@ -92,6 +92,10 @@ def _load(path: str = LIB_PATH):
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
         "lcs_advect_aux": [P, P, P, D, D, D, P, P, P, P],
+        "lcs_cg_eig": [I32, I64, P, P, P, P],
+        "lcs_advect_ab_sorted": [P, P, I32, D, D, D, I32, P, P, P, P, I64, P],
+        "lcs_advect_snapshots": [P, P, D, D, I32, P, P, P, P, P],
+        "lcs_ftle_early": [P, P, D, D, I32, P, P, P, P, P, P, I64, P],
         "lcs_cg_aux": [P, P, P, P, P, P, P, P],
         "lcs_mesh_create": [P, P, P],
         "lcs_mesh_info": [P, P],
@@ -116,6 +120,10 @@ def _load(path: str = LIB_PATH):
     L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
     L.lcs_advect_sorted_workspace_bytes.restype = C.c_int64
     L.lcs_advect_sorted_workspace_bytes.argtypes = [P, P]
+    L.lcs_advect_ab_sorted_workspace_bytes.restype = C.c_int64
+    L.lcs_advect_ab_sorted_workspace_bytes.argtypes = [P, P]
+    L.lcs_ftle_early_workspace_bytes.restype = C.c_int64
+    L.lcs_ftle_early_workspace_bytes.argtypes = [P]
     L.lcs_check_tile_count.restype = C.c_int64
     L.lcs_check_tile_count.argtypes = [P]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
@@ -333,6 +341,115 @@ def lcs_cg_aux(seeds, delta, xa_hi, xa_lo, flags=None, C_out=None, stencil_flags
     _check(_lib.lcs_cg_aux(C.byref(sd), dl, _ptr(xa_hi), _ptr(xa_lo), _ptr(flags), _ptr(C_out),
                            _ptr(stencil_flags), _stream_handle(stream)))
     return C_out, stencil_flags
+
+
+def lcs_advect_ab_sorted_workspace_bytes(frames: DeviceFrames, seeds) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_advect_ab_sorted_workspace_bytes(frames.ref, C.byref(sd)))
+
+
+def lcs_advect_ab_sorted(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
+                         order: int = 4, segment_steps: int = 0, xf=None, cell=None, flags=None,
+                         workspace=None, want_cell=True, want_flags=True, stream=None):
+    """lcs_advect_ab with tracers re-bundled by position between segments."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_advect_ab_sorted_workspace_bytes(frames, seeds), dev)
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_ab_sorted(frames.ref, C.byref(sd), int(order), float(t0), float(T),
+                                     float(dt), int(segment_steps), _ptr(xf), _ptr(cell),
+                                     _ptr(flags), _ptr(workspace),
+                                     int(workspace.numel() * workspace.element_size()),
+                                     _stream_handle(stream)))
+    return xf, cell, flags
+
+
+def lcs_cg_eig(dim: int, C_in, evals=None, evecs=None, want_vectors=True, stream=None):
+    """(evals (dim, n) ascending, evecs (dim, dim, n)) of packed C (nq, n), FP64."""
+    torch = _torch()
+    nq = dim * (dim + 1) // 2
+    n = int(C_in.shape[1])
+    _need(C_in, torch.float64, (nq, n), "C")
+    if evals is None:
+        evals = torch.empty((dim, n), dtype=torch.float64, device=C_in.device)
+    if evecs is None and want_vectors:
+        evecs = torch.empty((dim, dim, n), dtype=torch.float64, device=C_in.device)
+    _need(evals, torch.float64, (dim, n), "evals")
+    _need(evecs, torch.float64, (dim, dim, n), "evecs")
+    _check(_lib.lcs_cg_eig(int(dim), n, _ptr(C_in), _ptr(evals), _ptr(evecs), _stream_handle(stream)))
+    return evals, evecs
+
+
+def lcs_advect_snapshots(frames: DeviceFrames, seeds, t0: float, dt: float, snap_steps, xf=None,
+                         flags=None, steps_done=None, want_flags=True, want_steps=True,
+                         stream=None):
+    """Positions (n_snap, dim, Ns), flags (n_snap, Ns) and accepted steps (Ns) after
+    each of snap_steps RK4 steps."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    st = [int(x) for x in snap_steps]
+    k = len(st)
+    if xf is None:
+        xf = torch.empty((k, d, ns), dtype=torch.float32, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty((k, ns), dtype=torch.uint8, device=dev)
+    if steps_done is None and want_steps:
+        steps_done = torch.empty(ns, dtype=torch.int32, device=dev)
+    _need(xf, torch.float32, (k, d, ns), "xf")
+    _need(flags, torch.uint8, (k, ns), "flags")
+    _need(steps_done, torch.int32, (ns,), "steps_done")
+    arr = (C.c_int32 * k)(*st)
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_snapshots(frames.ref, C.byref(sd), float(t0), float(dt), k, arr,
+                                     _ptr(xf), _ptr(flags), _ptr(steps_done),
+                                     _stream_handle(stream)))
+    return xf, flags, steps_done
+
+
+def lcs_ftle_early_workspace_bytes(seeds) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_ftle_early_workspace_bytes(C.byref(sd)))
+
+
+def lcs_ftle_early(frames: DeviceFrames, seeds, t0: float, dt: float, nsteps: int, xf, steps_done,
+                   lambda_max=None, ftle=None, t_eff=None, workspace=None, stream=None):
+    """FTLE with early evaluation where a stencil left the domain: (lambda_max, ftle, t_eff)."""
+    torch = _torch()
+    dev = xf.device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(steps_done, torch.int32, (ns,), "steps_done")
+    if lambda_max is None:
+        lambda_max = torch.empty(ns, dtype=torch.float64, device=dev)
+    if ftle is None:
+        ftle = torch.empty(ns, dtype=torch.float64, device=dev)
+    if t_eff is None:
+        t_eff = torch.empty(ns, dtype=torch.float64, device=dev)
+    for t, nm in ((lambda_max, "lambda_max"), (ftle, "ftle"), (t_eff, "t_eff")):
+        _need(t, torch.float64, (ns,), nm)
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_ftle_early_workspace_bytes(seeds), dev)
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_ftle_early(frames.ref, C.byref(sd), float(t0), float(dt), int(nsteps), _ptr(xf),
+                               _ptr(steps_done), _ptr(lambda_max), _ptr(ftle), _ptr(t_eff),
+                               _ptr(workspace), int(workspace.numel() * workspace.element_size()),
+                               _stream_handle(stream)))
+    return lambda_max, ftle, t_eff
 
 
 def lcs_advect_sorted_workspace_bytes(frames: DeviceFrames, seeds) -> int:

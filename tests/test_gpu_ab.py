@@ -169,3 +169,31 @@ def test_linear_saddle_recurrence(lcs):
         gpu = run_gpu(lcs, fs, g, 0.0, T, dt, order)
         gx, gy = growth(lam * dt, order), growth(-lam * dt, order)
         np.testing.assert_allclose(gpu["ftle"], math.log(max(abs(gx), abs(gy))) / T, atol=1e-5)
+
+
+@pytest.mark.parametrize("order,seg", [(2, 7), (3, 50), (4, 1), (4, 33)])
+def test_rebundled_equals_single_launch_2d(lcs, torch, order, seg):
+    """Re-bundled AB (history carried with the tracer through the sorts) is
+    bit-identical to the single-launch AB, with exits and a NaN node."""
+    fs = inputs.double_gyre_frames(nx=51, ny=26, n_frames=11)
+    fs.u[0][4, 10, 30] = np.nan
+    g = inputs.linspace_seeds(2, (97, 45), (0.0, 0.0), (2.0, 1.0))
+    frames = lcs.DeviceFrames(fs)
+    a = lcs.lcs_advect_ab(frames, g, 0.5, 7.0, 0.05, order=order)
+    b = lcs.lcs_advect_ab_sorted(frames, g, 0.5, 7.0, 0.05, order=order, segment_steps=seg)
+    lcs.lcs_sync_status()
+    assert (a[2] == 2).sum().item() > 0
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+
+
+def test_rebundled_equals_single_launch_abc_full(lcs, torch):
+    fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
+    L = 2 * math.pi
+    g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
+    frames = lcs.DeviceFrames(fs)
+    a = lcs.lcs_advect_ab(frames, g, 8.0, -8.0, -0.02, order=4, want_cell=False)
+    b = lcs.lcs_advect_ab_sorted(frames, g, 8.0, -8.0, -0.02, order=4, segment_steps=50,
+                                 want_cell=False)
+    lcs.lcs_sync_status()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[2], b[2])
