@@ -57,6 +57,31 @@ def parse():
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+def profiled_traffic_kernel(kernel):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary, or None if there is none or its source changed since."""
+    import hashlib
+    try:
+        names = sorted(os.listdir(PROFILES))
+    except OSError:
+        return None
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)).read().splitlines():
+            if not (line.startswith("{") and "traffic_bytes_per_launch" in line):
+                continue
+            rec = json.loads(line)
+            if rec.get("kernel") != kernel:
+                continue
+            h = hashlib.sha1()
+            for f in rec["source_files"]:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            if h.hexdigest()[:16] == rec["source_sha1"]:
+                return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def profiled_traffic(strategy):
     """HBM bytes of one advection call (all its kernels) from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain
@@ -278,6 +303,7 @@ def bench_mesh(torch, lcs, inputs, reps=3, cpu_sample=0):
                             "achieved": bps * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s",
                             "frac": bps * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "traffic": profiled_traffic_kernel("mesh_advect_grid_kernel<%d>" % dim),
                             "bytes_per_unit": bps, "unit_of_work": "%dD mesh tracer-RK4-step" % dim}}
         if cpu_sample and dim == 3:
             import oracle
