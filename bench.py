@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-window, random-Fourier and surrogate workloads")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
+    ap.add_argument("--layout", default="xyzw", choices=("soa", "xyz", "xyzw"),
+                    help="frame layout the kernels read; with an interleaved layout the main "
+                         "step converts the structure-of-arrays frames inside its timed region")
     ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux,time_resolved",
                     help="comma-separated extra workloads to run after the main step")
     ap.add_argument("--strategy", default=None,
@@ -82,7 +85,18 @@ def profiled_traffic_kernel(kernel):
     return None
 
 
-def profiled_traffic(strategy):
+def stage_frames(lcs, fs, layout, tensors=None):
+    """Device frames of fs in the given layout (interleaved copies are made by
+    lcs_frames_interleave from the structure-of-arrays frames)."""
+    soa = lcs.DeviceFrames(fs, tensors=tensors)
+    if layout == "soa":
+        return soa
+    fr = lcs.lcs_frames_interleave(soa, layout)
+    del soa
+    return fr
+
+
+def profiled_traffic(strategy, layout="soa"):
     """HBM bytes of one advection call (all its kernels) from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain
     copy of known size), or None if it was taken for another strategy or the
@@ -99,7 +113,7 @@ def profiled_traffic(strategy):
             if not (line.startswith("{") and "traffic_bytes_per_launch" in line):
                 continue
             rec = json.loads(line)
-            if rec.get("strategy", "tiles") != strategy:
+            if rec.get("strategy", "tiles") != strategy or rec.get("layout", "soa") != layout:
                 continue
             h = hashlib.sha1()
             for f in rec["source_files"]:
@@ -134,7 +148,7 @@ def cpu_baseline(fs, g, t0, T, dt, target_s):
                       f"FP64, OpenMP, {el:.1f} s"}
 
 
-def bench_batched(torch, lcs, inputs, reps=3):
+def bench_batched(torch, lcs, inputs, reps=3, layout="xyz"):
     """Double gyre on 1025x513 nodes x 101 FP32 frames (t = 0.25 f); 64 windows
     (t0 ~ U[0,10], T from {5, 7.5, 10, 12.5, 15}, default_rng(0)) of a
     1024x512 seed grid, dt = 0.05, all in one graph-replayed persistent launch."""
@@ -143,7 +157,7 @@ def bench_batched(torch, lcs, inputs, reps=3):
     g = inputs.linspace_seeds(2, (1024, 512), (0.0, 0.0), (2.0, 1.0))
     windows = inputs.t0_windows(64, seed=0)
     dt = 0.05
-    frames = lcs.DeviceFrames(fs)
+    frames = stage_frames(lcs, fs, layout)
     plan = lcs.Plan()
     nw, ns = len(windows), g.count
     xf = torch.empty((nw, 2, ns), dtype=torch.float32, device="cuda")
@@ -163,7 +177,8 @@ def bench_batched(torch, lcs, inputs, reps=3):
     lcs.lcs_sync_status()
     steps = int(sum(round(T / dt) for _, T in windows)) * ns
     ms = float(np.median(times))
-    out = {"workload": "double_gyre_batched_1025x513_64windows", "windows": nw,
+    out = {"workload": "double_gyre_batched_1025x513_64windows", "frame_layout": layout,
+           "windows": nw,
            "seeds_per_window": ns, "tracer_steps": steps, "ms_per_launch": ms,
            "tracer_steps_per_s": steps / (ms * 1e-3),
            "roofline": {"kernel": "advect_batched_kernel<2>", "bound": "hbm",
@@ -182,7 +197,7 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     L = 2 * math.pi
     g = inputs.SeedGrid(3, (512, 512, 256), (0.0, 0.0, 0.0), (L / 512, L / 512, L / 256),
                         (True, True, True))
-    frames = lcs.DeviceFrames(fs, tensors=fs.u)
+    frames = stage_frames(lcs, fs, "xyzw", tensors=fs.u)
     ns = g.count
     from paper_2209_13775_amd import autotune
     tuned = autotune.tune(frames, g, 4.0, 4.0, 0.01, candidates=("sorted:100", "sorted:50",
@@ -222,7 +237,8 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     adv = res["forward"][0] + res["backward"][0]
     cgf = res["forward"][1] + res["backward"][1]
     del ws
-    return {"workload": "random_fourier_256cubed_seeds512x512x256", "seeds": ns,
+    return {"workload": "random_fourier_256cubed_seeds512x512x256", "frame_layout": "xyzw",
+            "seeds": ns,
             "advect_strategy": choice, "autotune_ms": tuned["ms"],
             "tracer_steps": steps, "advect_ms_forward": res["forward"][0],
             "advect_ms_backward": res["backward"][0], "cg_ftle_ms": cgf,
@@ -331,7 +347,7 @@ def bench_ab(torch, lcs, inputs, reps=2):
     fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
     L = 2 * math.pi
     g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = lcs.DeviceFrames(fs)
+    frames = stage_frames(lcs, fs, "xyzw")
     ns = g.count
     T = 8.0
     stream = torch.cuda.current_stream()
@@ -385,7 +401,8 @@ def bench_ab(torch, lcs, inputs, reps=2):
     lcs.lcs_sync_status()
     steps = ns * 400
     del ws, frames
-    return {"workload": "abc_128cubed_seeds256cubed_ab4", "reference": "rk4 dt=0.005",
+    return {"workload": "abc_128cubed_seeds256cubed_ab4", "frame_layout": "xyzw",
+            "reference": "rk4 dt=0.005",
             "runs": runs, "tracer_steps_per_s_ab4_dt0.02": steps / (ab_ms * 1e-3),
             "velocity_evaluations_per_step": {"rk4": 4, "ab4": 1},
             "roofline": {"kernel": "ab4 re-bundled call (rebundle_segment_kernel<3, 4> + sorts)",
@@ -405,7 +422,7 @@ def bench_aux(torch, lcs, inputs, reps=2):
     L = 2 * math.pi
     g = inputs.periodic_seeds(3, (128, 128, 128), (L, L, L))
     g2 = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = lcs.DeviceFrames(fs)
+    frames = stage_frames(lcs, fs, "xyzw")
     T, dt = 8.0, 0.02
     h = L / 128
     stream = torch.cuda.current_stream()
@@ -447,7 +464,8 @@ def bench_aux(torch, lcs, inputs, reps=2):
             e[::17].float(), 0.99).item()), "ftle_err_max": float(e.max().item())}
 
     ns = g.count
-    return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "reference":
+    return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "frame_layout": "xyzw",
+            "reference":
             "auxiliary points, delta = h/100", "seed_spacing_h": h,
             "grid_128cubed": dict(ms=ms_g1, tracers=ns, **err(s_g1)),
             "grid_256cubed_subsampled": dict(ms=ms_g2, tracers=8 * ns, **err(s_g2)),
@@ -465,7 +483,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
     L = 2 * math.pi
     fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
     g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = lcs.DeviceFrames(fs)
+    frames = stage_frames(lcs, fs, "xyzw")
     ns = g.count
     steps = [50 * k for k in range(1, 9)]
     xs = torch.empty((8, 3, ns), dtype=torch.float32, device="cuda")
@@ -499,7 +517,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
     torch.cuda.empty_cache()
     ft = inputs.sample_field(inputs.abc_velocity, 3, (129, 129, 129), (0.0,) * 3, (L / 128,) * 3,
                              (False,) * 3, 0.0, 0.5, 17).astype(np.float32)
-    frames = lcs.DeviceFrames(ft)
+    frames = stage_frames(lcs, ft, "xyzw")
     gt = inputs.linspace_seeds(3, (128, 128, 128), (0.0,) * 3, (L,) * 3)
     nt = gt.count
     x1 = torch.empty((1, 3, nt), dtype=torch.float32, device="cuda")
@@ -514,7 +532,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
                                                 ws, stream=stream))
     lcs.lcs_sync_status()
     early = int((te < 4.0 - 1e-12).sum().item())
-    return {"workload": "abc_128cubed_seeds256cubed_8_snapshots",
+    return {"workload": "abc_128cubed_seeds256cubed_8_snapshots", "frame_layout": "xyzw",
             "snapshot_steps": steps, "ms_8_snapshots_and_8_ftle_fields": ms_snap,
             "ms_single_lcs_advect_tiles": ms_one,
             "truncated_box": {"workload": "abc_closed_box_129cubed_seeds128cubed_T4",
@@ -622,7 +640,9 @@ def main():
     g = inputs.periodic_seeds(3, W["seeds"], (L, L, L))
     ns = g.count
     nsteps = int(round(W["T"] / W["dt"]))
-    frames = lcs.DeviceFrames(fs, device=dev)
+    frames_soa = lcs.DeviceFrames(fs, device=dev)
+    layout = args.layout
+    frames = frames_soa if layout == "soa" else lcs.lcs_frames_interleave(frames_soa, layout)
     from paper_2209_13775_amd import autotune
     if args.strategy:
         tuned = {"choice": args.strategy, "ms": None}
@@ -647,6 +667,8 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
+        if layout != "soa":      # the step starts from the structure-of-arrays frames
+            lcs.lcs_frames_interleave(frames_soa, layout, out=frames.u[0], stream=stream)
         autotune.run(choice, frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, ws, stream=stream)
         if ev is not None:
             ev[1].record(stream)
@@ -693,7 +715,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["name"], "field": "time-dependent ABC flow",
                    "grid": [W["grid"]] * 3, "frames": W["frames"], "seeds": list(W["seeds"]),
-                   "t0": W["t0"], "T": W["T"], "dt": W["dt"], "rk4_steps": nsteps},
+                   "t0": W["t0"], "T": W["T"], "dt": W["dt"], "rk4_steps": nsteps,
+                   "frame_layout": layout},
         "advect_ms": adv_ms,
         "cg_ftle_ms": cgf_ms,
         "tracer_steps_per_s_advect_kernel": tracer_steps / (adv_ms * 1e-3),
@@ -702,17 +725,18 @@ def main():
         "advect_strategy": choice,
         "autotune_ms": tuned["ms"],
         "roofline": {"kernel": ("advect_grid_kernel<3>" if choice == "tiles" else
-                                "advection call: rebundle_segment_kernel<3> x %d + re-bundling sorts"
+                                "advection call: rebundle_segment_kernel<3, 0> x %d + re-bundling "
+                                "sorts (+ frame interleave)"
                                 % math.ceil(nsteps / int(choice.split(":")[1]))),
                      "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(choice),
+                     "traffic": profiled_traffic(choice, layout),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
                      "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
                      "units_per_launch": tracer_steps},
         "cpu_baseline": None,
     }
-    del frames, xf, cell, flags, Cm, sfl, lam, sig, ws
+    del frames, frames_soa, xf, cell, flags, Cm, sfl, lam, sig, ws
     if not args.no_extra:
         want = set(x.strip() for x in args.extras.split(",") if x.strip())
         if args.no_surrogate:

@@ -76,10 +76,27 @@ enum {
  *              closed interval [origin, origin + (n-1)*spacing].
  * n_frames     >= 2; frame f holds the field at t_first + f*dt_frame,
  *              dt_frame > 0.
- * u[c]         [device] FP32, component c for all frames:
- *              u[c][f*n0*n1*n2 + i + n0*(j + n1*k)]  (structure of arrays).
- *              u[2] is ignored in 2D.
+ * layout       how the frames are stored (node = i + n0*(j + n1*k),
+ *              N = n0*n1*n2):
+ *   LCS_LAYOUT_SOA   u[c] [device] FP32, component c of all frames at
+ *                    u[c][f*N + node] (structure of arrays); u[2] ignored in 2D.
+ *   LCS_LAYOUT_XYZ   u[0] [device] FP32, the dim components of a node adjacent:
+ *                    u[0][(f*N + node)*dim + c] (interleaved, as VTK stores
+ *                    vector point data); u[1], u[2] ignored; 4-byte aligned
+ *                    (8-byte in 2D).
+ *   LCS_LAYOUT_XYZW  3D only: u[0][(f*N + node)*4 + c], the 4th float unused;
+ *                    16-byte aligned.
+ *              Every layout gives the same field; the interleaved ones need
+ *              fewer memory transactions per interpolation (one record per
+ *              node instead of one value per component array), see
+ *              lcs_frames_interleave.
  */
+enum {
+    LCS_LAYOUT_SOA = 0,
+    LCS_LAYOUT_XYZ = 1,
+    LCS_LAYOUT_XYZW = 2
+};
+
 typedef struct {
     int32_t dim;
     int32_t n_frames;
@@ -87,7 +104,7 @@ typedef struct {
     double origin[3];
     double spacing[3];
     uint32_t periodic_mask;
-    uint32_t reserved;        /* must be 0 */
+    uint32_t layout;          /* LCS_LAYOUT_* */
     double t_first;
     double dt_frame;
     const float *u[3];
@@ -124,6 +141,20 @@ typedef struct lcs_plan *lcs_plan_t;
 
 /* Maximum number of snapshots of one lcs_advect_snapshots call. */
 #define LCS_MAX_SNAPSHOTS 64
+
+/*
+ * lcs_frames_interleave -- copy frames f_first .. f_first+f_count-1 of a
+ * structure-of-arrays velocity (layout LCS_LAYOUT_SOA) into the interleaved
+ * layout (LCS_LAYOUT_XYZ, or LCS_LAYOUT_XYZW in 3D) on the device, and describe
+ * the copy (Sec. 2 Reader/Cache filters: velocity data staged in GPU memory in
+ * the form the kernels read).
+ * out       [device] FP32, f_count * N * S floats (S = dim, or 4 for XYZW).
+ * out_desc  [host] filled with the interleaved descriptor of the copied span
+ *           (t_first moved to frame f_first, n_frames = f_count >= 2).
+ */
+lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int32_t f_first,
+                                 int32_t f_count, float *out, lcs_velocity_t *out_desc,
+                                 void *stream);
 
 /*
  * lcs_advect -- flow map F_{t0}^{t0+T} of a structured seed grid (Eq. 2;

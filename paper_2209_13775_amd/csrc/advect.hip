@@ -101,6 +101,30 @@ __device__ __forceinline__ float2 load_pair(const float *base, unsigned int elem
     return v;
 }
 
+// Interleaved frames: the components of a node are adjacent (S floats per
+// node: 3 (x, y, z), 4 (x, y, z, unused) or 2 in 2D).  A record is read with one
+// load at a 32-bit record offset from the frame base; in 2D the two nodes of a
+// corner pair (i, i+1) are one 16-byte load.
+template <int S>
+__device__ __forceinline__ void load_rec(const float *frame, unsigned int node, float *out)
+{
+    if constexpr (S == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(frame + (size_t)node * 4u);
+        out[0] = q.x; out[1] = q.y; out[2] = q.z;
+    } else {
+        float q[3];
+        __builtin_memcpy(q, reinterpret_cast<const char *>(frame) + (size_t)node * 12u, 12);
+        out[0] = q[0]; out[1] = q[1]; out[2] = q[2];
+    }
+}
+
+__device__ __forceinline__ float4 load_pair2(const float *frame, unsigned int node)
+{
+    float4 q;
+    __builtin_memcpy(&q, reinterpret_cast<const char *>(frame) + (size_t)node * 8u, sizeof(q));
+    return q;
+}
+
 // u at the two-float point (ph + pl): multilinear in space within frames f and
 // f+1, then linear in time.  The corners of a cell come in x-adjacent pairs
 // (i, i+1) that are read with one 8-byte load per (row, frame, component);
@@ -110,6 +134,9 @@ template <int D>
 __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const float *pl,
                                          long long base, float alpha, float *out)
 {
+    // The blends are written as explicit FMAs with contraction off, so every
+    // kernel (and every frame layout) computes the same bits.
+#pragma clang fp contract(off)
     int lo[3], hi[3];
     float xi[3];
 #pragma unroll
@@ -135,6 +162,52 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
         const unsigned int z0 = n01 * lo[2], z1 = n01 * hi[2];
         row[0] = y0 + z0; row[1] = y1 + z0; row[2] = y0 + z1; row[3] = y1 + z1;
         wr[0] = wy0 * wz0; wr[1] = wy1 * wz0; wr[2] = wy0 * wz1; wr[3] = wy1 * wz1;
+    }
+    if (v.ilv) {
+        // interleaved layout: per (row, frame) the lower and upper node records
+        const long long S = v.ilv;
+        const float *__restrict__ A = v.ilv_u + base * S;
+        const float *__restrict__ B = A + fs * S;
+        float ua[3] = {0.0f, 0.0f, 0.0f}, ub[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (D == 3) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const unsigned int e0 = row[r] + (unsigned int)lo[0];
+                const unsigned int e1 = row[r] + (unsigned int)hi[0];
+                float pa0[3], pa1[3], pb0[3], pb1[3];   // frame f / f+1, node e0 / e1
+                if (S == 4) {
+                    load_rec<4>(A, e0, pa0); load_rec<4>(A, e1, pa1);
+                    load_rec<4>(B, e0, pb0); load_rec<4>(B, e1, pb1);
+                } else {
+                    load_rec<3>(A, e0, pa0); load_rec<3>(A, e1, pa1);
+                    load_rec<3>(B, e0, pb0); load_rec<3>(B, e1, pb1);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    ua[c] = fmaf(wr[r], fmaf(wx1, pa1[c], wx0 * pa0[c]), ua[c]);
+                    ub[c] = fmaf(wr[r], fmaf(wx1, pb1[c], wx0 * pb0[c]), ub[c]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const unsigned int e = row[r] + (unsigned int)px;
+                float4 qa = load_pair2(A, e), qb = load_pair2(B, e);
+                if (wrap) {   // pair (n0-2, n0-1) -> (n0-1, 0)
+                    const float2 za = *reinterpret_cast<const float2 *>(A + (size_t)row[r] * 2u);
+                    const float2 zb = *reinterpret_cast<const float2 *>(B + (size_t)row[r] * 2u);
+                    qa = make_float4(qa.z, qa.w, za.x, za.y);
+                    qb = make_float4(qb.z, qb.w, zb.x, zb.y);
+                }
+                ua[0] = fmaf(wr[r], fmaf(wx1, qa.z, wx0 * qa.x), ua[0]);
+                ua[1] = fmaf(wr[r], fmaf(wx1, qa.w, wx0 * qa.y), ua[1]);
+                ub[0] = fmaf(wr[r], fmaf(wx1, qb.z, wx0 * qb.x), ub[0]);
+                ub[1] = fmaf(wr[r], fmaf(wx1, qb.w, wx0 * qb.y), ub[1]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) out[c] = fmaf(a1, ub[c], a0 * ua[c]);
+        return;
     }
     float2 pa[D][R], pb[D][R];
 #pragma unroll
@@ -165,10 +238,10 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
         float ua = 0.0f, ub = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            ua += wr[r] * (wx0 * pa[c][r].x + wx1 * pa[c][r].y);
-            ub += wr[r] * (wx0 * pb[c][r].x + wx1 * pb[c][r].y);
+            ua = fmaf(wr[r], fmaf(wx1, pa[c][r].y, wx0 * pa[c][r].x), ua);
+            ub = fmaf(wr[r], fmaf(wx1, pb[c][r].y, wx0 * pb[c][r].x), ub);
         }
-        out[c] = a0 * ua + a1 * ub;
+        out[c] = fmaf(a1, ub, a0 * ua);
     }
 }
 
@@ -540,6 +613,21 @@ __global__ LCS_ADVECT_BOUNDS void early_advect_kernel(EarlyAdvArgs A, int first,
     double *P = A.pos + ((long long)e * 7 + slot) * 3;
 #pragma unroll
     for (int a = 0; a < D; ++a) P[a] = (double)xh[a] + (double)xl[a];
+}
+
+// Structure-of-arrays frames -> interleaved (S floats per node; a 4th float
+// of 3D records is 0), frames f_first .. f_first + f_count - 1.
+__global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const float *u0,
+                                                        const float *u1, const float *u2,
+                                                        long long n, long long off, float *out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float *o = out + i * S;
+    o[0] = u0[off + i];
+    o[1] = u1[off + i];
+    if (dim == 3) o[2] = u2[off + i];
+    if (S == 4) o[3] = 0.0f;
 }
 
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
@@ -1015,6 +1103,15 @@ hipError_t launch_early_advect(int dim, const EarlyAdvArgs &a, int first, int co
     dim3 grid((unsigned)((work + 255) / 256)), block(256);
     if (dim == 2) hipLaunchKernelGGL(early_advect_kernel<2>, grid, block, 0, s, a, first, count);
     else hipLaunchKernelGGL(early_advect_kernel<3>, grid, block, 0, s, a, first, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_interleave(int dim, int S, const float *const *u, long long nodes, int f_count,
+                             long long f_first, float *out, hipStream_t s)
+{
+    const long long n = nodes * f_count;
+    hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, S,
+                       u[0], u[1], dim == 3 ? u[2] : u[1], n, f_first * nodes, out);
     return hipGetLastError();
 }
 

@@ -51,7 +51,14 @@ lcs_status check_velocity(const lcs_velocity_t *v)
 {
     if (!v) return lcs::set_error(LCS_E_ARG, "velocity descriptor is NULL");
     if (v->dim != 2 && v->dim != 3) return lcs::set_error(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
-    if (v->reserved != 0) return lcs::set_error(LCS_E_ARG, "velocity reserved field must be 0");
+    if (v->layout > LCS_LAYOUT_XYZW || (v->layout == LCS_LAYOUT_XYZW && v->dim != 3))
+        return lcs::set_error(LCS_E_ARG, "velocity layout %u is not valid for %dD", v->layout, v->dim);
+    if (v->layout != LCS_LAYOUT_SOA) {
+        const uintptr_t align = (v->layout == LCS_LAYOUT_XYZW) ? 16u : (v->dim == 2 ? 8u : 4u);
+        if (!v->u[0]) return lcs::set_error(LCS_E_ARG, "interleaved frames pointer u[0] is NULL");
+        if (reinterpret_cast<uintptr_t>(v->u[0]) % align)
+            return lcs::set_error(LCS_E_ARG, "interleaved frames must be %d-byte aligned", (int)align);
+    }
     if (v->n_frames < 2) return lcs::set_error(LCS_E_SHAPE, "need at least 2 frames (got %d)", v->n_frames);
     if (!finite_pos(v->dt_frame) || !isfinite(v->t_first))
         return lcs::set_error(LCS_E_ARG, "t_first must be finite and dt_frame > 0");
@@ -62,7 +69,8 @@ lcs_status check_velocity(const lcs_velocity_t *v)
             if (v->n[a] < 2) return lcs::set_error(LCS_E_SHAPE, "velocity axis %d needs >= 2 nodes", a);
             if (!finite_pos(v->spacing[a]) || !isfinite(v->origin[a]))
                 return lcs::set_error(LCS_E_ARG, "velocity axis %d: bad origin/spacing", a);
-            if (!v->u[a]) return lcs::set_error(LCS_E_ARG, "velocity component %d pointer is NULL", a);
+            if (v->layout == LCS_LAYOUT_SOA && !v->u[a])
+                return lcs::set_error(LCS_E_ARG, "velocity component %d pointer is NULL", a);
         } else if (v->n[a] != 1) {
             return lcs::set_error(LCS_E_SHAPE, "velocity n[%d] must be 1 in %dD", a, v->dim);
         }
@@ -132,8 +140,12 @@ lcs::VelDev make_vel(const lcs_velocity_t *v)
     lcs::VelDev d;
     memset(&d, 0, sizeof(d));
     d.frame_stride = v->n[0] * v->n[1] * v->n[2];
+    if (v->layout != LCS_LAYOUT_SOA) {
+        d.ilv = (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
+        d.ilv_u = v->u[0];
+    }
     for (int a = 0; a < 3; ++a) {
-        d.u[a] = a < v->dim ? v->u[a] : nullptr;
+        d.u[a] = (a < v->dim && v->layout == LCS_LAYOUT_SOA) ? v->u[a] : nullptr;
         d.n[a] = (int)v->n[a];
         d.nf[a] = (float)v->n[a];
         const double inv = 1.0 / v->spacing[a];
@@ -280,6 +292,37 @@ lcs_status lcs_sync_status(void *stream)
     if (e != hipSuccess) return lcs::hip_error(e, "hipStreamSynchronize");
     e = hipGetLastError();
     if (e != hipSuccess) return lcs::hip_error(e, "pending error");
+    return lcs::clear_error();
+}
+
+lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int32_t f_first,
+                                 int32_t f_count, float *out, lcs_velocity_t *out_desc,
+                                 void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(soa)) != LCS_OK) return st;
+    if (soa->layout != LCS_LAYOUT_SOA) return lcs::set_error(LCS_E_ARG, "source frames must be LCS_LAYOUT_SOA");
+    if (layout != LCS_LAYOUT_XYZ && !(layout == LCS_LAYOUT_XYZW && soa->dim == 3))
+        return lcs::set_error(LCS_E_ARG, "target layout must be LCS_LAYOUT_XYZ (or XYZW in 3D)");
+    if (!out || !out_desc) return lcs::set_error(LCS_E_ARG, "out and out_desc must not be NULL");
+    if (f_first < 0 || f_count < 2 || (long long)f_first + f_count > soa->n_frames)
+        return lcs::set_error(LCS_E_SHAPE, "frame span [%d, %d) outside [0, %d) or shorter than 2",
+                              f_first, f_first + f_count, soa->n_frames);
+    const int S = (layout == LCS_LAYOUT_XYZW) ? 4 : soa->dim;
+    const uintptr_t align = (S == 4) ? 16u : (soa->dim == 2 ? 8u : 4u);
+    if (reinterpret_cast<uintptr_t>(out) % align)
+        return lcs::set_error(LCS_E_ARG, "out must be %d-byte aligned", (int)align);
+    const long long nodes = soa->n[0] * soa->n[1] * soa->n[2];
+    hipError_t e = lcs::launch_interleave(soa->dim, S, soa->u, nodes, f_count, f_first, out,
+                                          (hipStream_t)stream);
+    if (e != hipSuccess) return lcs::hip_error(e, "interleave launch");
+    *out_desc = *soa;
+    out_desc->layout = layout;
+    out_desc->n_frames = f_count;
+    out_desc->t_first = soa->t_first + (double)f_first * soa->dt_frame;
+    out_desc->u[0] = out;
+    out_desc->u[1] = nullptr;
+    out_desc->u[2] = nullptr;
     return lcs::clear_error();
 }
 

@@ -15,7 +15,9 @@ constexpr int kWave = 64;   // CDNA wavefront width
 // drive the FP32 advection; the FP64 copies are used only for the FP64 cell
 // index of the returned positions.
 struct VelDev {
-    const float *u[3];
+    const float *u[3];        // structure-of-arrays components (ilv == 0)
+    const float *ilv_u;       // interleaved frames (ilv = floats per node: 2, 3 or 4)
+    int ilv;
     long long frame_stride;   // n0*n1*n2
     int n[3];
     float nf[3];
@@ -350,6 +352,8 @@ lcs_status clear_error();
 lcs_status hip_error(hipError_t e, const char *where);
 
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
+hipError_t launch_interleave(int dim, int S, const float *const *u, long long nodes, int f_count,
+                             long long f_first, float *out, hipStream_t s);
 hipError_t launch_advect_ab(int dim, int order, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s);
 hipError_t launch_advect_snap(int dim, const SnapArgs &a, hipStream_t s);

@@ -415,6 +415,7 @@ __device__ __forceinline__ void mesh_velocity(const MeshDev &m, const MeshFrames
                                               const float *lam, long long base, float alpha,
                                               float *out)
 {
+#pragma clang fp contract(off)
     const int4 cn = m.conn[c];
     const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
     const float *A = f.u + base;
@@ -453,7 +454,7 @@ __device__ __forceinline__ void mesh_velocity(const MeshDev &m, const MeshFrames
     }
     const float a1 = alpha, a0 = 1.0f - alpha;
 #pragma unroll
-    for (int k = 0; k < D; ++k) out[k] = a0 * ua[k] + a1 * ub[k];
+    for (int k = 0; k < D; ++k) out[k] = fmaf(a1, ub[k], a0 * ua[k]);
 }
 
 // Stage point: finite, then located by a walk from cell c (updated).

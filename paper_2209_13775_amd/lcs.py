@@ -45,7 +45,7 @@ class LcsError(RuntimeError):
 class lcs_velocity_t(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_frames", C.c_int32), ("n", C.c_int64 * 3),
                 ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
-                ("periodic_mask", C.c_uint32), ("reserved", C.c_uint32),
+                ("periodic_mask", C.c_uint32), ("layout", C.c_uint32),
                 ("t_first", C.c_double), ("dt_frame", C.c_double),
                 ("u", C.c_void_p * 3)]
 
@@ -91,6 +91,7 @@ def _load(path: str = LIB_PATH):
         "lcs_sub": [P, P, I64, P, P],
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
+        "lcs_frames_interleave": [P, C.c_uint32, I32, I32, P, P, P],
         "lcs_advect_aux": [P, P, P, D, D, D, P, P, P, P],
         "lcs_cg_eig": [I32, I64, P, P, P, P],
         "lcs_advect_ab_sorted": [P, P, I32, D, D, D, I32, P, P, P, P, I64, P],
@@ -211,7 +212,7 @@ class DeviceFrames:
             d.origin[a] = float(fs.origin[a])
             d.spacing[a] = float(fs.spacing[a])
         d.periodic_mask = int(fs.periodic_mask)
-        d.reserved = 0
+        d.layout = LCS_LAYOUT_SOA
         d.t_first = float(fs.t_first)
         d.dt_frame = float(fs.dt_frame)
         nodes = int(fs.n[0] * fs.n[1] * fs.n[2])
@@ -233,6 +234,42 @@ class DeviceFrames:
     @property
     def ref(self):
         return C.byref(self.desc)
+
+    @classmethod
+    def interleaved(cls, fs, layout: str = "xyz", device="cuda", stream=None) -> "DeviceFrames":
+        """Frames of the FrameSet fs staged on the device in an interleaved layout
+        ("xyz": dim floats per node, "xyzw": 4 in 3D) by lcs_frames_interleave."""
+        return lcs_frames_interleave(cls(fs, device=device), layout, stream=stream)
+
+
+LCS_LAYOUT_SOA, LCS_LAYOUT_XYZ, LCS_LAYOUT_XYZW = 0, 1, 2
+
+
+class _InterleavedFrames(DeviceFrames):
+    """Frames in an interleaved layout: one tensor (F, N, S) and its descriptor."""
+
+    def __init__(self, fs, tensor, desc):     # noqa: D401 (no SoA construction)
+        self.fs = fs
+        self.u = [tensor]
+        self.desc = desc
+
+
+def lcs_frames_interleave(frames: DeviceFrames, layout: str = "xyz", f_first: int = 0,
+                          f_count: Optional[int] = None, out=None, stream=None) -> DeviceFrames:
+    """Copy (a span of) structure-of-arrays frames into the interleaved layout."""
+    torch = _torch()
+    lay = {"xyz": LCS_LAYOUT_XYZ, "xyzw": LCS_LAYOUT_XYZW}[layout]
+    d = frames.desc
+    F = int(d.n_frames) if f_count is None else int(f_count)
+    N = int(d.n[0] * d.n[1] * d.n[2])
+    S = 4 if lay == LCS_LAYOUT_XYZW else int(d.dim)
+    if out is None:
+        out = torch.empty((F, N, S), dtype=torch.float32, device=frames.u[0].device)
+    _need(out, torch.float32, (F, N, S), "out")
+    nd = lcs_velocity_t()
+    _check(_lib.lcs_frames_interleave(frames.ref, lay, int(f_first), F, _ptr(out), C.byref(nd),
+                                      _stream_handle(stream)))
+    return _InterleavedFrames(frames.fs, out, nd)
 
 
 def seed_grid_desc(g) -> lcs_seed_grid_t:

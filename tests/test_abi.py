@@ -62,7 +62,9 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("time_range", lcs.LCS_E_TIME_RANGE),
     ("seed_outside", lcs.LCS_E_SEED_DOMAIN),
     ("periodic_seed_on_closed_axis", lcs.LCS_E_ARG),
-    ("reserved", lcs.LCS_E_ARG),
+    ("bad_layout", lcs.LCS_E_ARG),
+    ("xyzw_in_2d", lcs.LCS_E_ARG),
+    ("misaligned_interleaved", lcs.LCS_E_ARG),
 ])
 def test_advect_validation(case, expect):
     v, s = _vel(), _seeds()
@@ -91,8 +93,13 @@ def test_advect_validation(case, expect):
         s.origin[0] = 0.7  # 0.7 + 2*0.2 = 1.1 > 4*0.25
     elif case == "periodic_seed_on_closed_axis":
         s.periodic_mask = 1
-    elif case == "reserved":
-        v.reserved = 7
+    elif case == "bad_layout":
+        v.layout = 7
+    elif case == "xyzw_in_2d":
+        v.layout = lcs.LCS_LAYOUT_XYZW
+    elif case == "misaligned_interleaved":
+        v.layout = lcs.LCS_LAYOUT_XYZ
+        v.u[0] = 0x1004                # 2D interleaved frames need 8-byte alignment
     st = _advect(v, s, t0, T, dt, xf)
     assert st == expect, lcs.lcs_last_error()
     assert lcs.lcs_last_error() != ""
@@ -170,3 +177,20 @@ def test_mesh_entry_points_validate():
     assert L.lcs_mesh_locate(None, 0x10, 4, 0x20, None, None) == lcs.LCS_E_ARG
     assert L.lcs_mesh_velocity_at(None, C.byref(f), 0x10, 0x20, 4, 0x30, None, None) == lcs.LCS_E_ARG
     L.lcs_mesh_destroy(None)
+
+
+def test_frames_interleave_validates():
+    L = lcs.lib()
+    v = _vel()
+    out_desc = lcs.lcs_velocity_t()
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZW, 0, 2, 0x1000, C.byref(out_desc),
+                                   None) == lcs.LCS_E_ARG          # XYZW is 3D only
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 1, 0x1000, C.byref(out_desc),
+                                   None) == lcs.LCS_E_SHAPE        # fewer than 2 frames
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 1, 9, 0x1000, C.byref(out_desc),
+                                   None) == lcs.LCS_E_SHAPE        # past the last frame
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 2, None, C.byref(out_desc),
+                                   None) == lcs.LCS_E_ARG
+    v.layout = lcs.LCS_LAYOUT_XYZ
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 2, 0x1000, C.byref(out_desc),
+                                   None) == lcs.LCS_E_ARG          # source must be SoA
