@@ -125,14 +125,116 @@ __device__ __forceinline__ float4 load_pair2(const float *frame, unsigned int no
     return q;
 }
 
+// Corner values of the cell a tracer sampled last, for both frames of the
+// pair, kept in registers: consecutive RK4 stage points mostly fall in the
+// same cell of the same frame pair (frames change only every dt_frame/dt
+// steps), and then the gathers are skipped.  The values are the same either
+// way, so the result does not depend on whether the cache is used.
+#ifndef LCS_CELL_CACHE
+#define LCS_CELL_CACHE 1
+#endif
+
+template <int D>
+struct CellCache {
+    static constexpr int R = (D == 2) ? 2 : 4;    // rows of 2 corners
+    unsigned int node = ~0u;  // lower-corner node of the cached cell (~0u: empty)
+    long long base = -1;      // frame base of the cached pair
+    float c[2][R][2][D];      // [frame f/f+1][row][lower/upper node][component]
+};
+
+// Gather the corner values of the cell (rows row[], x nodes lo0/hi0, the pair
+// starting at px) for the frames at base and base + frame_stride.
+template <int D>
+__device__ __forceinline__ void gather_cell(const VelDev &v, long long base, const unsigned int *row,
+                                            int lo0, int hi0, int px, bool wrap,
+                                            float (&c)[2][CellCache<D>::R][2][D])
+{
+    constexpr int R = CellCache<D>::R;
+    const long long fs = v.frame_stride;
+    if (v.ilv) {
+        // interleaved layout: per (row, frame) the lower and upper node records
+        const long long S = v.ilv;
+        const float *__restrict__ A = v.ilv_u + base * S;
+        const float *__restrict__ B = A + fs * S;
+        if constexpr (D == 3) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const unsigned int e0 = row[r] + (unsigned int)lo0;
+                const unsigned int e1 = row[r] + (unsigned int)hi0;
+                if (S == 4) {
+                    load_rec<4>(A, e0, c[0][r][0]); load_rec<4>(A, e1, c[0][r][1]);
+                    load_rec<4>(B, e0, c[1][r][0]); load_rec<4>(B, e1, c[1][r][1]);
+                } else {
+                    load_rec<3>(A, e0, c[0][r][0]); load_rec<3>(A, e1, c[0][r][1]);
+                    load_rec<3>(B, e0, c[1][r][0]); load_rec<3>(B, e1, c[1][r][1]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const unsigned int e = row[r] + (unsigned int)px;
+                float4 qa = load_pair2(A, e), qb = load_pair2(B, e);
+                if (wrap) {   // pair (n0-2, n0-1) -> (n0-1, 0)
+                    const float2 za = *reinterpret_cast<const float2 *>(A + (size_t)row[r] * 2u);
+                    const float2 zb = *reinterpret_cast<const float2 *>(B + (size_t)row[r] * 2u);
+                    qa = make_float4(qa.z, qa.w, za.x, za.y);
+                    qb = make_float4(qb.z, qb.w, zb.x, zb.y);
+                }
+                c[0][r][0][0] = qa.x; c[0][r][0][1] = qa.y; c[0][r][1][0] = qa.z; c[0][r][1][1] = qa.w;
+                c[1][r][0][0] = qb.x; c[1][r][0][1] = qb.y; c[1][r][1][0] = qb.z; c[1][r][1][1] = qb.w;
+            }
+        }
+        return;
+    }
+    // structure of arrays: one 8-byte pair load per (row, frame, component)
+    float2 pa[D][R], pb[D][R];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float *__restrict__ A = v.u[k] + base;
+        const float *__restrict__ B = A + fs;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pa[k][r] = load_pair(A, row[r] + (unsigned int)px);
+            pb[k][r] = load_pair(B, row[r] + (unsigned int)px);
+        }
+    }
+    if (wrap) {
+        // cell (n0-1, 0): the loaded pair is (n0-2, n0-1); shift it and fetch node 0
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float *__restrict__ A = v.u[k] + base;
+            const float *__restrict__ B = A + fs;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                pa[k][r] = make_float2(pa[k][r].y, A[row[r]]);
+                pb[k][r] = make_float2(pb[k][r].y, B[row[r]]);
+            }
+        }
+    }
+    // stored in the order of the interleaved fill above (row, frame, node,
+    // component), so that the two fills end in the same stores
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) c[0][r][0][k] = pa[k][r].x;
+#pragma unroll
+        for (int k = 0; k < D; ++k) c[0][r][1][k] = pa[k][r].y;
+#pragma unroll
+        for (int k = 0; k < D; ++k) c[1][r][0][k] = pb[k][r].x;
+#pragma unroll
+        for (int k = 0; k < D; ++k) c[1][r][1][k] = pb[k][r].y;
+    }
+}
+
 // u at the two-float point (ph + pl): multilinear in space within frames f and
 // f+1, then linear in time.  The corners of a cell come in x-adjacent pairs
-// (i, i+1) that are read with one 8-byte load per (row, frame, component);
-// on a periodic x axis the pair of the last cell wraps to node 0 and is
-// patched by a rarely taken branch.
+// (i, i+1); on a periodic x axis the pair of the last cell wraps to node 0.
+// The corner values are reused while the tracer stays in the cell and frame
+// pair of its previous evaluation (cc).
 template <int D>
 __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const float *pl,
-                                         long long base, float alpha, float *out)
+                                         long long base, float alpha, float *out,
+                                         CellCache<D> &cc)
 {
     // The blends are written as explicit FMAs with contraction off, so every
     // kernel (and every frame layout) computes the same bits.
@@ -142,12 +244,11 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
 #pragma unroll
     for (int a = 0; a < D; ++a) locate(v, a, ph[a], pl[a], lo[a], hi[a], xi[a]);
     const float a1 = alpha, a0 = 1.0f - alpha;
-    const long long fs = v.frame_stride;
     const int n0 = v.n[0];
     const bool wrap = (hi[0] != lo[0] + 1);          // periodic x, last cell
-    const int px = wrap ? n0 - 2 : lo[0];             // start of the loaded pair
+    const int px = wrap ? n0 - 2 : lo[0];             // start of the x pair
     const float wx1 = xi[0], wx0 = 1.0f - xi[0];
-    constexpr int R = (D == 2) ? 2 : 4;               // rows of 2 corners
+    constexpr int R = CellCache<D>::R;
     unsigned int row[R];
     float wr[R];
     if constexpr (D == 2) {
@@ -163,85 +264,21 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
         row[0] = y0 + z0; row[1] = y1 + z0; row[2] = y0 + z1; row[3] = y1 + z1;
         wr[0] = wy0 * wz0; wr[1] = wy1 * wz0; wr[2] = wy0 * wz1; wr[3] = wy1 * wz1;
     }
-    if (v.ilv) {
-        // interleaved layout: per (row, frame) the lower and upper node records
-        const long long S = v.ilv;
-        const float *__restrict__ A = v.ilv_u + base * S;
-        const float *__restrict__ B = A + fs * S;
-        float ua[3] = {0.0f, 0.0f, 0.0f}, ub[3] = {0.0f, 0.0f, 0.0f};
-        if constexpr (D == 3) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned int e0 = row[r] + (unsigned int)lo[0];
-                const unsigned int e1 = row[r] + (unsigned int)hi[0];
-                float pa0[3], pa1[3], pb0[3], pb1[3];   // frame f / f+1, node e0 / e1
-                if (S == 4) {
-                    load_rec<4>(A, e0, pa0); load_rec<4>(A, e1, pa1);
-                    load_rec<4>(B, e0, pb0); load_rec<4>(B, e1, pb1);
-                } else {
-                    load_rec<3>(A, e0, pa0); load_rec<3>(A, e1, pa1);
-                    load_rec<3>(B, e0, pb0); load_rec<3>(B, e1, pb1);
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    ua[c] = fmaf(wr[r], fmaf(wx1, pa1[c], wx0 * pa0[c]), ua[c]);
-                    ub[c] = fmaf(wr[r], fmaf(wx1, pb1[c], wx0 * pb0[c]), ub[c]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned int e = row[r] + (unsigned int)px;
-                float4 qa = load_pair2(A, e), qb = load_pair2(B, e);
-                if (wrap) {   // pair (n0-2, n0-1) -> (n0-1, 0)
-                    const float2 za = *reinterpret_cast<const float2 *>(A + (size_t)row[r] * 2u);
-                    const float2 zb = *reinterpret_cast<const float2 *>(B + (size_t)row[r] * 2u);
-                    qa = make_float4(qa.z, qa.w, za.x, za.y);
-                    qb = make_float4(qb.z, qb.w, zb.x, zb.y);
-                }
-                ua[0] = fmaf(wr[r], fmaf(wx1, qa.z, wx0 * qa.x), ua[0]);
-                ua[1] = fmaf(wr[r], fmaf(wx1, qa.w, wx0 * qa.y), ua[1]);
-                ub[0] = fmaf(wr[r], fmaf(wx1, qb.z, wx0 * qb.x), ub[0]);
-                ub[1] = fmaf(wr[r], fmaf(wx1, qb.w, wx0 * qb.y), ub[1]);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < D; ++c) out[c] = fmaf(a1, ub[c], a0 * ua[c]);
-        return;
-    }
-    float2 pa[D][R], pb[D][R];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-        const float *__restrict__ A = v.u[c] + base;
-        const float *__restrict__ B = A + fs;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            pa[c][r] = load_pair(A, row[r] + (unsigned int)px);
-            pb[c][r] = load_pair(B, row[r] + (unsigned int)px);
-        }
-    }
-    if (wrap) {
-        // cell (n0-1, 0): the loaded pair is (n0-2, n0-1); shift it and fetch node 0
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const float *__restrict__ A = v.u[c] + base;
-            const float *__restrict__ B = A + fs;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                pa[c][r] = make_float2(pa[c][r].y, A[row[r]]);
-                pb[c][r] = make_float2(pb[c][r].y, B[row[r]]);
-            }
-        }
+    const unsigned int key = row[0] + (unsigned int)lo[0];   // the cell's lower-corner node
+    if (!LCS_CELL_CACHE || cc.node != key || cc.base != base) {
+        gather_cell<D>(v, base, row, lo[0], hi[0], px, wrap, cc.c);
+        cc.node = key;
+        cc.base = base;
     }
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
+    for (int k = 0; k < D; ++k) {
         float ua = 0.0f, ub = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            ua = fmaf(wr[r], fmaf(wx1, pa[c][r].y, wx0 * pa[c][r].x), ua);
-            ub = fmaf(wr[r], fmaf(wx1, pb[c][r].y, wx0 * pb[c][r].x), ub);
+            ua = fmaf(wr[r], fmaf(wx1, cc.c[0][r][1][k], wx0 * cc.c[0][r][0][k]), ua);
+            ub = fmaf(wr[r], fmaf(wx1, cc.c[1][r][1][k], wx0 * cc.c[1][r][0][k]), ub);
         }
-        out[c] = fmaf(a1, ub, a0 * ua);
+        out[k] = fmaf(a1, ub, a0 * ua);
     }
 }
 
@@ -268,6 +305,7 @@ __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
+    CellCache<D> cc;
     for (int n = n_begin; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1, b2, b4;
@@ -283,22 +321,22 @@ __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t
         }
         float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
 
-        velocity<D>(v, xh, xl, b1, al1, k1);
+        velocity<D>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b2, al2, k2);
+        velocity<D>(v, ph, pl, b2, al2, k2, cc);
         if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b2, al2, k3);
+        velocity<D>(v, ph, pl, b2, al2, k3, cc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b4, al4, k4);
+        velocity<D>(v, ph, pl, b4, al4, k4, cc);
         if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 
         // (xh, xl) <- (xh, xl) + dt/6 (k1 + 2k2 + 2k3 + k4)
@@ -426,13 +464,14 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
     const StepConsts sc = step_consts(dt);
     const double cab = dt / ab_den<S>();
     const float ch = (float)cab, cl = (float)(cab - (double)ch);
+    CellCache<D> cc;
     for (int n = n_begin; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1;
         float al1;
         frame_at_uniform(v, t, b1, al1);
         float k1[3];
-        velocity<D>(v, xh, xl, b1, al1, k1);
+        velocity<D>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         float nh[3], nl[3];
         if (n < S - 1) {
@@ -443,15 +482,15 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
             float k2[3], k3[3], k4[3], ph[3], pl[3];
             stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b2, al2, k2);
+            velocity<D>(v, ph, pl, b2, al2, k2, cc);
             if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b2, al2, k3);
+            velocity<D>(v, ph, pl, b2, al2, k3, cc);
             if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b4, al4, k4);
+            velocity<D>(v, ph, pl, b4, al4, k4, cc);
             if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 #pragma unroll
             for (int a = 0; a < D; ++a) {

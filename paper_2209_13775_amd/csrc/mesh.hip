@@ -325,21 +325,40 @@ __device__ __forceinline__ void barycentric(const float4 *q, const float *ph, co
     }
 }
 
+#ifndef LCS_MESH_CACHE
+#define LCS_MESH_CACHE 1
+#endif
+
+// Per-tracer copies, in registers, of the geometry of the cell visited last
+// and of the node values of the cell and frame pair sampled last.  RK4 stage
+// points and successive steps mostly stay in one cell, and then the loads are
+// skipped; the values are the same either way.
+template <int D>
+struct MeshCache {
+    int gcell = -1;                  // cell whose geometry is in q (-1: none)
+    float4 q[MeshGeo<D>::G];
+    int vcell = -1;                  // cell whose node values are in ua/ub (-1: none)
+    long long vbase = -1;            // frame base of those values
+    float ua[D + 1][D], ub[D + 1][D];   // [node][component], frames f and f+1
+};
+
 // Local cell search from cell c (updated in place).  Returns 0 with lam set
 // when the point is in c (every coordinate >= -eps), kOut when the walk
 // reaches a boundary face, kLost after max_walk steps.  The point must be
 // finite.
 template <int D>
 __device__ __forceinline__ uint32_t walk(const MeshDev &m, const float *ph, const float *pl, int &c,
-                                         float *lam)
+                                         float *lam, MeshCache<D> &mc)
 {
     constexpr int G = MeshGeo<D>::G;
     for (int s = 0; s < m.max_walk; ++s) {
-        const float4 *g = m.geo + (long long)c * G;
-        float4 q[G];
+        if (!LCS_MESH_CACHE || c != mc.gcell) {
+            const float4 *g = m.geo + (long long)c * G;
 #pragma unroll
-        for (int i = 0; i < G; ++i) q[i] = g[i];
-        barycentric<D>(q, ph, pl, lam);
+            for (int i = 0; i < G; ++i) mc.q[i] = g[i];
+            mc.gcell = c;
+        }
+        barycentric<D>(mc.q, ph, pl, lam);
         float lmin = lam[0];
         int imin = 0;
 #pragma unroll
@@ -360,7 +379,7 @@ __device__ __forceinline__ uint32_t walk(const MeshDev &m, const float *ph, cons
 // First location of a point: start cell from its bucket, then the walk.
 template <int D>
 __device__ __forceinline__ uint32_t first_locate(const MeshDev &m, const float *ph, const float *pl,
-                                                 int &c, float *lam)
+                                                 int &c, float *lam, MeshCache<D> &mc)
 {
     long long b = 0, stride = 1;
 #pragma unroll
@@ -372,7 +391,7 @@ __device__ __forceinline__ uint32_t first_locate(const MeshDev &m, const float *
     }
     c = m.loc[b];
     if (c < 0) return kOut;
-    return walk<D>(m, ph, pl, c, lam);
+    return walk<D>(m, ph, pl, c, lam, mc);
 }
 
 __device__ __forceinline__ void mesh_frame_at(const MeshFramesDev &f, double t, long long &base,
@@ -413,45 +432,37 @@ __device__ __forceinline__ float2 load_node2(const float *base, int node)
 template <int D>
 __device__ __forceinline__ void mesh_velocity(const MeshDev &m, const MeshFramesDev &f, int c,
                                               const float *lam, long long base, float alpha,
-                                              float *out)
+                                              float *out, MeshCache<D> &mc)
 {
 #pragma clang fp contract(off)
-    const int4 cn = m.conn[c];
-    const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
-    const float *A = f.u + base;
-    const float *B = A + f.frame_stride;
-    float ua[3] = {0.0f, 0.0f, 0.0f}, ub[3] = {0.0f, 0.0f, 0.0f};
-    if constexpr (D == 3) {
-        float4 va[4], vb[4];
+    if (!LCS_MESH_CACHE || c != mc.vcell || base != mc.vbase) {
+        const int4 cn = m.conn[c];
+        const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
+        const float *A = f.u + base;
+        const float *B = A + f.frame_stride;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            va[i] = load_node4(A, nd[i]);
-            vb[i] = load_node4(B, nd[i]);
+        for (int i = 0; i <= D; ++i) {
+            if constexpr (D == 3) {
+                const float4 va = load_node4(A, nd[i]), vb = load_node4(B, nd[i]);
+                mc.ua[i][0] = va.x; mc.ua[i][1] = va.y; mc.ua[i][2] = va.z;
+                mc.ub[i][0] = vb.x; mc.ub[i][1] = vb.y; mc.ub[i][2] = vb.z;
+            } else {
+                const float2 va = load_node2(A, nd[i]), vb = load_node2(B, nd[i]);
+                mc.ua[i][0] = va.x; mc.ua[i][1] = va.y;
+                mc.ub[i][0] = vb.x; mc.ub[i][1] = vb.y;
+            }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ua[0] = fmaf(lam[i], va[i].x, ua[0]);
-            ua[1] = fmaf(lam[i], va[i].y, ua[1]);
-            ua[2] = fmaf(lam[i], va[i].z, ua[2]);
-            ub[0] = fmaf(lam[i], vb[i].x, ub[0]);
-            ub[1] = fmaf(lam[i], vb[i].y, ub[1]);
-            ub[2] = fmaf(lam[i], vb[i].z, ub[2]);
-        }
-    } else {
-        float2 va[3], vb[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            va[i] = load_node2(A, nd[i]);
-            vb[i] = load_node2(B, nd[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ua[0] = fmaf(lam[i], va[i].x, ua[0]);
-            ua[1] = fmaf(lam[i], va[i].y, ua[1]);
-            ub[0] = fmaf(lam[i], vb[i].x, ub[0]);
-            ub[1] = fmaf(lam[i], vb[i].y, ub[1]);
-        }
+        mc.vcell = c;
+        mc.vbase = base;
     }
+    float ua[3] = {0.0f, 0.0f, 0.0f}, ub[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i <= D; ++i)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ua[k] = fmaf(lam[i], mc.ua[i][k], ua[k]);
+            ub[k] = fmaf(lam[i], mc.ub[i][k], ub[k]);
+        }
     const float a1 = alpha, a0 = 1.0f - alpha;
 #pragma unroll
     for (int k = 0; k < D; ++k) out[k] = fmaf(a1, ub[k], a0 * ua[k]);
@@ -460,10 +471,10 @@ __device__ __forceinline__ void mesh_velocity(const MeshDev &m, const MeshFrames
 // Stage point: finite, then located by a walk from cell c (updated).
 template <int D>
 __device__ __forceinline__ uint32_t stage_locate(const MeshDev &m, const float *ph, const float *pl,
-                                                 int &c, float *lam)
+                                                 int &c, float *lam, MeshCache<D> &mc)
 {
     if (!finite_vec<D>(ph)) return kNonFinite;
-    return walk<D>(m, ph, pl, c, lam);
+    return walk<D>(m, ph, pl, c, lam, mc);
 }
 
 // Classical RK4 on the mesh field for steps 0 <= n < nsteps from t0, the
@@ -475,7 +486,7 @@ __device__ __forceinline__ uint32_t stage_locate(const MeshDev &m, const float *
 template <int D, bool UNIFORM_T>
 __device__ uint32_t mesh_advect_steps(const MeshDev &m, const MeshFramesDev &f, float *xh,
                                       float *xl, int &c, float *lam, double t0, double dt,
-                                      int nsteps)
+                                      int nsteps, MeshCache<D> &mc)
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
@@ -495,22 +506,22 @@ __device__ uint32_t mesh_advect_steps(const MeshDev &m, const MeshFramesDev &f, 
         float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3], ls[4];
         int cs = c;
 
-        mesh_velocity<D>(m, f, c, lam, b1, al1, k1);
+        mesh_velocity<D>(m, f, c, lam, b1, al1, k1, mc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
-        if ((fl = stage_locate<D>(m, ph, pl, cs, ls))) break;
+        if ((fl = stage_locate<D>(m, ph, pl, cs, ls, mc))) break;
 
-        mesh_velocity<D>(m, f, cs, ls, b2, al2, k2);
+        mesh_velocity<D>(m, f, cs, ls, b2, al2, k2, mc);
         if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
-        if ((fl = stage_locate<D>(m, ph, pl, cs, ls))) break;
+        if ((fl = stage_locate<D>(m, ph, pl, cs, ls, mc))) break;
 
-        mesh_velocity<D>(m, f, cs, ls, b2, al2, k3);
+        mesh_velocity<D>(m, f, cs, ls, b2, al2, k3, mc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
-        if ((fl = stage_locate<D>(m, ph, pl, cs, ls))) break;
+        if ((fl = stage_locate<D>(m, ph, pl, cs, ls, mc))) break;
 
-        mesh_velocity<D>(m, f, cs, ls, b4, al4, k4);
+        mesh_velocity<D>(m, f, cs, ls, b4, al4, k4, mc);
         if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 
         float nh[3], nl[3];
@@ -520,7 +531,7 @@ __device__ uint32_t mesh_advect_steps(const MeshDev &m, const MeshFramesDev &f, 
             const float inc = fmaf(sc.sh, sum, sc.sl * sum);
             two_sum(xh[a], xl[a] + inc, nh[a], nl[a]);
         }
-        if ((fl = stage_locate<D>(m, nh, nl, cs, ls))) break;
+        if ((fl = stage_locate<D>(m, nh, nl, cs, ls, mc))) break;
 #pragma unroll
         for (int a = 0; a < D; ++a) { xh[a] = nh[a]; xl[a] = nl[a]; }
         c = cs;
@@ -545,9 +556,11 @@ __global__ LCS_MESH_BOUNDS void mesh_advect_grid_kernel(MeshAdvectArgs A)
         xl[a] = (float)(x0 - (double)xh[a]);
     }
     int c = -1;
-    uint32_t fl = first_locate<D>(A.m, xh, xl, c, lam);
+    MeshCache<D> mc;
+    uint32_t fl = first_locate<D>(A.m, xh, xl, c, lam, mc);
     const bool located = (fl == 0);
-    if (located) fl = mesh_advect_steps<D, true>(A.m, A.f, xh, xl, c, lam, A.t0, A.dt, A.nsteps);
+    if (located)
+        fl = mesh_advect_steps<D, true>(A.m, A.f, xh, xl, c, lam, A.t0, A.dt, A.nsteps, mc);
 #pragma unroll
     for (int a = 0; a < D; ++a) A.xf[a * A.ns + s] = xh[a] + xl[a];
     if (A.cell) A.cell[s] = located ? (long long)c : -1LL;
@@ -566,16 +579,18 @@ __global__ LCS_MESH_BOUNDS void mesh_advect_points_kernel(MeshAdvectArgs A)
     const double t1 = t0 + A.T;
     uint32_t fl;
     int c = -1;
+    MeshCache<D> mc;
     bool located = false;
     if (!(t0 >= A.f.t_first && t0 <= A.f.t_last && t1 >= A.f.t_first && t1 <= A.f.t_last)) {
         fl = kTimeOut;
     } else if (!finite_vec<D>(xh)) {
         fl = kNonFinite;
     } else {
-        fl = first_locate<D>(A.m, xh, xl, c, lam);
+        fl = first_locate<D>(A.m, xh, xl, c, lam, mc);
         located = (fl == 0);
         if (located)
-            fl = mesh_advect_steps<D, false>(A.m, A.f, xh, xl, c, lam, t0, A.dt, A.nsteps);
+            fl = mesh_advect_steps<D, false>(A.m, A.f, xh, xl, c, lam, t0, A.dt, A.nsteps,
+                                             mc);
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) A.xf[a * A.ns + p] = xh[a] + xl[a];
@@ -593,9 +608,10 @@ __global__ __launch_bounds__(256) void mesh_locate_kernel(MeshDev m, const float
 #pragma unroll
     for (int a = 0; a < D; ++a) xh[a] = x[a * n + p];
     int c = -1;
+    MeshCache<D> mc;
     long long r = -1;
     if (finite_vec<D>(xh)) {
-        const uint32_t fl = first_locate<D>(m, xh, xl, c, lam);
+        const uint32_t fl = first_locate<D>(m, xh, xl, c, lam, mc);
         r = (fl == 0) ? (long long)c : (fl == kLost ? -2LL : -1LL);
     }
     cell[p] = r;
@@ -615,10 +631,11 @@ __global__ __launch_bounds__(256) void mesh_velocity_kernel(MeshDev m, MeshFrame
 #pragma unroll
     for (int a = 0; a < D; ++a) xh[a] = x[a * n + p];
     int c = -1;
+    MeshCache<D> mc;
     long long r = -1;
     bool ok = false;
     if (finite_vec<D>(xh)) {
-        const uint32_t fl = first_locate<D>(m, xh, xl, c, lam);
+        const uint32_t fl = first_locate<D>(m, xh, xl, c, lam, mc);
         ok = (fl == 0);
         r = ok ? (long long)c : (fl == kLost ? -2LL : -1LL);
     }
@@ -626,7 +643,7 @@ __global__ __launch_bounds__(256) void mesh_velocity_kernel(MeshDev m, MeshFrame
         long long base;
         float alpha;
         mesh_frame_at(f, t[p], base, alpha);
-        mesh_velocity<D>(m, f, c, lam, base, alpha, out);
+        mesh_velocity<D>(m, f, c, lam, base, alpha, out, mc);
     } else {
 #pragma unroll
         for (int a = 0; a < D; ++a) out[a] = __builtin_nanf("");
