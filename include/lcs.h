@@ -68,7 +68,10 @@ enum {
  *
  * dim          2 or 3.
  * n[a]         nodes along axis a (n[2] == 1 in 2D); n[a] >= 2, and
- *              n0*n1*n2 < 2^31.
+ *              n0*n1*n2 < 2^31; one frame of one array (a component in
+ *              LCS_LAYOUT_SOA, all components when interleaved) must be at
+ *              most 4 GiB (n0*n1*n2 * 4 B, resp. * 4*dim B or * 16 B), else
+ *              LCS_E_SHAPE.
  * origin[a],   node i of axis a sits at origin[a] + i*spacing[a].
  * spacing[a]   spacing[a] > 0.
  * periodic_mask  bit a set: axis a is periodic with period n[a]*spacing[a]

@@ -92,38 +92,11 @@ __device__ __forceinline__ void frame_at_uniform(const VelDev &v, double t, long
     base = (long long)f * v.frame_stride;
 }
 
-// Two x-adjacent nodes (i, i+1) with one dword-aligned 8-byte load at a
-// 32-bit element offset from a (wave-uniform) base.
-__device__ __forceinline__ float2 load_pair(const float *base, unsigned int elem)
-{
-    float2 v;
-    __builtin_memcpy(&v, reinterpret_cast<const char *>(base) + elem * 4u, sizeof(v));
-    return v;
-}
-
-// Interleaved frames: the components of a node are adjacent (S floats per
-// node: 3 (x, y, z), 4 (x, y, z, unused) or 2 in 2D).  A record is read with one
-// load at a 32-bit record offset from the frame base; in 2D the two nodes of a
-// corner pair (i, i+1) are one 16-byte load.
-template <int S>
-__device__ __forceinline__ void load_rec(const float *frame, unsigned int node, float *out)
-{
-    if constexpr (S == 4) {
-        const float4 q = *reinterpret_cast<const float4 *>(frame + (size_t)node * 4u);
-        out[0] = q.x; out[1] = q.y; out[2] = q.z;
-    } else {
-        float q[3];
-        __builtin_memcpy(q, reinterpret_cast<const char *>(frame) + (size_t)node * 12u, 12);
-        out[0] = q[0]; out[1] = q[1]; out[2] = q[2];
-    }
-}
-
-__device__ __forceinline__ float4 load_pair2(const float *frame, unsigned int node)
-{
-    float4 q;
-    __builtin_memcpy(&q, reinterpret_cast<const char *>(frame) + (size_t)node * 8u, sizeof(q));
-    return q;
-}
+// Frame layouts: structure of arrays (one array per component; the x pair
+// (i, i+1) of a cell row is one 8-byte load per component) or interleaved
+// records (2, 3 or 4 floats per node with the components together; one 12-byte
+// load per node in 3D, one 16-byte load per x pair in 2D).  Every load is a
+// 32-bit byte offset from a wave-uniform frame base.
 
 // Corner values of the cell a tracer sampled last, for both frames of the
 // pair, kept in registers: consecutive RK4 stage points mostly fall in the
@@ -137,82 +110,52 @@ __device__ __forceinline__ float4 load_pair2(const float *frame, unsigned int no
 template <int D>
 struct CellCache {
     static constexpr int R = (D == 2) ? 2 : 4;    // rows of 2 corners
-    unsigned int node = ~0u;  // lower-corner node of the cached cell (~0u: empty)
+    uint32_t node = ~0u;      // byte offset of the cached cell's lower corner (~0u: empty)
     long long base = -1;      // frame base of the cached pair
     float c[2][R][2][D];      // [frame f/f+1][row][lower/upper node][component]
 };
 
-// Gather the corner values of the cell (rows row[], x nodes lo0/hi0, the pair
-// starting at px) for the frames at base and base + frame_stride.
+// Bytes at a 32-bit offset from a (wave-uniform) frame base.
+template <typename T>
+__device__ __forceinline__ T load_at(const char *base, uint32_t off)
+{
+    T v;
+    __builtin_memcpy(&v, base + off, sizeof(T));
+    return v;
+}
+
+// Structure of arrays: one 8-byte pair load per (row, frame, component).
 template <int D>
-__device__ __forceinline__ void gather_cell(const VelDev &v, long long base, const unsigned int *row,
-                                            int lo0, int hi0, int px, bool wrap,
-                                            float (&c)[2][CellCache<D>::R][2][D])
+__device__ __forceinline__ void gather_cell_soa(const VelDev &v, long long base,
+                                                const uint32_t *rowb, uint32_t pxb, bool wrap,
+                                                float (&c)[2][CellCache<D>::R][2][D])
 {
     constexpr int R = CellCache<D>::R;
     const long long fs = v.frame_stride;
-    if (v.ilv) {
-        // interleaved layout: per (row, frame) the lower and upper node records
-        const long long S = v.ilv;
-        const float *__restrict__ A = v.ilv_u + base * S;
-        const float *__restrict__ B = A + fs * S;
-        if constexpr (D == 3) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned int e0 = row[r] + (unsigned int)lo0;
-                const unsigned int e1 = row[r] + (unsigned int)hi0;
-                if (S == 4) {
-                    load_rec<4>(A, e0, c[0][r][0]); load_rec<4>(A, e1, c[0][r][1]);
-                    load_rec<4>(B, e0, c[1][r][0]); load_rec<4>(B, e1, c[1][r][1]);
-                } else {
-                    load_rec<3>(A, e0, c[0][r][0]); load_rec<3>(A, e1, c[0][r][1]);
-                    load_rec<3>(B, e0, c[1][r][0]); load_rec<3>(B, e1, c[1][r][1]);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned int e = row[r] + (unsigned int)px;
-                float4 qa = load_pair2(A, e), qb = load_pair2(B, e);
-                if (wrap) {   // pair (n0-2, n0-1) -> (n0-1, 0)
-                    const float2 za = *reinterpret_cast<const float2 *>(A + (size_t)row[r] * 2u);
-                    const float2 zb = *reinterpret_cast<const float2 *>(B + (size_t)row[r] * 2u);
-                    qa = make_float4(qa.z, qa.w, za.x, za.y);
-                    qb = make_float4(qb.z, qb.w, zb.x, zb.y);
-                }
-                c[0][r][0][0] = qa.x; c[0][r][0][1] = qa.y; c[0][r][1][0] = qa.z; c[0][r][1][1] = qa.w;
-                c[1][r][0][0] = qb.x; c[1][r][0][1] = qb.y; c[1][r][1][0] = qb.z; c[1][r][1][1] = qb.w;
-            }
-        }
-        return;
-    }
-    // structure of arrays: one 8-byte pair load per (row, frame, component)
     float2 pa[D][R], pb[D][R];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        const float *__restrict__ A = v.u[k] + base;
-        const float *__restrict__ B = A + fs;
+        const char *__restrict__ A = reinterpret_cast<const char *>(v.u[k] + base);
+        const char *__restrict__ B = reinterpret_cast<const char *>(v.u[k] + base + fs);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            pa[k][r] = load_pair(A, row[r] + (unsigned int)px);
-            pb[k][r] = load_pair(B, row[r] + (unsigned int)px);
+            pa[k][r] = load_at<float2>(A, rowb[r] + pxb);
+            pb[k][r] = load_at<float2>(B, rowb[r] + pxb);
         }
     }
     if (wrap) {
         // cell (n0-1, 0): the loaded pair is (n0-2, n0-1); shift it and fetch node 0
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const float *__restrict__ A = v.u[k] + base;
-            const float *__restrict__ B = A + fs;
+            const char *__restrict__ A = reinterpret_cast<const char *>(v.u[k] + base);
+            const char *__restrict__ B = reinterpret_cast<const char *>(v.u[k] + base + fs);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                pa[k][r] = make_float2(pa[k][r].y, A[row[r]]);
-                pb[k][r] = make_float2(pb[k][r].y, B[row[r]]);
+                pa[k][r] = make_float2(pa[k][r].y, load_at<float>(A, rowb[r]));
+                pb[k][r] = make_float2(pb[k][r].y, load_at<float>(B, rowb[r]));
             }
         }
     }
-    // stored in the order of the interleaved fill above (row, frame, node,
-    // component), so that the two fills end in the same stores
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -226,12 +169,57 @@ __device__ __forceinline__ void gather_cell(const VelDev &v, long long base, con
     }
 }
 
+// Gather the corner values of the cell for the frames at element offset base
+// and base + frame_stride.  rowb[] are the byte offsets of the cell's rows
+// (lower x corner excluded), xb0/xb1 those of its lower and upper x nodes and
+// pxb that of the first node of the loaded x pair (n0-2 on a wrapped cell).
+template <int D, bool ILV>
+__device__ __forceinline__ void gather_cell(const VelDev &v, long long base, const uint32_t *rowb,
+                                            uint32_t xb0, uint32_t xb1, uint32_t pxb, bool wrap,
+                                            float (&c)[2][CellCache<D>::R][2][D])
+{
+    constexpr int R = CellCache<D>::R;
+    const long long fs = v.frame_stride;
+    if constexpr (ILV) {
+        // interleaved layout: per (row, frame) the lower and upper node records
+        const long long S = v.ilv;
+        const char *__restrict__ A = reinterpret_cast<const char *>(v.ilv_u + base * S);
+        const char *__restrict__ B = reinterpret_cast<const char *>(v.ilv_u + (base + fs) * S);
+        if constexpr (D == 3) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t e0 = rowb[r] + xb0, e1 = rowb[r] + xb1;
+                const float3 a0 = load_at<float3>(A, e0), a1 = load_at<float3>(A, e1);
+                const float3 b0 = load_at<float3>(B, e0), b1 = load_at<float3>(B, e1);
+                c[0][r][0][0] = a0.x; c[0][r][0][1] = a0.y; c[0][r][0][2] = a0.z;
+                c[0][r][1][0] = a1.x; c[0][r][1][1] = a1.y; c[0][r][1][2] = a1.z;
+                c[1][r][0][0] = b0.x; c[1][r][0][1] = b0.y; c[1][r][0][2] = b0.z;
+                c[1][r][1][0] = b1.x; c[1][r][1][1] = b1.y; c[1][r][1][2] = b1.z;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float4 qa = load_at<float4>(A, rowb[r] + pxb), qb = load_at<float4>(B, rowb[r] + pxb);
+                if (wrap) {   // pair (n0-2, n0-1) -> (n0-1, 0)
+                    const float2 za = load_at<float2>(A, rowb[r]), zb = load_at<float2>(B, rowb[r]);
+                    qa = make_float4(qa.z, qa.w, za.x, za.y);
+                    qb = make_float4(qb.z, qb.w, zb.x, zb.y);
+                }
+                c[0][r][0][0] = qa.x; c[0][r][0][1] = qa.y; c[0][r][1][0] = qa.z; c[0][r][1][1] = qa.w;
+                c[1][r][0][0] = qb.x; c[1][r][0][1] = qb.y; c[1][r][1][0] = qb.z; c[1][r][1][1] = qb.w;
+            }
+        }
+    } else {
+        gather_cell_soa<D>(v, base, rowb, pxb, wrap, c);
+    }
+}
+
 // u at the two-float point (ph + pl): multilinear in space within frames f and
 // f+1, then linear in time.  The corners of a cell come in x-adjacent pairs
 // (i, i+1); on a periodic x axis the pair of the last cell wraps to node 0.
 // The corner values are reused while the tracer stays in the cell and frame
 // pair of its previous evaluation (cc).
-template <int D>
+template <int D, bool ILV>
 __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const float *pl,
                                          long long base, float alpha, float *out,
                                          CellCache<D> &cc)
@@ -246,27 +234,32 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
     const float a1 = alpha, a0 = 1.0f - alpha;
     const int n0 = v.n[0];
     const bool wrap = (hi[0] != lo[0] + 1);          // periodic x, last cell
-    const int px = wrap ? n0 - 2 : lo[0];             // start of the x pair
     const float wx1 = xi[0], wx0 = 1.0f - xi[0];
     constexpr int R = CellCache<D>::R;
-    unsigned int row[R];
+    // byte offsets within a frame array (a node's offset is its index times
+    // sb[0]; hi is lo + 1 except where a periodic axis wraps to node 0)
+    const uint32_t xb0 = (uint32_t)lo[0] * v.sb[0];
+    const uint32_t xb1 = wrap ? 0u : xb0 + v.sb[0];
+    const uint32_t pxb = wrap ? (uint32_t)(n0 - 2) * v.sb[0] : xb0;
+    const uint32_t yb0 = (uint32_t)lo[1] * v.sb[1];
+    const uint32_t yb1 = (hi[1] == 0) ? 0u : yb0 + v.sb[1];
+    uint32_t rowb[R];
     float wr[R];
     if constexpr (D == 2) {
         const float wy1 = xi[1], wy0 = 1.0f - xi[1];
-        row[0] = n0 * lo[1]; row[1] = n0 * hi[1];
+        rowb[0] = yb0; rowb[1] = yb1;
         wr[0] = wy0; wr[1] = wy1;
     } else {
-        const unsigned int n01 = (unsigned int)(n0 * v.n[1]);
+        const uint32_t zb0 = (uint32_t)lo[2] * v.sb[2];
+        const uint32_t zb1 = (hi[2] == 0) ? 0u : zb0 + v.sb[2];
         const float wy1 = xi[1], wy0 = 1.0f - xi[1];
         const float wz1 = xi[2], wz0 = 1.0f - xi[2];
-        const unsigned int y0 = n0 * lo[1], y1 = n0 * hi[1];
-        const unsigned int z0 = n01 * lo[2], z1 = n01 * hi[2];
-        row[0] = y0 + z0; row[1] = y1 + z0; row[2] = y0 + z1; row[3] = y1 + z1;
+        rowb[0] = yb0 + zb0; rowb[1] = yb1 + zb0; rowb[2] = yb0 + zb1; rowb[3] = yb1 + zb1;
         wr[0] = wy0 * wz0; wr[1] = wy1 * wz0; wr[2] = wy0 * wz1; wr[3] = wy1 * wz1;
     }
-    const unsigned int key = row[0] + (unsigned int)lo[0];   // the cell's lower-corner node
+    const uint32_t key = rowb[0] + xb0;   // the cell's lower-corner offset
     if (!LCS_CELL_CACHE || cc.node != key || cc.base != base) {
-        gather_cell<D>(v, base, row, lo[0], hi[0], px, wrap, cc.c);
+        gather_cell<D, ILV>(v, base, rowb, xb0, xb1, pxb, wrap, cc.c);
         cc.node = key;
         cc.base = base;
     }
@@ -299,9 +292,9 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
 // or outside the closed domain (or a non-finite sampled velocity) rejects the
 // step, freezes the tracer and returns its flag.
-template <int D, bool UNIFORM_T = true>
-__device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
-                                 int n_begin, int n_end)
+template <int D, bool UNIFORM_T, bool ILV>
+__device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                   int n_begin, int n_end)
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
@@ -321,22 +314,22 @@ __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t
         }
         float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
 
-        velocity<D>(v, xh, xl, b1, al1, k1, cc);
+        velocity<D, ILV>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b2, al2, k2, cc);
+        velocity<D, ILV>(v, ph, pl, b2, al2, k2, cc);
         if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b2, al2, k3, cc);
+        velocity<D, ILV>(v, ph, pl, b2, al2, k3, cc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D>(v, ph, pl, b4, al4, k4, cc);
+        velocity<D, ILV>(v, ph, pl, b4, al4, k4, cc);
         if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 
         // (xh, xl) <- (xh, xl) + dt/6 (k1 + 2k2 + 2k3 + k4)
@@ -352,6 +345,16 @@ __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t
         for (int a = 0; a < D; ++a) { xh[a] = nh[a]; xl[a] = nl[a]; }
     }
     return fl;
+}
+
+// The frame layout is fixed for a launch: each layout gets its own copy of the
+// step loop (and of the cell cache's registers).
+template <int D, bool UNIFORM_T = true>
+__device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
+                                 int n_begin, int n_end)
+{
+    if (v.ilv) return advect_steps_l<D, UNIFORM_T, true>(v, xh, xl, t0, dt, n_begin, n_end);
+    return advect_steps_l<D, UNIFORM_T, false>(v, xh, xl, t0, dt, n_begin, n_end);
 }
 
 // UNIFORM_T: every lane of the wave integrates from the same t0 (grid,
@@ -456,9 +459,9 @@ constexpr double ab_den() { return S == 2 ? 2.0 : (S == 3 ? 12.0 : 24.0); }
 
 // Steps n_begin <= n < n_end; hist[j] = f_{n-1-j} on entry and is updated, so
 // an integration can be resumed from a saved (position, history) state.
-template <int D, int S>
-__device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float (*hist)[3],
-                                    double t0, double dt, int n_begin, int n_end)
+template <int D, int S, bool ILV>
+__device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, float (*hist)[3],
+                                      double t0, double dt, int n_begin, int n_end)
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
@@ -471,7 +474,7 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
         float al1;
         frame_at_uniform(v, t, b1, al1);
         float k1[3];
-        velocity<D>(v, xh, xl, b1, al1, k1, cc);
+        velocity<D, ILV>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         float nh[3], nl[3];
         if (n < S - 1) {
@@ -482,15 +485,15 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
             float k2[3], k3[3], k4[3], ph[3], pl[3];
             stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b2, al2, k2, cc);
+            velocity<D, ILV>(v, ph, pl, b2, al2, k2, cc);
             if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b2, al2, k3, cc);
+            velocity<D, ILV>(v, ph, pl, b2, al2, k3, cc);
             if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D>(v, ph, pl, b4, al4, k4, cc);
+            velocity<D, ILV>(v, ph, pl, b4, al4, k4, cc);
             if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -519,6 +522,14 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
         }
     }
     return fl;
+}
+
+template <int D, int S>
+__device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float (*hist)[3],
+                                    double t0, double dt, int n_begin, int n_end)
+{
+    if (v.ilv) return advect_steps_ab_l<D, S, true>(v, xh, xl, hist, t0, dt, n_begin, n_end);
+    return advect_steps_ab_l<D, S, false>(v, xh, xl, hist, t0, dt, n_begin, n_end);
 }
 
 template <int D, int S>

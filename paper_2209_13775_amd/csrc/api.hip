@@ -77,6 +77,12 @@ lcs_status check_velocity(const lcs_velocity_t *v)
         nodes *= v->n[a];
         if (nodes > kMaxNodes) return lcs::set_error(LCS_E_SHAPE, "velocity frame exceeds 2^31-1 nodes");
     }
+    // kernels address a frame array with 32-bit byte offsets
+    const long long rec = (v->layout == LCS_LAYOUT_SOA) ? 4 :
+                          (v->layout == LCS_LAYOUT_XYZW) ? 16 : 4LL * v->dim;
+    if (nodes * rec > (1LL << 32))
+        return lcs::set_error(LCS_E_SHAPE, "a velocity frame array exceeds 4 GiB (%lld nodes x %lld B)",
+                              nodes, rec);
     return LCS_OK;
 }
 
@@ -144,6 +150,10 @@ lcs::VelDev make_vel(const lcs_velocity_t *v)
         d.ilv = (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
         d.ilv_u = v->u[0];
     }
+    const uint32_t rec = (v->layout == LCS_LAYOUT_SOA) ? 4u : 4u * (uint32_t)(d.ilv);
+    d.sb[0] = rec;
+    d.sb[1] = rec * (uint32_t)v->n[0];
+    d.sb[2] = rec * (uint32_t)(v->n[0] * v->n[1]);
     for (int a = 0; a < 3; ++a) {
         d.u[a] = (a < v->dim && v->layout == LCS_LAYOUT_SOA) ? v->u[a] : nullptr;
         d.n[a] = (int)v->n[a];

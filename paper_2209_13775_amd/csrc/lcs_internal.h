@@ -19,6 +19,8 @@ struct VelDev {
     const float *ilv_u;       // interleaved frames (ilv = floats per node: 2, 3 or 4)
     int ilv;
     long long frame_stride;   // n0*n1*n2
+    uint32_t sb[3];           // bytes between nodes adjacent along each axis, within one
+                              // frame array (every offset in a frame fits 32 bits)
     int n[3];
     float nf[3];
     float oh[3], ol[3];       // origin as a two-float (hi + lo)
