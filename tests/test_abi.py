@@ -65,6 +65,7 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("bad_layout", lcs.LCS_E_ARG),
     ("xyzw_in_2d", lcs.LCS_E_ARG),
     ("misaligned_interleaved", lcs.LCS_E_ARG),
+    ("frame_over_4gib", lcs.LCS_E_SHAPE),
 ])
 def test_advect_validation(case, expect):
     v, s = _vel(), _seeds()
@@ -100,9 +101,21 @@ def test_advect_validation(case, expect):
     elif case == "misaligned_interleaved":
         v.layout = lcs.LCS_LAYOUT_XYZ
         v.u[0] = 0x1004                # 2D interleaved frames need 8-byte alignment
+    elif case == "frame_over_4gib":
+        v.layout = lcs.LCS_LAYOUT_XYZ  # 2^29 nodes x 8 B per interleaved 2D frame = 4 GiB
+        v.n[0], v.n[1] = 1 << 15, (1 << 14) + 1
     st = _advect(v, s, t0, T, dt, xf)
     assert st == expect, lcs.lcs_last_error()
     assert lcs.lcs_last_error() != ""
+
+
+def test_frame_size_limit_accepts_4gib():
+    """A frame array of exactly 4 GiB passes validation (32-bit byte offsets
+    reach every record); the call then fails on its time range instead."""
+    v, s = _vel(), _seeds()
+    v.n[0], v.n[1] = 1 << 15, 1 << 15        # 2^30 nodes x 4 B per component
+    st = _advect(v, s, 0.0, 2.5, 0.1)
+    assert st == lcs.LCS_E_TIME_RANGE, lcs.lcs_last_error()
 
 
 def test_other_entry_points_validate():
