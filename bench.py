@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched-window, random-Fourier and surrogate workloads")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
-    ap.add_argument("--layout", default="xyzw", choices=("soa", "xyz", "xyzw"),
+    ap.add_argument("--layout", default="tpair", choices=("soa", "xyz", "xyzw", "tpair"),
                     help="frame layout the kernels read; with an interleaved layout the main "
                          "step converts the structure-of-arrays frames inside its timed region")
     ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux,time_resolved",
@@ -83,6 +83,10 @@ def profiled_traffic_kernel(kernel):
             if h.hexdigest()[:16] == rec["source_sha1"]:
                 return rec["traffic_bytes_per_launch"]
     return None
+
+
+# frame layout of the 3D workloads (set from --layout in main)
+LAYOUT_3D = "tpair"
 
 
 def stage_frames(lcs, fs, layout, tensors=None):
@@ -197,7 +201,7 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     L = 2 * math.pi
     g = inputs.SeedGrid(3, (512, 512, 256), (0.0, 0.0, 0.0), (L / 512, L / 512, L / 256),
                         (True, True, True))
-    frames = stage_frames(lcs, fs, "xyzw", tensors=fs.u)
+    frames = stage_frames(lcs, fs, LAYOUT_3D, tensors=fs.u)
     ns = g.count
     from paper_2209_13775_amd import autotune
     tuned = autotune.tune(frames, g, 4.0, 4.0, 0.01, candidates=("sorted:100", "sorted:50",
@@ -237,7 +241,7 @@ def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
     adv = res["forward"][0] + res["backward"][0]
     cgf = res["forward"][1] + res["backward"][1]
     del ws
-    return {"workload": "random_fourier_256cubed_seeds512x512x256", "frame_layout": "xyzw",
+    return {"workload": "random_fourier_256cubed_seeds512x512x256", "frame_layout": LAYOUT_3D,
             "seeds": ns,
             "advect_strategy": choice, "autotune_ms": tuned["ms"],
             "tracer_steps": steps, "advect_ms_forward": res["forward"][0],
@@ -347,7 +351,7 @@ def bench_ab(torch, lcs, inputs, reps=2):
     fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
     L = 2 * math.pi
     g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = stage_frames(lcs, fs, "xyzw")
+    frames = stage_frames(lcs, fs, LAYOUT_3D)
     ns = g.count
     T = 8.0
     stream = torch.cuda.current_stream()
@@ -401,7 +405,7 @@ def bench_ab(torch, lcs, inputs, reps=2):
     lcs.lcs_sync_status()
     steps = ns * 400
     del ws, frames
-    return {"workload": "abc_128cubed_seeds256cubed_ab4", "frame_layout": "xyzw",
+    return {"workload": "abc_128cubed_seeds256cubed_ab4", "frame_layout": LAYOUT_3D,
             "reference": "rk4 dt=0.005",
             "runs": runs, "tracer_steps_per_s_ab4_dt0.02": steps / (ab_ms * 1e-3),
             "velocity_evaluations_per_step": {"rk4": 4, "ab4": 1},
@@ -422,7 +426,7 @@ def bench_aux(torch, lcs, inputs, reps=2):
     L = 2 * math.pi
     g = inputs.periodic_seeds(3, (128, 128, 128), (L, L, L))
     g2 = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = stage_frames(lcs, fs, "xyzw")
+    frames = stage_frames(lcs, fs, LAYOUT_3D)
     T, dt = 8.0, 0.02
     h = L / 128
     stream = torch.cuda.current_stream()
@@ -464,7 +468,7 @@ def bench_aux(torch, lcs, inputs, reps=2):
             e[::17].float(), 0.99).item()), "ftle_err_max": float(e.max().item())}
 
     ns = g.count
-    return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "frame_layout": "xyzw",
+    return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "frame_layout": LAYOUT_3D,
             "reference":
             "auxiliary points, delta = h/100", "seed_spacing_h": h,
             "grid_128cubed": dict(ms=ms_g1, tracers=ns, **err(s_g1)),
@@ -483,7 +487,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
     L = 2 * math.pi
     fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
     g = inputs.periodic_seeds(3, (256, 256, 256), (L, L, L))
-    frames = stage_frames(lcs, fs, "xyzw")
+    frames = stage_frames(lcs, fs, LAYOUT_3D)
     ns = g.count
     steps = [50 * k for k in range(1, 9)]
     xs = torch.empty((8, 3, ns), dtype=torch.float32, device="cuda")
@@ -517,7 +521,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
     torch.cuda.empty_cache()
     ft = inputs.sample_field(inputs.abc_velocity, 3, (129, 129, 129), (0.0,) * 3, (L / 128,) * 3,
                              (False,) * 3, 0.0, 0.5, 17).astype(np.float32)
-    frames = stage_frames(lcs, ft, "xyzw")
+    frames = stage_frames(lcs, ft, LAYOUT_3D)
     gt = inputs.linspace_seeds(3, (128, 128, 128), (0.0,) * 3, (L,) * 3)
     nt = gt.count
     x1 = torch.empty((1, 3, nt), dtype=torch.float32, device="cuda")
@@ -532,7 +536,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
                                                 ws, stream=stream))
     lcs.lcs_sync_status()
     early = int((te < 4.0 - 1e-12).sum().item())
-    return {"workload": "abc_128cubed_seeds256cubed_8_snapshots", "frame_layout": "xyzw",
+    return {"workload": "abc_128cubed_seeds256cubed_8_snapshots", "frame_layout": LAYOUT_3D,
             "snapshot_steps": steps, "ms_8_snapshots_and_8_ftle_fields": ms_snap,
             "ms_single_lcs_advect_tiles": ms_one,
             "truncated_box": {"workload": "abc_closed_box_129cubed_seeds128cubed_T4",
@@ -642,6 +646,8 @@ def main():
     nsteps = int(round(W["T"] / W["dt"]))
     frames_soa = lcs.DeviceFrames(fs, device=dev)
     layout = args.layout
+    global LAYOUT_3D
+    LAYOUT_3D = layout
     frames = frames_soa if layout == "soa" else lcs.lcs_frames_interleave(frames_soa, layout)
     from paper_2209_13775_amd import autotune
     if args.strategy:

@@ -169,18 +169,36 @@ __device__ __forceinline__ void gather_cell_soa(const VelDev &v, long long base,
     }
 }
 
+// Frame layouts as the kernels see them (a compile-time copy of the step loop
+// per layout).
+constexpr int kLaySoa = 0, kLayInterleaved = 1, kLayTPair = 2;
+
 // Gather the corner values of the cell for the frames at element offset base
 // and base + frame_stride.  rowb[] are the byte offsets of the cell's rows
 // (lower x corner excluded), xb0/xb1 those of its lower and upper x nodes and
 // pxb that of the first node of the loaded x pair (n0-2 on a wrapped cell).
-template <int D, bool ILV>
+template <int D, int L>
 __device__ __forceinline__ void gather_cell(const VelDev &v, long long base, const uint32_t *rowb,
                                             uint32_t xb0, uint32_t xb1, uint32_t pxb, bool wrap,
                                             float (&c)[2][CellCache<D>::R][2][D])
 {
     constexpr int R = CellCache<D>::R;
     const long long fs = v.frame_stride;
-    if constexpr (ILV) {
+    if constexpr (L == kLayTPair) {
+        // time-paired records: per row the lower and upper x node, both frames,
+        // in 48 contiguous bytes (a wrapped cell reads the row's extra node)
+        const char *__restrict__ P = reinterpret_cast<const char *>(v.ilv_u + base * 6);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = rowb[r] + xb0;
+            const float4 q0 = load_at<float4>(P, e), q1 = load_at<float4>(P, e + 16u),
+                         q2 = load_at<float4>(P, e + 32u);
+            c[0][r][0][0] = q0.x; c[0][r][0][1] = q0.y; c[0][r][0][2] = q0.z;
+            c[0][r][1][0] = q1.z; c[0][r][1][1] = q1.w; c[0][r][1][2] = q2.x;
+            c[1][r][0][0] = q0.w; c[1][r][0][1] = q1.x; c[1][r][0][2] = q1.y;
+            c[1][r][1][0] = q2.y; c[1][r][1][1] = q2.z; c[1][r][1][2] = q2.w;
+        }
+    } else if constexpr (L == kLayInterleaved) {
         // interleaved layout: per (row, frame) the lower and upper node records
         const long long S = v.ilv;
         const char *__restrict__ A = reinterpret_cast<const char *>(v.ilv_u + base * S);
@@ -219,7 +237,7 @@ __device__ __forceinline__ void gather_cell(const VelDev &v, long long base, con
 // (i, i+1); on a periodic x axis the pair of the last cell wraps to node 0.
 // The corner values are reused while the tracer stays in the cell and frame
 // pair of its previous evaluation (cc).
-template <int D, bool ILV>
+template <int D, int L>
 __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const float *pl,
                                          long long base, float alpha, float *out,
                                          CellCache<D> &cc)
@@ -259,7 +277,7 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
     }
     const uint32_t key = rowb[0] + xb0;   // the cell's lower-corner offset
     if (!LCS_CELL_CACHE || cc.node != key || cc.base != base) {
-        gather_cell<D, ILV>(v, base, rowb, xb0, xb1, pxb, wrap, cc.c);
+        gather_cell<D, L>(v, base, rowb, xb0, xb1, pxb, wrap, cc.c);
         cc.node = key;
         cc.base = base;
     }
@@ -292,7 +310,7 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
 // or outside the closed domain (or a non-finite sampled velocity) rejects the
 // step, freezes the tracer and returns its flag.
-template <int D, bool UNIFORM_T, bool ILV>
+template <int D, bool UNIFORM_T, int L>
 __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double t0, double dt,
                                    int n_begin, int n_end)
 {
@@ -314,22 +332,22 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
         }
         float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
 
-        velocity<D, ILV>(v, xh, xl, b1, al1, k1, cc);
+        velocity<D, L>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D, ILV>(v, ph, pl, b2, al2, k2, cc);
+        velocity<D, L>(v, ph, pl, b2, al2, k2, cc);
         if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D, ILV>(v, ph, pl, b2, al2, k3, cc);
+        velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
         stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
         if ((fl = check_point<D>(v, ph))) break;
 
-        velocity<D, ILV>(v, ph, pl, b4, al4, k4, cc);
+        velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
         if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 
         // (xh, xl) <- (xh, xl) + dt/6 (k1 + 2k2 + 2k3 + k4)
@@ -353,8 +371,10 @@ template <int D, bool UNIFORM_T = true>
 __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
                                  int n_begin, int n_end)
 {
-    if (v.ilv) return advect_steps_l<D, UNIFORM_T, true>(v, xh, xl, t0, dt, n_begin, n_end);
-    return advect_steps_l<D, UNIFORM_T, false>(v, xh, xl, t0, dt, n_begin, n_end);
+    if constexpr (D == 3)
+        if (v.ilv == 6) return advect_steps_l<D, UNIFORM_T, kLayTPair>(v, xh, xl, t0, dt, n_begin, n_end);
+    if (v.ilv) return advect_steps_l<D, UNIFORM_T, kLayInterleaved>(v, xh, xl, t0, dt, n_begin, n_end);
+    return advect_steps_l<D, UNIFORM_T, kLaySoa>(v, xh, xl, t0, dt, n_begin, n_end);
 }
 
 // UNIFORM_T: every lane of the wave integrates from the same t0 (grid,
@@ -459,7 +479,7 @@ constexpr double ab_den() { return S == 2 ? 2.0 : (S == 3 ? 12.0 : 24.0); }
 
 // Steps n_begin <= n < n_end; hist[j] = f_{n-1-j} on entry and is updated, so
 // an integration can be resumed from a saved (position, history) state.
-template <int D, int S, bool ILV>
+template <int D, int S, int L>
 __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, float (*hist)[3],
                                       double t0, double dt, int n_begin, int n_end)
 {
@@ -474,7 +494,7 @@ __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, flo
         float al1;
         frame_at_uniform(v, t, b1, al1);
         float k1[3];
-        velocity<D, ILV>(v, xh, xl, b1, al1, k1, cc);
+        velocity<D, L>(v, xh, xl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         float nh[3], nl[3];
         if (n < S - 1) {
@@ -485,15 +505,15 @@ __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, flo
             float k2[3], k3[3], k4[3], ph[3], pl[3];
             stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D, ILV>(v, ph, pl, b2, al2, k2, cc);
+            velocity<D, L>(v, ph, pl, b2, al2, k2, cc);
             if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D, ILV>(v, ph, pl, b2, al2, k3, cc);
+            velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
             if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
             stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
             if ((fl = check_point<D>(v, ph))) break;
-            velocity<D, ILV>(v, ph, pl, b4, al4, k4, cc);
+            velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
             if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -528,8 +548,10 @@ template <int D, int S>
 __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float (*hist)[3],
                                     double t0, double dt, int n_begin, int n_end)
 {
-    if (v.ilv) return advect_steps_ab_l<D, S, true>(v, xh, xl, hist, t0, dt, n_begin, n_end);
-    return advect_steps_ab_l<D, S, false>(v, xh, xl, hist, t0, dt, n_begin, n_end);
+    if constexpr (D == 3)
+        if (v.ilv == 6) return advect_steps_ab_l<D, S, kLayTPair>(v, xh, xl, hist, t0, dt, n_begin, n_end);
+    if (v.ilv) return advect_steps_ab_l<D, S, kLayInterleaved>(v, xh, xl, hist, t0, dt, n_begin, n_end);
+    return advect_steps_ab_l<D, S, kLaySoa>(v, xh, xl, hist, t0, dt, n_begin, n_end);
 }
 
 template <int D, int S>
@@ -678,6 +700,30 @@ __global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const f
     o[1] = u1[off + i];
     if (dim == 3) o[2] = u2[off + i];
     if (S == 4) o[3] = 0.0f;
+}
+
+// Time-paired records: one thread per record of pair p (frames f_first + p and
+// f_first + p + 1) on the grid with n0 + 1 nodes per row, the last repeating
+// node 0 of the row.
+__global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *u0, const float *u1,
+                                                               const float *u2, int n0, int n1,
+                                                               int n2, long long f_first,
+                                                               long long n_rec, float *out)
+{
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rec) return;
+    const long long per_pair = (long long)(n0 + 1) * n1 * n2;
+    const long long p = r / per_pair;
+    const long long q = r - p * per_pair;
+    const long long row = q / (n0 + 1);            // j + n1*k
+    const int i = (int)(q - row * (n0 + 1));
+    const long long nodes = (long long)n0 * n1 * n2;
+    const long long node = row * n0 + (i == n0 ? 0 : i);
+    const long long a = (f_first + p) * nodes + node, b = a + nodes;
+    float2 *o = reinterpret_cast<float2 *>(out + r * 6);
+    o[0] = make_float2(u0[a], u1[a]);
+    o[1] = make_float2(u2[a], u0[b]);
+    o[2] = make_float2(u1[b], u2[b]);
 }
 
 __global__ void reset_counter_kernel(int *counter) { *counter = 0; }
@@ -1162,6 +1208,15 @@ hipError_t launch_interleave(int dim, int S, const float *const *u, long long no
     const long long n = nodes * f_count;
     hipLaunchKernelGGL(interleave_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dim, S,
                        u[0], u[1], dim == 3 ? u[2] : u[1], n, f_first * nodes, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_count, int f_first,
+                                  float *out, hipStream_t s)
+{
+    const long long n_rec = (long long)(f_count - 1) * (n[0] + 1) * n[1] * n[2];
+    hipLaunchKernelGGL(interleave_tpair_kernel, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0,
+                       s, u[0], u[1], u[2], n[0], n[1], n[2], (long long)f_first, n_rec, out);
     return hipGetLastError();
 }
 

@@ -51,10 +51,12 @@ lcs_status check_velocity(const lcs_velocity_t *v)
 {
     if (!v) return lcs::set_error(LCS_E_ARG, "velocity descriptor is NULL");
     if (v->dim != 2 && v->dim != 3) return lcs::set_error(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
-    if (v->layout > LCS_LAYOUT_XYZW || (v->layout == LCS_LAYOUT_XYZW && v->dim != 3))
+    if (v->layout > LCS_LAYOUT_TPAIR ||
+        ((v->layout == LCS_LAYOUT_XYZW || v->layout == LCS_LAYOUT_TPAIR) && v->dim != 3))
         return lcs::set_error(LCS_E_ARG, "velocity layout %u is not valid for %dD", v->layout, v->dim);
     if (v->layout != LCS_LAYOUT_SOA) {
-        const uintptr_t align = (v->layout == LCS_LAYOUT_XYZW) ? 16u : (v->dim == 2 ? 8u : 4u);
+        const uintptr_t align = (v->layout == LCS_LAYOUT_XYZW || v->layout == LCS_LAYOUT_TPAIR)
+                                    ? 16u : (v->dim == 2 ? 8u : 4u);
         if (!v->u[0]) return lcs::set_error(LCS_E_ARG, "interleaved frames pointer u[0] is NULL");
         if (reinterpret_cast<uintptr_t>(v->u[0]) % align)
             return lcs::set_error(LCS_E_ARG, "interleaved frames must be %d-byte aligned", (int)align);
@@ -77,12 +79,15 @@ lcs_status check_velocity(const lcs_velocity_t *v)
         nodes *= v->n[a];
         if (nodes > kMaxNodes) return lcs::set_error(LCS_E_SHAPE, "velocity frame exceeds 2^31-1 nodes");
     }
-    // kernels address a frame array with 32-bit byte offsets
+    // kernels address a frame array (a frame-pair block for TPAIR) with 32-bit
+    // byte offsets
     const long long rec = (v->layout == LCS_LAYOUT_SOA) ? 4 :
-                          (v->layout == LCS_LAYOUT_XYZW) ? 16 : 4LL * v->dim;
-    if (nodes * rec > (1LL << 32))
-        return lcs::set_error(LCS_E_SHAPE, "a velocity frame array exceeds 4 GiB (%lld nodes x %lld B)",
-                              nodes, rec);
+                          (v->layout == LCS_LAYOUT_XYZW) ? 16 :
+                          (v->layout == LCS_LAYOUT_TPAIR) ? 24 : 4LL * v->dim;
+    const long long recs = (v->layout == LCS_LAYOUT_TPAIR) ? nodes / v->n[0] * (v->n[0] + 1) : nodes;
+    if (recs * rec > (1LL << 32))
+        return lcs::set_error(LCS_E_SHAPE, "a velocity frame array exceeds 4 GiB (%lld records x %lld B)",
+                              recs, rec);
     return LCS_OK;
 }
 
@@ -145,15 +150,18 @@ lcs::VelDev make_vel(const lcs_velocity_t *v)
 {
     lcs::VelDev d;
     memset(&d, 0, sizeof(d));
-    d.frame_stride = v->n[0] * v->n[1] * v->n[2];
+    // TPAIR: a "frame" is a frame-pair block of (n0+1)*n1*n2 records of 6 floats
+    const bool tpair = (v->layout == LCS_LAYOUT_TPAIR);
+    const long long n0r = tpair ? v->n[0] + 1 : v->n[0];
+    d.frame_stride = n0r * v->n[1] * v->n[2];
     if (v->layout != LCS_LAYOUT_SOA) {
-        d.ilv = (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
+        d.ilv = tpair ? 6 : (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
         d.ilv_u = v->u[0];
     }
     const uint32_t rec = (v->layout == LCS_LAYOUT_SOA) ? 4u : 4u * (uint32_t)(d.ilv);
     d.sb[0] = rec;
-    d.sb[1] = rec * (uint32_t)v->n[0];
-    d.sb[2] = rec * (uint32_t)(v->n[0] * v->n[1]);
+    d.sb[1] = rec * (uint32_t)n0r;
+    d.sb[2] = rec * (uint32_t)(n0r * v->n[1]);
     for (int a = 0; a < 3; ++a) {
         d.u[a] = (a < v->dim && v->layout == LCS_LAYOUT_SOA) ? v->u[a] : nullptr;
         d.n[a] = (int)v->n[a];
@@ -312,19 +320,32 @@ lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int
     lcs_status st;
     if ((st = check_velocity(soa)) != LCS_OK) return st;
     if (soa->layout != LCS_LAYOUT_SOA) return lcs::set_error(LCS_E_ARG, "source frames must be LCS_LAYOUT_SOA");
-    if (layout != LCS_LAYOUT_XYZ && !(layout == LCS_LAYOUT_XYZW && soa->dim == 3))
-        return lcs::set_error(LCS_E_ARG, "target layout must be LCS_LAYOUT_XYZ (or XYZW in 3D)");
+    if (layout != LCS_LAYOUT_XYZ &&
+        !((layout == LCS_LAYOUT_XYZW || layout == LCS_LAYOUT_TPAIR) && soa->dim == 3))
+        return lcs::set_error(LCS_E_ARG, "target layout must be LCS_LAYOUT_XYZ (or XYZW / TPAIR in 3D)");
     if (!out || !out_desc) return lcs::set_error(LCS_E_ARG, "out and out_desc must not be NULL");
     if (f_first < 0 || f_count < 2 || (long long)f_first + f_count > soa->n_frames)
         return lcs::set_error(LCS_E_SHAPE, "frame span [%d, %d) outside [0, %d) or shorter than 2",
                               f_first, f_first + f_count, soa->n_frames);
     const int S = (layout == LCS_LAYOUT_XYZW) ? 4 : soa->dim;
-    const uintptr_t align = (S == 4) ? 16u : (soa->dim == 2 ? 8u : 4u);
+    const uintptr_t align = (layout == LCS_LAYOUT_XYZ) ? (soa->dim == 2 ? 8u : 4u) : 16u;
     if (reinterpret_cast<uintptr_t>(out) % align)
         return lcs::set_error(LCS_E_ARG, "out must be %d-byte aligned", (int)align);
+    lcs_velocity_t desc = *soa;
+    desc.layout = layout;
+    desc.n_frames = f_count;
+    desc.u[0] = out;
+    desc.u[1] = desc.u[2] = nullptr;
+    if ((st = check_velocity(&desc)) != LCS_OK) return st;   // size limits of the target layout
     const long long nodes = soa->n[0] * soa->n[1] * soa->n[2];
-    hipError_t e = lcs::launch_interleave(soa->dim, S, soa->u, nodes, f_count, f_first, out,
-                                          (hipStream_t)stream);
+    hipError_t e;
+    if (layout == LCS_LAYOUT_TPAIR) {
+        const int n[3] = {(int)soa->n[0], (int)soa->n[1], (int)soa->n[2]};
+        e = lcs::launch_interleave_tpair(soa->u, n, f_count, f_first, out, (hipStream_t)stream);
+    } else {
+        e = lcs::launch_interleave(soa->dim, S, soa->u, nodes, f_count, f_first, out,
+                                   (hipStream_t)stream);
+    }
     if (e != hipSuccess) return lcs::hip_error(e, "interleave launch");
     *out_desc = *soa;
     out_desc->layout = layout;
@@ -334,6 +355,19 @@ lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int
     out_desc->u[1] = nullptr;
     out_desc->u[2] = nullptr;
     return lcs::clear_error();
+}
+
+int64_t lcs_frames_interleave_floats(const lcs_velocity_t *soa, uint32_t layout, int32_t f_count)
+{
+    if (!soa || (soa->dim != 2 && soa->dim != 3) || f_count < 2) return -1;
+    const long long nodes = soa->n[0] * soa->n[1] * soa->n[2];
+    switch (layout) {
+    case LCS_LAYOUT_XYZ: return (int64_t)f_count * nodes * soa->dim;
+    case LCS_LAYOUT_XYZW: return soa->dim == 3 ? (int64_t)f_count * nodes * 4 : -1;
+    case LCS_LAYOUT_TPAIR:
+        return soa->dim == 3 ? (int64_t)(f_count - 1) * (soa->n[0] + 1) * soa->n[1] * soa->n[2] * 6 : -1;
+    default: return -1;
+    }
 }
 
 lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,

@@ -127,6 +127,8 @@ def _load(path: str = LIB_PATH):
     L.lcs_ftle_early_workspace_bytes.argtypes = [P]
     L.lcs_check_tile_count.restype = C.c_int64
     L.lcs_check_tile_count.argtypes = [P]
+    L.lcs_frames_interleave_floats.restype = C.c_int64
+    L.lcs_frames_interleave_floats.argtypes = [P, C.c_uint32, I32]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
     return L
 
@@ -238,15 +240,18 @@ class DeviceFrames:
     @classmethod
     def interleaved(cls, fs, layout: str = "xyz", device="cuda", stream=None) -> "DeviceFrames":
         """Frames of the FrameSet fs staged on the device in an interleaved layout
-        ("xyz": dim floats per node, "xyzw": 4 in 3D) by lcs_frames_interleave."""
+        ("xyz": dim floats per node, "xyzw": 4 in 3D, "tpair": time-paired
+        records in 3D) by lcs_frames_interleave."""
         return lcs_frames_interleave(cls(fs, device=device), layout, stream=stream)
 
 
-LCS_LAYOUT_SOA, LCS_LAYOUT_XYZ, LCS_LAYOUT_XYZW = 0, 1, 2
+LCS_LAYOUT_SOA, LCS_LAYOUT_XYZ, LCS_LAYOUT_XYZW, LCS_LAYOUT_TPAIR = 0, 1, 2, 3
+_LAYOUTS = {"xyz": LCS_LAYOUT_XYZ, "xyzw": LCS_LAYOUT_XYZW, "tpair": LCS_LAYOUT_TPAIR}
 
 
 class _InterleavedFrames(DeviceFrames):
-    """Frames in an interleaved layout: one tensor (F, N, S) and its descriptor."""
+    """Frames in an interleaved layout: one tensor ((F, N, S), or (F-1, N', 6)
+    for time-paired records) and its descriptor."""
 
     def __init__(self, fs, tensor, desc):     # noqa: D401 (no SoA construction)
         self.fs = fs
@@ -258,14 +263,16 @@ def lcs_frames_interleave(frames: DeviceFrames, layout: str = "xyz", f_first: in
                           f_count: Optional[int] = None, out=None, stream=None) -> DeviceFrames:
     """Copy (a span of) structure-of-arrays frames into the interleaved layout."""
     torch = _torch()
-    lay = {"xyz": LCS_LAYOUT_XYZ, "xyzw": LCS_LAYOUT_XYZW}[layout]
+    lay = _LAYOUTS[layout]
     d = frames.desc
     F = int(d.n_frames) if f_count is None else int(f_count)
-    N = int(d.n[0] * d.n[1] * d.n[2])
-    S = 4 if lay == LCS_LAYOUT_XYZW else int(d.dim)
+    if lay == LCS_LAYOUT_TPAIR:
+        shape = (F - 1, int((d.n[0] + 1) * d.n[1] * d.n[2]), 6)
+    else:
+        shape = (F, int(d.n[0] * d.n[1] * d.n[2]), 4 if lay == LCS_LAYOUT_XYZW else int(d.dim))
     if out is None:
-        out = torch.empty((F, N, S), dtype=torch.float32, device=frames.u[0].device)
-    _need(out, torch.float32, (F, N, S), "out")
+        out = torch.empty(shape, dtype=torch.float32, device=frames.u[0].device)
+    _need(out, torch.float32, shape, "out")
     nd = lcs_velocity_t()
     _check(_lib.lcs_frames_interleave(frames.ref, lay, int(f_first), F, _ptr(out), C.byref(nd),
                                       _stream_handle(stream)))

@@ -66,6 +66,8 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("xyzw_in_2d", lcs.LCS_E_ARG),
     ("misaligned_interleaved", lcs.LCS_E_ARG),
     ("frame_over_4gib", lcs.LCS_E_SHAPE),
+    ("tpair_in_2d", lcs.LCS_E_ARG),
+    ("misaligned_tpair", lcs.LCS_E_ARG),
 ])
 def test_advect_validation(case, expect):
     v, s = _vel(), _seeds()
@@ -101,6 +103,13 @@ def test_advect_validation(case, expect):
     elif case == "misaligned_interleaved":
         v.layout = lcs.LCS_LAYOUT_XYZ
         v.u[0] = 0x1004                # 2D interleaved frames need 8-byte alignment
+    elif case == "tpair_in_2d":
+        v.layout = lcs.LCS_LAYOUT_TPAIR
+    elif case == "misaligned_tpair":
+        v.dim, v.n[2] = 3, 4
+        v.layout = lcs.LCS_LAYOUT_TPAIR
+        v.u[0] = 0x1008                # time-paired records need 16-byte alignment
+        s.dim, s.n[2], s.spacing[2] = 3, 1, 0.2
     elif case == "frame_over_4gib":
         v.layout = lcs.LCS_LAYOUT_XYZ  # 2^29 nodes x 8 B per interleaved 2D frame = 4 GiB
         v.n[0], v.n[1] = 1 << 15, (1 << 14) + 1
@@ -192,12 +201,26 @@ def test_mesh_entry_points_validate():
     L.lcs_mesh_destroy(None)
 
 
+def test_frames_interleave_floats():
+    v = _vel(dim=3, n=(5, 4, 3), frames=6)
+    L = lcs.lib()
+    assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_XYZ, 4) == 4 * 60 * 3
+    assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_XYZW, 4) == 4 * 60 * 4
+    assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 4) == 3 * 6 * 4 * 3 * 6
+    assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 1) == -1
+    assert L.lcs_frames_interleave_floats(C.byref(v), 9, 4) == -1
+    v2 = _vel()
+    assert L.lcs_frames_interleave_floats(C.byref(v2), lcs.LCS_LAYOUT_TPAIR, 3) == -1
+
+
 def test_frames_interleave_validates():
     L = lcs.lib()
     v = _vel()
     out_desc = lcs.lcs_velocity_t()
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZW, 0, 2, 0x1000, C.byref(out_desc),
                                    None) == lcs.LCS_E_ARG          # XYZW is 3D only
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 0, 2, 0x1000, C.byref(out_desc),
+                                   None) == lcs.LCS_E_ARG          # TPAIR is 3D only
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 1, 0x1000, C.byref(out_desc),
                                    None) == lcs.LCS_E_SHAPE        # fewer than 2 frames
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 1, 9, 0x1000, C.byref(out_desc),

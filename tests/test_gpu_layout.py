@@ -1,4 +1,5 @@
-"""GPU tests of the interleaved frame layouts (LCS_LAYOUT_XYZ, LCS_LAYOUT_XYZW):
+"""GPU tests of the interleaved frame layouts (LCS_LAYOUT_XYZ, LCS_LAYOUT_XYZW,
+LCS_LAYOUT_TPAIR):
 lcs_frames_interleave copies values exactly, and the advection entry points
 reading interleaved frames meet the same oracle parity bars as with
 structure-of-arrays frames (positions 1e-5 L mean and p99, FTLE 1e-3, flags
@@ -75,6 +76,29 @@ def test_interleave_copies_exactly(lcs, torch, dim, layout):
     assert il.desc.layout == (lcs.LCS_LAYOUT_XYZW if S == 4 else lcs.LCS_LAYOUT_XYZ)
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_tpair_records_exact(lcs, torch, periodic):
+    """Time-paired records: frames p and p+1 of each node side by side, one
+    extra node per x row repeating node 0."""
+    fs = inputs.random_frames(3, (9, 7, 5), 6, seed=4,
+                              periodic=(True, True, True) if periodic else None).astype(np.float32)
+    soa = lcs.DeviceFrames(fs)
+    il = lcs.lcs_frames_interleave(soa, "tpair", f_first=1, f_count=4)
+    lcs.lcs_sync_status()
+    got = _np(il.u[0]).reshape(3, 5, 7, 10, 6)
+    u = [np.asarray(c)[1:5] for c in fs.u]          # (4, 5, 7, 9) per component
+    for p in range(3):
+        for c in range(3):
+            np.testing.assert_array_equal(got[p, :, :, :9, c], u[c][p])
+            np.testing.assert_array_equal(got[p, :, :, :9, 3 + c], u[c][p + 1])
+            np.testing.assert_array_equal(got[p, :, :, 9, c], u[c][p][:, :, 0])
+            np.testing.assert_array_equal(got[p, :, :, 9, 3 + c], u[c][p + 1][:, :, 0])
+    assert il.desc.layout == lcs.LCS_LAYOUT_TPAIR and il.desc.n_frames == 4
+    assert il.desc.t_first == fs.t_first + fs.dt_frame
+    want = lcs.lib().lcs_frames_interleave_floats(soa.ref, lcs.LCS_LAYOUT_TPAIR, 4)
+    assert want == il.u[0].numel()
+
+
 def test_double_gyre_interleaved(orc, lcs):
     fs = inputs.double_gyre_frames()
     g = inputs.linspace_seeds(2, (256, 128), (0.0, 0.0), (2.0, 1.0))
@@ -94,7 +118,7 @@ def test_periodic_2d_interleaved_wrap(orc, lcs):
                  "taylor-green xy")
 
 
-@pytest.mark.parametrize("layout", ["xyz", "xyzw"])
+@pytest.mark.parametrize("layout", ["xyz", "xyzw", "tpair"])
 def test_abc_small_interleaved(orc, lcs, layout):
     fs = inputs.abc_frames(n=32, n_frames=9, dt_frame=0.5)
     L = 2 * math.pi
@@ -105,14 +129,15 @@ def test_abc_small_interleaved(orc, lcs, layout):
                  f"abc {layout}")
 
 
-def test_exits_and_nan_interleaved(orc, lcs):
+@pytest.mark.parametrize("layout3", ["xyzw", "tpair"])
+def test_exits_and_nan_interleaved(orc, lcs, layout3):
     c = np.array([0.37, -0.21, 0.13])
     fs = inputs.uniform_frames(c, dim=3, n=9, lo=0.0, hi=1.0)
     g = inputs.linspace_seeds(3, (20, 18, 16), (0.013, 0.011, 0.017), (0.987, 0.989, 0.983))
-    frames = lcs.DeviceFrames.interleaved(fs, "xyzw")
+    frames = lcs.DeviceFrames.interleaved(fs, layout3)
     ref = _orc(orc, fs, g, 0.0, 3.0, 0.05)
     assert (ref["flags"] == 1).sum() > 500
-    compare_full(orc, fs, g, _gpu(lcs, frames, g, 0.0, 3.0, 0.05), ref, "uniform xyzw")
+    compare_full(orc, fs, g, _gpu(lcs, frames, g, 0.0, 3.0, 0.05), ref, f"uniform {layout3}")
     fs2 = inputs.double_gyre_frames(nx=51, ny=26, n_frames=11)
     fs2.u[1][3, 12, 20] = np.nan
     g2 = inputs.linspace_seeds(2, (64, 32), (0.02, 0.02), (1.98, 0.98))
@@ -122,7 +147,7 @@ def test_exits_and_nan_interleaved(orc, lcs):
     compare_full(orc, fs2, g2, _gpu(lcs, frames2, g2, 0.0, 8.0, 0.05), ref2, "NaN xy")
 
 
-@pytest.mark.parametrize("layout", ["xyz", "xyzw"])
+@pytest.mark.parametrize("layout", ["xyz", "xyzw", "tpair"])
 def test_abc_full_size_interleaved_sampled(orc, lcs, torch, layout):
     """The benchmark launch (ABC 128^3, 256^3 seeds, T = 8, re-bundled segments
     of 50) on interleaved frames, checked at sampled seeds; the single-launch
@@ -176,7 +201,7 @@ def test_layouts_give_identical_bits(lcs, torch):
     L = 2 * math.pi
     g = inputs.periodic_seeds(3, (48, 40, 36), (L, L, L))
     outs = []
-    for layout in ("soa", "xyz", "xyzw"):
+    for layout in ("soa", "xyz", "xyzw", "tpair"):
         fr = lcs.DeviceFrames(fs) if layout == "soa" else lcs.DeviceFrames.interleaved(fs, layout)
         a = lcs.lcs_advect(fr, g, 0.5, 3.0, 0.02)
         b = lcs.lcs_advect_sorted(fr, g, 0.5, 3.0, 0.02, 20)
@@ -185,7 +210,7 @@ def test_layouts_give_identical_bits(lcs, torch):
         for u, v in zip(a, b):
             assert torch.equal(u, v), layout
         outs.append((a[0], c[0]))
-    for k in (1, 2):
+    for k in (1, 2, 3):
         assert torch.equal(outs[0][0], outs[k][0]) and torch.equal(outs[0][1], outs[k][1])
     fs2 = inputs.double_gyre_frames(nx=51, ny=26, n_frames=11)
     g2 = inputs.linspace_seeds(2, (97, 45), (0.0, 0.0), (2.0, 1.0))
