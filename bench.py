@@ -655,7 +655,7 @@ def main():
     else:
         print("bench: autotuning the seed ordering", file=sys.stderr, flush=True)
         tuned = autotune.tune(frames, g, W["t0"], W["T"], W["dt"],
-                              candidates=("tiles", "sorted:100", "sorted:50"))
+                              candidates=("tiles", "sorted:100"))
     choice = tuned["choice"]
     ws = None
     if choice != "tiles":
