@@ -309,15 +309,17 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
 // RK4 from t0 with step dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
 // or outside the closed domain (or a non-finite sampled velocity) rejects the
-// step, freezes the tracer and returns its flag.
+// step, freezes the tracer and returns its flag.  n_stop (if given) receives
+// the index of the rejected step, or n_end: the steps before it were accepted.
 template <int D, bool UNIFORM_T, int L>
 __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double t0, double dt,
-                                   int n_begin, int n_end)
+                                   int n_begin, int n_end, int *n_stop)
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
     CellCache<D> cc;
-    for (int n = n_begin; n < n_end; ++n) {
+    int n = n_begin;
+    for (; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1, b2, b4;
         float al1, al2, al4;
@@ -362,6 +364,7 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
 #pragma unroll
         for (int a = 0; a < D; ++a) { xh[a] = nh[a]; xl[a] = nl[a]; }
     }
+    if (n_stop) *n_stop = n;
     return fl;
 }
 
@@ -369,12 +372,14 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
 // step loop (and of the cell cache's registers).
 template <int D, bool UNIFORM_T = true>
 __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
-                                 int n_begin, int n_end)
+                                 int n_begin, int n_end, int *n_stop = nullptr)
 {
     if constexpr (D == 3)
-        if (v.ilv == 6) return advect_steps_l<D, UNIFORM_T, kLayTPair>(v, xh, xl, t0, dt, n_begin, n_end);
-    if (v.ilv) return advect_steps_l<D, UNIFORM_T, kLayInterleaved>(v, xh, xl, t0, dt, n_begin, n_end);
-    return advect_steps_l<D, UNIFORM_T, kLaySoa>(v, xh, xl, t0, dt, n_begin, n_end);
+        if (v.ilv == 6)
+            return advect_steps_l<D, UNIFORM_T, kLayTPair>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
+    if (v.ilv)
+        return advect_steps_l<D, UNIFORM_T, kLayInterleaved>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
+    return advect_steps_l<D, UNIFORM_T, kLaySoa>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
 }
 
 // UNIFORM_T: every lane of the wave integrates from the same t0 (grid,
@@ -633,20 +638,21 @@ __global__ LCS_ADVECT_BOUNDS void advect_snap_kernel(SnapArgs A)
         xl[a] = (float)(x0 - (double)xh[a]);
     }
     uint32_t fl = check_point<D>(A.a.v, xh);
-    int nacc = 0, k = 0;
-    const int last = A.steps[A.n_snap - 1];
+    int nacc = 0, n = 0;
     const long long ns = A.a.ns;
-    for (int n = 0; n < last; ++n) {
-        if (!fl) {
-            fl = advect_steps<D, true>(A.a.v, xh, xl, A.a.t0, A.a.dt, n, n + 1);
-            if (!fl) nacc = n + 1;
+    // from one listed step count to the next in one call, so the tracer's cell
+    // cache carries across the steps of a stretch
+    for (int k = 0; k < A.n_snap; ++k) {
+        const int nk = A.steps[k];
+        if (!fl && nk > n) {
+            int stop = nk;
+            fl = advect_steps<D, true>(A.a.v, xh, xl, A.a.t0, A.a.dt, n, nk, &stop);
+            nacc = stop;
         }
-        if (n + 1 == A.steps[k]) {
+        n = nk;
 #pragma unroll
-            for (int a = 0; a < D; ++a) A.xf[((long long)k * D + a) * ns + s] = xh[a] + xl[a];
-            if (A.flags) A.flags[(long long)k * ns + s] = (uint8_t)fl;
-            ++k;
-        }
+        for (int a = 0; a < D; ++a) A.xf[((long long)k * D + a) * ns + s] = xh[a] + xl[a];
+        if (A.flags) A.flags[(long long)k * ns + s] = (uint8_t)fl;
     }
     if (A.steps_done) A.steps_done[s] = nacc;
 }

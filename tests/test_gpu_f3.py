@@ -101,6 +101,22 @@ def test_snapshots_match_oracle_and_lcs_advect(orc, lcs, torch):
     assert (_np(done) == 200).all() and (do == 200).all()
 
 
+def test_snapshots_equal_lcs_advect_each_step_3d(lcs, torch):
+    """Every snapshot (3D, time-paired frames, stretches integrated in one call
+    each) equals an lcs_advect run of that many steps, bit for bit."""
+    fs = inputs.abc_frames(n=32, n_frames=9, dt_frame=0.5)
+    L = 2 * math.pi
+    g = inputs.periodic_seeds(3, (40, 36, 28), (L, L, L))
+    frames = lcs.DeviceFrames.interleaved(fs, "tpair")
+    steps = [1, 13, 25, 26, 90, 150]
+    xs, fl, done = lcs.lcs_advect_snapshots(frames, g, 0.5, 0.02, steps)
+    for k, n in enumerate(steps):
+        xa, _, fa = lcs.lcs_advect(frames, g, 0.5, 0.02 * n, 0.02)
+        lcs.lcs_sync_status()
+        assert torch.equal(xs[k], xa) and torch.equal(fl[k], fa), n
+    assert (_np(done) == 150).all()
+
+
 def test_snapshot_steps_done_with_exits(orc, lcs, torch):
     c = np.array([0.37, -0.21])
     fs = inputs.uniform_frames(c, dim=2, n=9, lo=0.0, hi=1.0)
