@@ -16,16 +16,15 @@
 #include "lcs_internal.h"
 #include "device_common.h"
 
-// Occupancy hint of the advection kernels (minimum waves per SIMD; 0 = let
-// the compiler choose the register budget).
-#ifndef LCS_ADVECT_MIN_WAVES
-#define LCS_ADVECT_MIN_WAVES 0
+// Occupancy of the RK4 advection kernels: at least LCS_RK4_MIN_WAVES waves per
+// SIMD (4: at most 128 VGPRs), measured faster than the larger register budget
+// the compiler picks by itself; the Adams-Bashforth kernels keep the
+// compiler's budget (capped, they spill and slow down).
+#ifndef LCS_RK4_MIN_WAVES
+#define LCS_RK4_MIN_WAVES 4
 #endif
-#if LCS_ADVECT_MIN_WAVES > 0
-#define LCS_ADVECT_BOUNDS __launch_bounds__(256, LCS_ADVECT_MIN_WAVES)
-#else
-#define LCS_ADVECT_BOUNDS __launch_bounds__(256)
-#endif
+#define LCS_RK4_BOUNDS __launch_bounds__(256, LCS_RK4_MIN_WAVES)
+#define LCS_AB_BOUNDS __launch_bounds__(256)
 
 namespace lcs {
 namespace {
@@ -34,24 +33,31 @@ constexpr uint32_t kOut = LCS_FLAG_OUT;
 constexpr uint32_t kNonFinite = LCS_FLAG_NONFINITE;
 constexpr uint32_t kTimeOut = LCS_FLAG_TIME_OUT;
 
-// Lower node, upper node and local coordinate of the two-float point
-// xh + xl along one axis.  s = (x - origin)/h is formed in two-float
-// arithmetic (the product's rounding error is recovered with an FMA), so the
-// local coordinate is accurate to FP32 rounding of xi itself rather than of
-// the unwrapped position.  Non-periodic: node = floor(s) limited to [0, n-2].
-// Periodic: s folded into [0, n) by whole periods (exact); a fold landing on
-// n is node 0.  s is clamped before any float->int conversion, so every input
-// (NaN included) yields in-range node indices.
-__device__ __forceinline__ void locate(const VelDev &v, int a, float xh, float xl, int &lo,
-                                       int &hi, float &xi)
+// Grid-index coordinate s = (x - origin)/h of the two-float point xh + xl
+// along one axis, as a two-float: the difference and the product are formed in
+// two-float arithmetic (the product's rounding error recovered with an FMA),
+// so s is accurate to FP32 rounding of its fraction rather than of the
+// unwrapped position.
+__device__ __forceinline__ void to_index(const VelDev &v, int a, float xh, float xl, float &sh,
+                                         float &sl)
 {
-    const int n = v.n[a];
-    const float nf = v.nf[a];
     float dh, dl;
     two_sum(xh, -v.oh[a], dh, dl);
     dl += xl - v.ol[a];
-    const float sh = dh * v.ih[a];
-    const float sl = fmaf(dh, v.ih[a], -sh) + fmaf(dh, v.il[a], dl * v.ih[a]);
+    sh = dh * v.ih[a];
+    sl = fmaf(dh, v.ih[a], -sh) + fmaf(dh, v.il[a], dl * v.ih[a]);
+}
+
+// Lower node, upper node and local coordinate of the grid-index point
+// sh + sl along one axis.  Non-periodic: node = floor(s) limited to [0, n-2].
+// Periodic: s folded into [0, n) by whole periods (exact); a fold landing on
+// n is node 0.  s is clamped before any float->int conversion, so every input
+// (NaN included) yields in-range node indices.
+__device__ __forceinline__ void locate_s(const VelDev &v, int a, float sh, float sl, int &lo,
+                                         int &hi, float &xi)
+{
+    const int n = v.n[a];
+    const float nf = v.nf[a];
     if ((v.periodic_mask >> a) & 1u) {
         float f = sh - nf * floorf(sh * (1.0f / nf));   // exact: sh minus a multiple of n
         f = fminf(fmaxf(f, 0.0f), nf);
@@ -232,7 +238,7 @@ __device__ __forceinline__ void gather_cell(const VelDev &v, long long base, con
     }
 }
 
-// u at the two-float point (ph + pl): multilinear in space within frames f and
+// u at the grid-index point (ph + pl): multilinear in space within frames f and
 // f+1, then linear in time.  The corners of a cell come in x-adjacent pairs
 // (i, i+1); on a periodic x axis the pair of the last cell wraps to node 0.
 // The corner values are reused while the tracer stays in the cell and frame
@@ -248,7 +254,7 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
     int lo[3], hi[3];
     float xi[3];
 #pragma unroll
-    for (int a = 0; a < D; ++a) locate(v, a, ph[a], pl[a], lo[a], hi[a], xi[a]);
+    for (int a = 0; a < D; ++a) locate_s(v, a, ph[a], pl[a], lo[a], hi[a], xi[a]);
     const float a1 = alpha, a0 = 1.0f - alpha;
     const int n0 = v.n[0];
     const bool wrap = (hi[0] != lo[0] + 1);          // periodic x, last cell
@@ -305,6 +311,52 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
     return 0;
 }
 
+// Stage increments in grid-index units: (dt/2)/h_a and dt/h_a per axis, as
+// two-floats (the physical stage point x + c k sits at s(x) + (c/h) k).
+struct IdxConsts {
+    float hh[3], hl[3];
+    float fh[3], fl[3];
+};
+
+__device__ __forceinline__ IdxConsts idx_consts(const VelDev &v, double dt)
+{
+    IdxConsts c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double h = 0.5 * dt / v.spacing_d[a], f = dt / v.spacing_d[a];
+        c.hh[a] = (float)h; c.hl[a] = (float)(h - (double)c.hh[a]);
+        c.fh[a] = (float)f; c.fl[a] = (float)(f - (double)c.fh[a]);
+    }
+    return c;
+}
+
+
+// Grid-index stage point (ph + pl) = (sh + sl) + (ch_a + cl_a) k_a.
+template <int D>
+__device__ __forceinline__ void stage_point_s(const float *sh, const float *sl, const float *ch,
+                                              const float *cl, const float *k, float *ph, float *pl)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const float inc = fmaf(ch[a], k[a], cl[a] * k[a]);
+        two_sum(sh[a], sl[a] + inc, ph[a], pl[a]);
+    }
+}
+
+// Domain test of a grid-index point: finite, and within [0, n-1] on the
+// non-periodic axes (the closed domain in index units).
+template <int D>
+__device__ __forceinline__ uint32_t check_point_s(const VelDev &v, const float *p)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (!isfinite(p[a])) return kNonFinite;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        if (!((v.periodic_mask >> a) & 1u) && !(p[a] >= 0.0f && p[a] <= v.nf[a] - 1.0f)) return kOut;
+    return 0;
+}
+
 // Integrate one tracer in place over steps n_begin <= n < n_end of classical
 // RK4 from t0 with step dt, t_n = t0 + n*dt recomputed each step.  The position is carried as a
 // two-float (x = xh + xl).  A stage point or new position that is non-finite
@@ -317,6 +369,7 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
 {
     uint32_t fl = 0;
     const StepConsts sc = step_consts(dt);
+    const IdxConsts ic = idx_consts(v, dt);
     CellCache<D> cc;
     int n = n_begin;
     for (; n < n_end; ++n) {
@@ -332,22 +385,26 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
             frame_at(v, t + 0.5 * dt, b2, al2);
             frame_at(v, t + dt, b4, al4);
         }
-        float k1[3], k2[3], k3[3], k4[3], ph[3], pl[3];
+        // the position in grid-index units once per step; the stage points
+        // are formed there directly
+        float k1[3], k2[3], k3[3], k4[3], sh[3], sl[3], ph[3], pl[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) to_index(v, a, xh[a], xl[a], sh[a], sl[a]);
 
-        velocity<D, L>(v, xh, xl, b1, al1, k1, cc);
+        velocity<D, L>(v, sh, sl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
-        stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
-        if ((fl = check_point<D>(v, ph))) break;
+        stage_point_s<D>(sh, sl, ic.hh, ic.hl, k1, ph, pl);
+        if ((fl = check_point_s<D>(v, ph))) break;
 
         velocity<D, L>(v, ph, pl, b2, al2, k2, cc);
         if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
-        stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
-        if ((fl = check_point<D>(v, ph))) break;
+        stage_point_s<D>(sh, sl, ic.hh, ic.hl, k2, ph, pl);
+        if ((fl = check_point_s<D>(v, ph))) break;
 
         velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
-        stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
-        if ((fl = check_point<D>(v, ph))) break;
+        stage_point_s<D>(sh, sl, ic.fh, ic.fl, k3, ph, pl);
+        if ((fl = check_point_s<D>(v, ph))) break;
 
         velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
         if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
@@ -453,7 +510,7 @@ __device__ __forceinline__ void advect_seed(const VelDev &v, const SeedTiling &g
 }
 
 template <int D>
-__global__ LCS_ADVECT_BOUNDS void advect_grid_kernel(AdvectArgs A)
+__global__ LCS_RK4_BOUNDS void advect_grid_kernel(AdvectArgs A)
 {
     const int m = xcd_remap((int)blockIdx.x, A.g.n_blocks);
     int sc[3];
@@ -492,14 +549,17 @@ __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, flo
     const StepConsts sc = step_consts(dt);
     const double cab = dt / ab_den<S>();
     const float ch = (float)cab, cl = (float)(cab - (double)ch);
+    const IdxConsts ic = idx_consts(v, dt);
     CellCache<D> cc;
     for (int n = n_begin; n < n_end; ++n) {
         const double t = t0 + (double)n * dt;
         long long b1;
         float al1;
         frame_at_uniform(v, t, b1, al1);
-        float k1[3];
-        velocity<D, L>(v, xh, xl, b1, al1, k1, cc);
+        float k1[3], sh[3], sl[3];
+#pragma unroll
+        for (int a = 0; a < D; ++a) to_index(v, a, xh[a], xl[a], sh[a], sl[a]);
+        velocity<D, L>(v, sh, sl, b1, al1, k1, cc);
         if (!finite_vec<D>(k1)) { fl = kNonFinite; break; }
         float nh[3], nl[3];
         if (n < S - 1) {
@@ -508,16 +568,16 @@ __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, flo
             frame_at_uniform(v, t + 0.5 * dt, b2, al2);
             frame_at_uniform(v, t + dt, b4, al4);
             float k2[3], k3[3], k4[3], ph[3], pl[3];
-            stage_point<D>(xh, xl, sc.hh, sc.hl, k1, ph, pl);
-            if ((fl = check_point<D>(v, ph))) break;
+            stage_point_s<D>(sh, sl, ic.hh, ic.hl, k1, ph, pl);
+            if ((fl = check_point_s<D>(v, ph))) break;
             velocity<D, L>(v, ph, pl, b2, al2, k2, cc);
             if (!finite_vec<D>(k2)) { fl = kNonFinite; break; }
-            stage_point<D>(xh, xl, sc.hh, sc.hl, k2, ph, pl);
-            if ((fl = check_point<D>(v, ph))) break;
+            stage_point_s<D>(sh, sl, ic.hh, ic.hl, k2, ph, pl);
+            if ((fl = check_point_s<D>(v, ph))) break;
             velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
             if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
-            stage_point<D>(xh, xl, sc.fh, sc.fl, k3, ph, pl);
-            if ((fl = check_point<D>(v, ph))) break;
+            stage_point_s<D>(sh, sl, ic.fh, ic.fl, k3, ph, pl);
+            if ((fl = check_point_s<D>(v, ph))) break;
             velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
             if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
 #pragma unroll
@@ -560,7 +620,7 @@ __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float
 }
 
 template <int D, int S>
-__global__ LCS_ADVECT_BOUNDS void advect_ab_grid_kernel(AdvectArgs A)
+__global__ LCS_AB_BOUNDS void advect_ab_grid_kernel(AdvectArgs A)
 {
     const int m = xcd_remap((int)blockIdx.x, A.g.n_blocks);
     int sc[3];
@@ -592,7 +652,7 @@ __global__ LCS_ADVECT_BOUNDS void advect_ab_grid_kernel(AdvectArgs A)
 // trajectories stay within about delta of each other).  Outputs keep the
 // two-float (hi, lo) so that the gradient can difference exact FP64 positions.
 template <int D>
-__global__ LCS_ADVECT_BOUNDS void advect_aux_kernel(AuxArgs A)
+__global__ LCS_RK4_BOUNDS void advect_aux_kernel(AuxArgs A)
 {
     const int r = xcd_remap((int)blockIdx.x, A.a.g.n_blocks * 2 * D);
     const int m = r / (2 * D);
@@ -624,7 +684,7 @@ __global__ LCS_ADVECT_BOUNDS void advect_aux_kernel(AuxArgs A)
 // every tracer after each listed step count, and the number of steps it took
 // before it froze.
 template <int D>
-__global__ LCS_ADVECT_BOUNDS void advect_snap_kernel(SnapArgs A)
+__global__ LCS_RK4_BOUNDS void advect_snap_kernel(SnapArgs A)
 {
     const int m = xcd_remap((int)blockIdx.x, A.a.g.n_blocks);
     int sc[3];
@@ -663,7 +723,7 @@ __global__ LCS_ADVECT_BOUNDS void advect_snap_kernel(SnapArgs A)
 // grid's dimension or past a non-periodic edge have no member.  Positions
 // are written in FP64 (two-float sum).
 template <int D>
-__global__ LCS_ADVECT_BOUNDS void early_advect_kernel(EarlyAdvArgs A, int first, int count)
+__global__ LCS_RK4_BOUNDS void early_advect_kernel(EarlyAdvArgs A, int first, int count)
 {
     const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int e = (int)(w / 7), slot = (int)(w % 7);
@@ -936,7 +996,7 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
 // Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
 // segment) or the state in place plus its new key and the histogram.
 template <int D, int S>
-__global__ LCS_ADVECT_BOUNDS void rebundle_segment_kernel(SegmentArgs A)
+__global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_segment_kernel(SegmentArgs A)
 {
     const int nblocks = (int)gridDim.x;
     const long long p = (long long)xcd_remap((int)blockIdx.x, nblocks) * blockDim.x + threadIdx.x;
