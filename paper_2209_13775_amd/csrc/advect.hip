@@ -959,6 +959,28 @@ __device__ __forceinline__ uint32_t bin_key(const VelDev &v, const SortKeys &k, 
     return key;
 }
 
+// counts[key] += 1 for every active lane, one atomic per run of consecutive
+// active lanes with equal keys (tracers that stay together keep landing in the
+// same bin, and same-address atomics from one wave serialise).  Returns the
+// lane's slot: the counter's old value plus the lane's rank in its run.
+__device__ __forceinline__ uint32_t run_atomic_inc(uint32_t *counts, uint32_t key)
+{
+    const uint64_t act = __ballot(1);
+    const int lane = (int)__lane_id();
+    const uint32_t prev = (uint32_t)__shfl_up((int)key, 1);
+    const bool start = lane == 0 || !((act >> (lane - 1)) & 1ull) || prev != key;
+    const uint64_t starts = __ballot(start);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= lane
+    const int s0 = 63 - __clzll(starts & upto);                              // my run's first lane
+    const uint64_t later = starts & ~upto;
+    const int s1 = later ? __ffsll((long long)later) - 1 : 64;               // next run's first lane
+    const uint64_t run = ((s1 == 64) ? ~0ull : ((1ull << s1) - 1ull)) & ~((1ull << s0) - 1ull);
+    uint32_t base = 0;
+    if (lane == s0) base = atomicAdd(&counts[key], (uint32_t)__popcll(act & run));
+    base = (uint32_t)__shfl((int)base, s0);
+    return base + (uint32_t)(lane - s0);
+}
+
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, long long n, uint32_t v)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -990,7 +1012,7 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
         for (int q = 0; q < 3 * D; ++q) A.st.hist[q][p] = 0.0f;
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
-    atomicAdd(&A.sk.counts[key], 1u);
+    (void)run_atomic_inc(A.sk.counts, key);
 }
 
 // Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
@@ -1044,7 +1066,7 @@ __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_
     }
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
-    atomicAdd(&A.sk.counts[key], 1u);
+    (void)run_atomic_inc(A.sk.counts, key);
 }
 
 // Exclusive scan of the counts: blocks of 1024 (4 per thread), block totals,
@@ -1115,7 +1137,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(SegmentArgs A, TracerState
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
     const uint32_t key = A.sk.keys[p];
-    const long long q = atomicAdd(&A.sk.counts[key], 1u);
+    const long long q = run_atomic_inc(A.sk.counts, key);
     if (q >= A.n) return;   // cannot happen when the histogram matches the keys
 #pragma unroll
     for (int a = 0; a < D; ++a) {
