@@ -218,3 +218,35 @@ def test_layouts_give_identical_bits(lcs, torch):
     x_xy = lcs.lcs_advect(lcs.DeviceFrames.interleaved(fs2, "xyz"), g2, 0.5, 7.0, 0.05)[0]
     lcs.lcs_sync_status()
     assert torch.equal(x_soa, x_xy)
+
+
+def test_tpair_equals_soa_in_every_entry_point(lcs, torch):
+    """Points, batched windows, auxiliary points, snapshots and early FTLE read
+    time-paired frames through the same step loop: the same bits as with
+    structure-of-arrays frames, on a closed box where tracers leave."""
+    L = 2 * math.pi
+    fs = inputs.sample_field(inputs.abc_velocity, 3, (33, 33, 33), (0.0,) * 3, (L / 32,) * 3,
+                             (False,) * 3, 0.0, 0.5, 9).astype(np.float32)
+    g = inputs.linspace_seeds(3, (22, 20, 18), (0.3,) * 3, (L - 0.3,) * 3)
+    t0, dt, N = 0.5, 0.02, 150
+    soa = lcs.DeviceFrames(fs)
+    tp = lcs.lcs_frames_interleave(soa, "tpair")
+    rng = np.random.default_rng(5)
+    x0 = torch.from_numpy(rng.uniform(0.2, L - 0.2, size=(3, 777)).astype(np.float32)).cuda()
+    tt = torch.from_numpy(rng.uniform(0.0, 1.0, size=777)).cuda()
+    windows = [(0.5, 2.0), (1.0, 1.5), (0.0, 3.0)]
+    out = {}
+    for name, fr in (("soa", soa), ("tpair", tp)):
+        plan = lcs.Plan()
+        r = {"points": lcs.lcs_advect_points(fr, x0, tt, 2.5, dt),
+             "batched": lcs.lcs_advect_batched(plan, fr, g, windows, dt),
+             "aux": lcs.lcs_advect_aux(fr, g, [1e-3, 1e-3, 1e-3], t0, 2.0, dt),
+             "snap": lcs.lcs_advect_snapshots(fr, g, t0, dt, [40, N])}
+        r["early"] = lcs.lcs_ftle_early(fr, g, t0, dt, N, r["snap"][0][1], r["snap"][2])
+        lcs.lcs_sync_status()
+        plan.close()
+        out[name] = r
+    for key in out["soa"]:
+        for u, v in zip(out["soa"][key], out["tpair"][key]):
+            assert torch.equal(u, v), key
+    assert int((out["soa"]["snap"][1][1] != 0).sum()) > 0      # some tracers left the box
