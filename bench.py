@@ -60,10 +60,24 @@ def parse():
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+def source_hash(files):
+    """SHA-1 (16 hex digits) of kernel sources with comments and blank lines
+    removed: the code the counters were taken on, not its commentary."""
+    import hashlib
+    import re
+    h = hashlib.sha1()
+    for f in files:
+        text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, f)).read(), flags=re.S)
+        for line in text.splitlines():
+            line = re.sub(r"//.*$", "", line).strip()
+            if line:
+                h.update(line.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
 def profiled_traffic_kernel(kernel):
     """HBM bytes per launch of a kernel from its committed rocprofv3 counter
     summary, or None if there is none or its source changed since."""
-    import hashlib
     try:
         names = sorted(os.listdir(PROFILES))
     except OSError:
@@ -77,10 +91,7 @@ def profiled_traffic_kernel(kernel):
             rec = json.loads(line)
             if rec.get("kernel") != kernel:
                 continue
-            h = hashlib.sha1()
-            for f in rec["source_files"]:
-                h.update(open(os.path.join(ROOT, f), "rb").read())
-            if h.hexdigest()[:16] == rec["source_sha1"]:
+            if source_hash(rec["source_files"]) == rec["source_sha1"]:
                 return rec["traffic_bytes_per_launch"]
     return None
 
@@ -105,7 +116,6 @@ def profiled_traffic(strategy, layout="soa"):
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain
     copy of known size), or None if it was taken for another strategy or the
     kernel source changed since."""
-    import hashlib
     try:
         names = sorted(os.listdir(PROFILES))
     except OSError:
@@ -119,10 +129,7 @@ def profiled_traffic(strategy, layout="soa"):
             rec = json.loads(line)
             if rec.get("strategy", "tiles") != strategy or rec.get("layout", "soa") != layout:
                 continue
-            h = hashlib.sha1()
-            for f in rec["source_files"]:
-                h.update(open(os.path.join(ROOT, f), "rb").read())
-            if h.hexdigest()[:16] == rec["source_sha1"]:
+            if source_hash(rec["source_files"]) == rec["source_sha1"]:
                 return rec["traffic_bytes_per_launch"]
     return None
 

@@ -6,12 +6,13 @@
 // budget (Sec. 3.1), which CDNA's 512-VGPR lanes do not need.
 //
 // Per evaluation (Sec. 2 Interpolator; Sec. 3.2): locate the cell on each
-// axis, gather the 2^D corners of the two frames that bracket t from the
-// structure-of-arrays frames, multilinear weights in space, then linear in
-// time.  Seeds, positions and stage points are carried as two-floats
-// (hi + lo): chaotic flows amplify any start or position rounding by
-// exp(sigma T), so only the FP32 interpolation arithmetic itself is left to
-// round.
+// axis, take the 2^D corners of the two frames that bracket t (from the
+// tracer's register cache of the cell it sampled last, else gathered from the
+// frames in their layout), multilinear weights in space, then linear in time.
+// Seeds and positions are carried as two-floats (hi + lo) and the stage
+// points as two-float grid-index coordinates: chaotic flows amplify any start
+// or position rounding by exp(sigma T), so only the FP32 interpolation
+// arithmetic itself is left to round.
 
 #include "lcs_internal.h"
 #include "device_common.h"
@@ -99,10 +100,12 @@ __device__ __forceinline__ void frame_at_uniform(const VelDev &v, double t, long
 }
 
 // Frame layouts: structure of arrays (one array per component; the x pair
-// (i, i+1) of a cell row is one 8-byte load per component) or interleaved
+// (i, i+1) of a cell row is one 8-byte load per component), interleaved
 // records (2, 3 or 4 floats per node with the components together; one 12-byte
-// load per node in 3D, one 16-byte load per x pair in 2D).  Every load is a
-// 32-bit byte offset from a wave-uniform frame base.
+// load per node in 3D, one 16-byte load per x pair in 2D) or, in 3D,
+// time-paired records (both frames of a pair per node, an extra node per x row;
+// the x pair of a cell row in both frames is three 16-byte loads).  Every load
+// is a 32-bit byte offset from a wave-uniform frame base.
 
 // Corner values of the cell a tracer sampled last, for both frames of the
 // pair, kept in registers: consecutive RK4 stage points mostly fall in the
