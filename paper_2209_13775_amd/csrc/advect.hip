@@ -290,13 +290,26 @@ __device__ __forceinline__ void velocity(const VelDev &v, const float *ph, const
         cc.node = key;
         cc.base = base;
     }
+    // corner weights (product of the axis weights), then one FMA chain per
+    // component and frame
+    float w[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        w[r][0] = wr[r] * wx0;
+        w[r][1] = wr[r] * wx1;
+    }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        float ua = 0.0f, ub = 0.0f;
+        float ua = w[0][0] * cc.c[0][0][0][k], ub = w[0][0] * cc.c[1][0][0][k];
+        ua = fmaf(w[0][1], cc.c[0][0][1][k], ua);
+        ub = fmaf(w[0][1], cc.c[1][0][1][k], ub);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            ua = fmaf(wr[r], fmaf(wx1, cc.c[0][r][1][k], wx0 * cc.c[0][r][0][k]), ua);
-            ub = fmaf(wr[r], fmaf(wx1, cc.c[1][r][1][k], wx0 * cc.c[1][r][0][k]), ub);
+        for (int r = 1; r < R; ++r) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                ua = fmaf(w[r][e], cc.c[0][r][e][k], ua);
+                ub = fmaf(w[r][e], cc.c[1][r][e][k], ub);
+            }
         }
         out[k] = fmaf(a1, ub, a0 * ua);
     }
