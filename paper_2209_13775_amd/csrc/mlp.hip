@@ -387,11 +387,23 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
 constexpr int kFT = 128;                  // samples per workgroup
 constexpr int kActStride = kMlpWidth + 8; // BF16 per LDS row (16-byte aligned rows)
 
-// tanh-form GELU written as z * sigmoid(2u): z / (1 + exp(-2u))
+// tanh-form GELU written as z * sigmoid(2u) = z / (1 + exp(-2u)), with the
+// hardware reciprocal (the result is rounded to BF16 next)
 __device__ __forceinline__ float gelu_fast(float z)
 {
     const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    return z / (1.0f + __expf(-2.0f * u));
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+}
+
+// Four floats rounded to BF16 (to nearest even) and packed in 8 bytes, two
+// per conversion.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
+{
+    const bf16x2 lo = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const bf16x2 hi = __builtin_convertvector((f32x2){c, d}, bf16x2);
+    return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
 }
 
 __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
@@ -432,6 +444,9 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             const int K = mlp_in_width(l);
             const uint16_t *Wt = P.wbf + mlp_off_bf16(l) + (long long)K * kMlpWidth;   // [256][K]
             const float *bias = P.params + mlp_off_b(l);
+            // the transposed product out^T[n][m] = sum_k W^T[n][k] act[m][k]: weights
+            // as the A operand, activations as B, so that a lane's four results
+            // are four consecutive output columns n of one sample m
             f32x4 acc[8][4];
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -439,33 +454,33 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
                 for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
             const int ko = 8 * (lane / 16);
             for (int kk = 0; kk < K; kk += 32) {
-                bf16x8 bfr[4];
+                bf16x8 wfr[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int n = wave * 64 + 16 * j + lane % 16;
-                    bfr[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
+                    wfr[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
                 }
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const bf16x8 af = *reinterpret_cast<const bf16x8 *>(
+                    const bf16x8 xfr = *reinterpret_cast<const bf16x8 *>(
                         &act[(16 * i + lane % 16) * kActStride + kk + ko]);
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[j], xfr, acc[i][j], 0, 0, 0);
                 }
             }
             __syncthreads();   // every wave has read this layer's input
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int n = wave * 64 + 16 * j + lane % 16;
-                const float bn = bias[n];
+                const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+                const float b0 = bias[n0], b1 = bias[n0 + 1], b2 = bias[n0 + 2], b3 = bias[n0 + 3];
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int m = 16 * i + 4 * (lane / 16) + e;
-                        act[m * kActStride + n] = f2bf(gelu_fast(acc[i][j][e] + bn));
-                    }
+                for (int i = 0; i < 8; ++i) {
+                    const int m = 16 * i + lane % 16;
+                    *reinterpret_cast<uint2 *>(&act[m * kActStride + n0]) =
+                        pack_bf16x4(gelu_fast(acc[i][j][0] + b0), gelu_fast(acc[i][j][1] + b1),
+                                    gelu_fast(acc[i][j][2] + b2), gelu_fast(acc[i][j][3] + b3));
+                }
             }
             __syncthreads();
         }
