@@ -23,9 +23,7 @@ struct lcs_mesh {
     int dim = 0;
     long long n_nodes = 0, n_cells = 0;
     int device = -1;
-    float4 *geo = nullptr;
-    int4 *nbr = nullptr;
-    int4 *conn = nullptr;
+    float4 *rec = nullptr;   // [n_cells][RS] geometry, neighbours, node ids
     int *loc = nullptr;
     int nb[3] = {1, 1, 1};
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, bs[3] = {1, 1, 1};
@@ -38,9 +36,7 @@ namespace {
 void free_mesh(lcs_mesh *m)
 {
     if (!m) return;
-    if (m->geo) (void)hipFree(m->geo);
-    if (m->nbr) (void)hipFree(m->nbr);
-    if (m->conn) (void)hipFree(m->conn);
+    if (m->rec) (void)hipFree(m->rec);
     if (m->loc) (void)hipFree(m->loc);
     delete m;
 }
@@ -85,9 +81,7 @@ lcs::MeshDev mesh_dev(const lcs_mesh *m)
 {
     lcs::MeshDev d;
     memset(&d, 0, sizeof(d));
-    d.geo = m->geo;
-    d.nbr = m->nbr;
-    d.conn = m->conn;
+    d.rec = m->rec;
     d.loc = m->loc;
     for (int a = 0; a < 3; ++a) {
         d.nb[a] = m->nb[a];
@@ -168,16 +162,14 @@ lcs_status lcs_mesh_create(const lcs_mesh_desc_t *desc, lcs_mesh_t *out, void *s
     hipStream_t s = (hipStream_t)stream;
     const int D = desc->dim;
     const long long nn = desc->n_nodes, nc = desc->n_cells;
-    const int G = (D == 3) ? 4 : 2;
     lcs_mesh *m = new lcs_mesh();
     m->dim = D;
     m->n_nodes = nn;
     m->n_cells = nc;
     MESH_HIP(hipGetDevice(&m->device), "hipGetDevice");
-    MESH_HIP(hipMalloc(&m->geo, sizeof(float4) * G * nc), "hipMalloc(geo)");
-    MESH_HIP(hipMalloc(&m->nbr, sizeof(int4) * nc), "hipMalloc(nbr)");
-    MESH_HIP(hipMalloc(&m->conn, sizeof(int4) * nc), "hipMalloc(conn)");
-    m->bytes = (long long)(sizeof(float4) * G + 2 * sizeof(int4)) * nc;
+    const int RS = (D == 3) ? lcs::MeshGeo<3>::RS : lcs::MeshGeo<2>::RS;
+    MESH_HIP(hipMalloc(&m->rec, sizeof(float4) * RS * nc), "hipMalloc(cell records)");
+    m->bytes = (long long)sizeof(float4) * RS * nc;
 
     Scratch tmp;
     uint32_t *off = nullptr, *sums = nullptr;
@@ -210,8 +202,8 @@ lcs_status lcs_mesh_create(const lcs_mesh_desc_t *desc, lcs_mesh_t *out, void *s
     // 2. adjacency lists, 3. geometry + neighbours, 4. bounding box
     MESH_HIP(lcs::launch_exclusive_scan_u32(off, nn, sums, s), "mesh scan");
     MESH_HIP(lcs::launch_mesh_adjacency(D, desc->cells, nc, nn, off, adj, s), "mesh adjacency");
-    MESH_HIP(lcs::launch_mesh_cells(D, desc->nodes, desc->cells, nc, off, adj, m->geo, m->nbr,
-                                    m->conn, err, nbnd, s), "mesh cells");
+    MESH_HIP(lcs::launch_mesh_cells(D, desc->nodes, desc->cells, nc, off, adj, m->rec, err, nbnd, s),
+             "mesh cells");
     MESH_HIP(lcs::launch_mesh_bbox(D, desc->nodes, nn, part, kBboxParts, box, s), "mesh bbox");
     double h_box[6];
     unsigned long long h_nb = 0;

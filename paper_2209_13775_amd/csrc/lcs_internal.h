@@ -383,12 +383,20 @@ hipError_t launch_ftle(int dim, const FtleArgs &a, hipStream_t s);
 //   lambda_{k+1} = M_k . (x - r) + c_k  (k < dim),  lambda_0 = 1 - sum_k lambda_{k+1}.
 // 3D, 4 float4 per cell: (r.xyz, c0), (M0.xyz, c1), (M1.xyz, c2), (M2.xyz, 0)
 // 2D, 2 float4 per cell: (r.xy, c0, c1), (M0.xy, M1.xy)
-template <int D> struct MeshGeo { static constexpr int G = (D == 3) ? 4 : 2; };
+// Per cell one record of RS float4 (96 B in 3D, 64 B in 2D): G float4 of
+// geometry, the face neighbours (int4, -1 on a boundary face; neighbour i is
+// across the face opposite vertex i), the node ids (int4, .w = -1 in 2D), so
+// a walk step and an evaluation's node ids come from the lines the geometry
+// load brought in.  (Padding 3D records to 128 B measured slower: the larger
+// footprint costs more than the alignment gains.)
+template <int D> struct MeshGeo {
+    static constexpr int G = (D == 3) ? 4 : 2;
+    static constexpr int RS = (D == 3) ? 6 : 4;
+    static constexpr int NBR = G, CONN = G + 1;
+};
 
 struct MeshDev {
-    const float4 *geo;        // [n_cells][G]
-    const int4 *nbr;          // [n_cells] neighbour across the face opposite vertex i (-1 boundary)
-    const int4 *conn;         // [n_cells] node ids (.w = -1 in 2D)
+    const float4 *rec;        // [n_cells][RS] cell records
     const int *loc;           // [nb0*nb1*nb2] first-location start cell per bucket (-1 none)
     int nb[3];
     float lo[3];
@@ -434,8 +442,8 @@ hipError_t launch_mesh_degree(int dim, const int32_t *cells, long long n_cells, 
 hipError_t launch_mesh_adjacency(int dim, const int32_t *cells, long long n_cells,
                                  long long n_nodes, uint32_t *off, int32_t *adj, hipStream_t s);
 hipError_t launch_mesh_cells(int dim, const double *nodes, const int32_t *cells, long long n_cells,
-                             const uint32_t *off, const int32_t *adj, float4 *geo, int4 *nbr,
-                             int4 *conn, int *err, unsigned long long *n_boundary, hipStream_t s);
+                             const uint32_t *off, const int32_t *adj, float4 *rec, int *err,
+                             unsigned long long *n_boundary, hipStream_t s);
 hipError_t launch_mesh_bbox(int dim, const double *nodes, long long n_nodes, double *part,
                             int n_parts, double *out, hipStream_t s);
 hipError_t launch_mesh_raster(int dim, const double *nodes, const int32_t *cells, long long n_cells,

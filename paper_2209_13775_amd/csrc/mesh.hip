@@ -128,11 +128,10 @@ __device__ bool cell_affine(const double *nodes, const int32_t *cells, long long
 template <int D>
 __global__ __launch_bounds__(256) void mesh_cells_kernel(const double *nodes, const int32_t *cells,
                                                          long long n_cells, const uint32_t *off,
-                                                         const int32_t *adj, float4 *geo,
-                                                         int4 *nbr, int4 *conn, int *err,
+                                                         const int32_t *adj, float4 *rec, int *err,
                                                          unsigned long long *n_boundary)
 {
-    constexpr int G = MeshGeo<D>::G;
+    constexpr int RS = MeshGeo<D>::RS;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     int nd[4] = {-1, -1, -1, -1};
@@ -153,7 +152,7 @@ __global__ __launch_bounds__(256) void mesh_cells_kernel(const double *nodes, co
         for (int a = 0; a < D; ++a) s += M[k][a] * ((double)r[a] - v[0][a]);
         cc[k] = s;
     }
-    float4 *g = geo + c * G;
+    float4 *g = rec + c * RS;
     if constexpr (D == 3) {
         g[0] = make_float4(r[0], r[1], r[2], (float)cc[0]);
         g[1] = make_float4((float)M[0][0], (float)M[0][1], (float)M[0][2], (float)cc[1]);
@@ -192,8 +191,8 @@ __global__ __launch_bounds__(256) void mesh_cells_kernel(const double *nodes, co
         if (found < 0) atomicAdd(n_boundary, 1ull);
         nb[i] = found;
     }
-    nbr[c] = make_int4(nb[0], nb[1], nb[2], nb[3]);
-    conn[c] = make_int4(nd[0], nd[1], nd[2], D == 3 ? nd[3] : -1);
+    reinterpret_cast<int4 *>(g)[MeshGeo<D>::NBR] = make_int4(nb[0], nb[1], nb[2], nb[3]);
+    reinterpret_cast<int4 *>(g)[MeshGeo<D>::CONN] = make_int4(nd[0], nd[1], nd[2], D == 3 ? nd[3] : -1);
 }
 
 // Bounding box: per-block partial min/max, then one block combines them.
@@ -353,7 +352,7 @@ __device__ __forceinline__ uint32_t walk(const MeshDev &m, const float *ph, cons
     constexpr int G = MeshGeo<D>::G;
     for (int s = 0; s < m.max_walk; ++s) {
         if (!LCS_MESH_CACHE || c != mc.gcell) {
-            const float4 *g = m.geo + (long long)c * G;
+            const float4 *g = m.rec + (long long)c * MeshGeo<D>::RS;
 #pragma unroll
             for (int i = 0; i < G; ++i) mc.q[i] = g[i];
             mc.gcell = c;
@@ -368,7 +367,7 @@ __device__ __forceinline__ uint32_t walk(const MeshDev &m, const float *ph, cons
                 imin = i;
             }
         if (lmin >= -m.eps) return 0;
-        const int4 nb = m.nbr[c];
+        const int4 nb = reinterpret_cast<const int4 *>(m.rec + (long long)c * MeshGeo<D>::RS)[MeshGeo<D>::NBR];
         const int next = (imin == 0) ? nb.x : (imin == 1) ? nb.y : (imin == 2) ? nb.z : nb.w;
         if (next < 0) return kOut;
         c = next;
@@ -436,7 +435,7 @@ __device__ __forceinline__ void mesh_velocity(const MeshDev &m, const MeshFrames
 {
 #pragma clang fp contract(off)
     if (!LCS_MESH_CACHE || c != mc.vcell || base != mc.vbase) {
-        const int4 cn = m.conn[c];
+        const int4 cn = reinterpret_cast<const int4 *>(m.rec + (long long)c * MeshGeo<D>::RS)[MeshGeo<D>::CONN];
         const int nd[4] = {cn.x, cn.y, cn.z, cn.w};
         const float *A = f.u + base;
         const float *B = A + f.frame_stride;
@@ -674,15 +673,15 @@ hipError_t launch_mesh_adjacency(int dim, const int32_t *cells, long long n_cell
 }
 
 hipError_t launch_mesh_cells(int dim, const double *nodes, const int32_t *cells, long long n_cells,
-                             const uint32_t *off, const int32_t *adj, float4 *geo, int4 *nbr,
-                             int4 *conn, int *err, unsigned long long *n_boundary, hipStream_t s)
+                             const uint32_t *off, const int32_t *adj, float4 *rec, int *err,
+                             unsigned long long *n_boundary, hipStream_t s)
 {
     if (dim == 2)
         hipLaunchKernelGGL(mesh_cells_kernel<2>, dim3(blocks_for(n_cells)), dim3(256), 0, s, nodes,
-                           cells, n_cells, off, adj, geo, nbr, conn, err, n_boundary);
+                           cells, n_cells, off, adj, rec, err, n_boundary);
     else
         hipLaunchKernelGGL(mesh_cells_kernel<3>, dim3(blocks_for(n_cells)), dim3(256), 0, s, nodes,
-                           cells, n_cells, off, adj, geo, nbr, conn, err, n_boundary);
+                           cells, n_cells, off, adj, rec, err, n_boundary);
     return hipGetLastError();
 }
 
