@@ -451,14 +451,21 @@ def bench_aux(torch, lcs, inputs, reps=2):
             ms.append(e0.elapsed_time(e1))
         return out, float(np.median(ms))
 
+    # every variant re-bundled, segments of 100 steps
+    ws = torch.empty(max(lcs.lcs_advect_aux_sorted_workspace_bytes(frames, g),
+                         lcs.lcs_advect_sorted_workspace_bytes(frames, g2)),
+                     dtype=torch.uint8, device="cuda")
+
     def aux(delta):
-        hi, lo, fl = lcs.lcs_advect_aux(frames, g, [delta] * 3, 0.0, T, dt, stream=stream)
+        hi, lo, fl = lcs.lcs_advect_aux_sorted(frames, g, [delta] * 3, 0.0, T, dt, 100,
+                                               workspace=ws, stream=stream)
         Cm, sfl = lcs.lcs_cg_aux(g, [delta] * 3, hi, lo, fl, stream=stream)
         _, sig = lcs.lcs_ftle(3, Cm, T, want_lambda=False, stream=stream)
         return sig
 
     def grid(gg):
-        xf, _, fl = lcs.lcs_advect(frames, gg, 0.0, T, dt, want_cell=False, stream=stream)
+        xf, _, fl = lcs.lcs_advect_sorted(frames, gg, 0.0, T, dt, 100, workspace=ws, want_cell=False,
+                                          stream=stream)
         _, sig, _ = lcs.lcs_cg_ftle(gg, xf, T, flags=fl, stream=stream)
         return sig
 
@@ -476,6 +483,7 @@ def bench_aux(torch, lcs, inputs, reps=2):
 
     ns = g.count
     return {"workload": "abc_128cubed_ftle_at_128cubed_seeds_aux_vs_grid", "frame_layout": LAYOUT_3D,
+            "advect_strategy": "re-bundled, segments of 100 (lcs_advect_aux_sorted, lcs_advect_sorted)",
             "reference":
             "auxiliary points, delta = h/100", "seed_spacing_h": h,
             "grid_128cubed": dict(ms=ms_g1, tracers=ns, **err(s_g1)),

@@ -484,6 +484,21 @@ lcs_status lcs_advect_aux(const lcs_velocity_t *vel, const lcs_seed_grid_t *seed
                           float *xa_lo, uint8_t *flags, void *stream);
 
 /*
+ * lcs_advect_aux_sorted -- lcs_advect_aux with the auxiliary tracers
+ * re-bundled by position between segments of segment_steps steps (0: 50), as
+ * lcs_advect_sorted does for seeds.  Same outputs, bit for bit.
+ * workspace [device], at least lcs_advect_aux_sorted_workspace_bytes(vel, seeds)
+ * bytes (caller-owned).  Errors: as lcs_advect_aux and lcs_advect_sorted, and
+ * LCS_E_SHAPE for more than 2^31-1 auxiliary points.
+ */
+int64_t lcs_advect_aux_sorted_workspace_bytes(const lcs_velocity_t *vel,
+                                              const lcs_seed_grid_t *seeds);
+lcs_status lcs_advect_aux_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                 const double *delta, double t0, double T, double dt,
+                                 int32_t segment_steps, float *xa_hi, float *xa_lo, uint8_t *flags,
+                                 void *workspace, int64_t workspace_bytes, void *stream);
+
+/*
  * lcs_cg_aux -- Cauchy-Green tensor from auxiliary points (Eq. 1; Sec. 2
  * Cauchy-Green filter): J[a][b] = (F_a(x0 + delta_b e_b) - F_a(x0 - delta_b e_b))
  * / (2 delta_b) in FP64 from the exact two-float positions, C = J^T J packed as

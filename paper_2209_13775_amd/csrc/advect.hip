@@ -1011,11 +1011,15 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
     const SeedTiling &g = A.g;
-    const long long c[3] = {p % g.sn[0], (p / g.sn[0]) % g.sn[1], p / ((long long)g.sn[0] * g.sn[1])};
+    // a seed, or auxiliary point q = 2b + side of seed s (side 0: x0 - delta_b e_b)
+    const int q = A.aux ? (int)(p / A.ns_seeds) : -1;
+    const long long sd = A.aux ? p - (long long)q * A.ns_seeds : p;
+    const long long c[3] = {sd % g.sn[0], (sd / g.sn[0]) % g.sn[1], sd / ((long long)g.sn[0] * g.sn[1])};
     float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double x0 = g.s_origin[a] + (double)c[a] * g.s_spacing[a];
+        double x0 = g.s_origin[a] + (double)c[a] * g.s_spacing[a];
+        if (a == (q >> 1)) x0 = (q & 1) ? x0 + A.delta[a] : x0 - A.delta[a];
         xh[a] = (float)x0;
         xl[a] = (float)(x0 - (double)xh[a]);
         A.st.xh[a][p] = xh[a];
@@ -1062,7 +1066,12 @@ __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             x[a] = xh[a] + xl[a];
-            A.xf[a * A.n + s] = x[a];
+            if (A.xf_lo) {
+                A.xf[a * A.n + s] = xh[a];
+                A.xf_lo[a * A.n + s] = xl[a];
+            } else {
+                A.xf[a * A.n + s] = x[a];
+            }
         }
         if (A.cell) A.cell[s] = cell_index<D>(A.v, x);
         if (A.flags) A.flags[s] = (uint8_t)fl;

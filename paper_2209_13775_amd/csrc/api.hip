@@ -820,16 +820,24 @@ int64_t lcs_advect_ab_sorted_workspace_bytes(const lcs_velocity_t *vel, const lc
 
 namespace {
 
-// Re-bundled advection with RK4 (order 0) or Adams-Bashforth (order 2..4).
+// Re-bundled advection with RK4 (order 0) or Adams-Bashforth (order 2..4), of
+// the seeds or (delta != NULL) of the 2*dim auxiliary points of every seed,
+// whose outputs are two-floats (xf high, xf_lo low parts).
 lcs_status advect_sorted_impl(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, int order,
                               double t0, double T, double dt, int32_t segment_steps, float *xf,
                               int64_t *cell, uint8_t *flags, void *workspace,
-                              int64_t workspace_bytes, void *stream)
+                              int64_t workspace_bytes, void *stream, const double *delta = nullptr,
+                              float *xf_lo = nullptr)
 {
     lcs_status st;
     if ((st = check_velocity(vel)) != LCS_OK) return st;
     if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
     if (!xf || !workspace) return lcs::set_error(LCS_E_ARG, "xf and workspace must not be NULL");
+    if (delta) {
+        for (int a = 0; a < vel->dim; ++a)
+            if (!finite_pos(delta[a])) return lcs::set_error(LCS_E_ARG, "delta[%d] must be > 0", a);
+        if (!xf_lo) return lcs::set_error(LCS_E_ARG, "xa_hi and xa_lo must not be NULL");
+    }
     if (segment_steps < 0) return lcs::set_error(LCS_E_ARG, "segment_steps must be >= 0");
     int nsteps = 0;
     if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
@@ -839,7 +847,9 @@ lcs_status advect_sorted_impl(const lcs_velocity_t *vel, const lcs_seed_grid_t *
         return lcs::set_error(LCS_E_TIME_RANGE, "[%g, %g] leaves the frame span [%g, %g]", t0, t1,
                               vel->t_first, t_last);
     if ((st = check_seed_domain(vel, seeds)) != LCS_OK) return st;
-    const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    const long long n = delta ? 2LL * vel->dim * ns : ns;
+    if (n > kMaxSeeds) return lcs::set_error(LCS_E_SHAPE, "more than 2^31-1 tracers");
     lcs::TracerState bufs[2];
     memset(bufs, 0, sizeof(bufs));
     const SortedLayout need = sorted_layout(vel, n, nullptr, nullptr, order);
@@ -860,10 +870,16 @@ lcs_status advect_sorted_impl(const lcs_velocity_t *vel, const lcs_seed_grid_t *
     A.n = n;
     A.sk = L.sk;
     A.xf = xf;
+    A.xf_lo = xf_lo;
     A.cell = reinterpret_cast<long long *>(cell);
     A.flags = flags;
     A.order = order;
     A.st = bufs[0];
+    if (delta) {
+        A.aux = 1;
+        A.ns_seeds = ns;
+        for (int a = 0; a < vel->dim; ++a) A.delta[a] = delta[a];
+    }
     hipError_t e = lcs::launch_fill_u32(L.sk.counts, L.sk.n_keys, 0u, s);
     if (e == hipSuccess) e = lcs::launch_rebundle_init(vel->dim, A, s);
     if (e == hipSuccess) e = lcs::launch_rebundle_sort(vel->dim, A, bufs[1], s);
@@ -903,6 +919,24 @@ lcs_status lcs_advect_ab_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t
     if (order < 2 || order > 4) return lcs::set_error(LCS_E_ARG, "order must be 2, 3 or 4");
     return advect_sorted_impl(vel, seeds, order, t0, T, dt, segment_steps, xf, cell, flags,
                               workspace, workspace_bytes, stream);
+}
+
+int64_t lcs_advect_aux_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds)
+{
+    if (check_velocity(vel) != LCS_OK || check_seeds(seeds, vel->dim) != LCS_OK) return 0;
+    const long long n = 2LL * vel->dim * seeds->n[0] * seeds->n[1] * seeds->n[2];
+    return sorted_layout(vel, n, nullptr, nullptr).bytes;
+}
+
+lcs_status lcs_advect_aux_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                 const double *delta, double t0, double T, double dt,
+                                 int32_t segment_steps, float *xa_hi, float *xa_lo, uint8_t *flags,
+                                 void *workspace, int64_t workspace_bytes, void *stream)
+{
+    if (!delta) return lcs::set_error(LCS_E_ARG, "delta is NULL");
+    if (!xa_hi || !xa_lo) return lcs::set_error(LCS_E_ARG, "xa_hi and xa_lo must not be NULL");
+    return advect_sorted_impl(vel, seeds, 0, t0, T, dt, segment_steps, xa_hi, nullptr, flags,
+                              workspace, workspace_bytes, stream, delta, xa_lo);
 }
 
 lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0, int64_t n,

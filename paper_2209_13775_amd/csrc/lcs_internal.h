@@ -328,8 +328,12 @@ struct SegmentArgs {
     int last;                         // 1: write outputs instead of state + keys
     int order;                        // 0: RK4; 2..4: Adams-Bashforth
     float *xf;
+    float *xf_lo;                     // non-null: xf gets the high and xf_lo the low part
     long long *cell;
     uint8_t *flags;
+    int aux;                          // tracer q*ns_seeds + s: auxiliary point q of seed s
+    long long ns_seeds;
+    double delta[3];
 };
 
 hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s);

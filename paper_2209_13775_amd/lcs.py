@@ -93,6 +93,7 @@ def _load(path: str = LIB_PATH):
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
         "lcs_frames_interleave": [P, C.c_uint32, I32, I32, P, P, P],
         "lcs_advect_aux": [P, P, P, D, D, D, P, P, P, P],
+        "lcs_advect_aux_sorted": [P, P, P, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_cg_eig": [I32, I64, P, P, P, P],
         "lcs_advect_ab_sorted": [P, P, I32, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_advect_snapshots": [P, P, D, D, I32, P, P, P, P, P],
@@ -121,6 +122,8 @@ def _load(path: str = LIB_PATH):
     L.lcs_mlp_workspace_bytes.argtypes = [I64, I32]
     L.lcs_advect_sorted_workspace_bytes.restype = C.c_int64
     L.lcs_advect_sorted_workspace_bytes.argtypes = [P, P]
+    L.lcs_advect_aux_sorted_workspace_bytes.restype = C.c_int64
+    L.lcs_advect_aux_sorted_workspace_bytes.argtypes = [P, P]
     L.lcs_advect_ab_sorted_workspace_bytes.restype = C.c_int64
     L.lcs_advect_ab_sorted_workspace_bytes.argtypes = [P, P]
     L.lcs_ftle_early_workspace_bytes.restype = C.c_int64
@@ -360,6 +363,40 @@ def lcs_advect_aux(frames: DeviceFrames, seeds, delta, t0: float, T: float, dt: 
     sd = seed_grid_desc(seeds)
     _check(_lib.lcs_advect_aux(frames.ref, C.byref(sd), dl, float(t0), float(T), float(dt),
                                _ptr(xa_hi), _ptr(xa_lo), _ptr(flags), _stream_handle(stream)))
+    return xa_hi, xa_lo, flags
+
+
+def lcs_advect_aux_sorted_workspace_bytes(frames: DeviceFrames, seeds) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_advect_aux_sorted_workspace_bytes(frames.ref, C.byref(sd)))
+
+
+def lcs_advect_aux_sorted(frames: DeviceFrames, seeds, delta, t0: float, T: float, dt: float,
+                          segment_steps: int = 50, xa_hi=None, xa_lo=None, flags=None,
+                          workspace=None, want_flags=True, stream=None):
+    """lcs_advect_aux with the auxiliary tracers re-bundled by position between
+    segments (same outputs, bit for bit)."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xa_hi is None:
+        xa_hi = torch.empty((d, 2 * d, ns), dtype=torch.float32, device=dev)
+    if xa_lo is None:
+        xa_lo = torch.empty((d, 2 * d, ns), dtype=torch.float32, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty((2 * d, ns), dtype=torch.uint8, device=dev)
+    _need(xa_hi, torch.float32, (d, 2 * d, ns), "xa_hi")
+    _need(xa_lo, torch.float32, (d, 2 * d, ns), "xa_lo")
+    _need(flags, torch.uint8, (2 * d, ns), "flags")
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_advect_aux_sorted_workspace_bytes(frames, seeds), dev)
+    dl = (C.c_double * 3)(*([float(x) for x in delta] + [0.0] * (3 - len(delta))))
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_aux_sorted(frames.ref, C.byref(sd), dl, float(t0), float(T), float(dt),
+                                      int(segment_steps), _ptr(xa_hi), _ptr(xa_lo), _ptr(flags),
+                                      _ptr(workspace), int(workspace.numel()),
+                                      _stream_handle(stream)))
     return xa_hi, xa_lo, flags
 
 

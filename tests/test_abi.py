@@ -201,6 +201,23 @@ def test_mesh_entry_points_validate():
     L.lcs_mesh_destroy(None)
 
 
+def test_aux_sorted_validates():
+    L = lcs.lib()
+    v, s = _vel(), _seeds()
+    d = (C.c_double * 3)(0.01, 0.01, 0.0)
+    bad = (C.c_double * 3)(0.01, 0.0, 0.0)
+    args = (0.0, 1.0, 0.1, 0, 0x2000, 0x3000, None, 0x4000, 1 << 20, None)
+    assert L.lcs_advect_aux_sorted(C.byref(v), C.byref(s), None, *args) == lcs.LCS_E_ARG
+    assert L.lcs_advect_aux_sorted(C.byref(v), C.byref(s), bad, *args) == lcs.LCS_E_ARG
+    assert L.lcs_advect_aux_sorted(C.byref(v), C.byref(s), d, 0.0, 1.0, 0.1, 0, 0x2000, None,
+                                   None, 0x4000, 1 << 20, None) == lcs.LCS_E_ARG
+    assert L.lcs_advect_aux_sorted(C.byref(v), C.byref(s), d, 0.0, 1.0, 0.1, 0, 0x2000, 0x3000,
+                                   None, 0x4000, 16, None) == lcs.LCS_E_SHAPE   # workspace too small
+    big = _seeds(n=(30, 30, 1), spacing=(0.02, 0.02, 1.0))   # 2*dim auxiliary tracers per seed
+    need = L.lcs_advect_aux_sorted_workspace_bytes(C.byref(v), C.byref(big))
+    assert need > L.lcs_advect_sorted_workspace_bytes(C.byref(v), C.byref(big)) > 0
+
+
 def test_frames_interleave_floats():
     v = _vel(dim=3, n=(5, 4, 3), frames=6)
     L = lcs.lib()
