@@ -558,7 +558,7 @@ def bench_time_resolved(torch, lcs, inputs, reps=2):
                               "seeds": nt, "early_seeds": early, "ms_ftle_early": ms_early}}
 
 
-def bench_surrogate(torch, lcs, keep, n_train=1 << 23, epochs=4):
+def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
     """Learned flow-map surrogate on the random-Fourier field: train on RK4
     displacements over tau = 0.5 (x0 uniform on the torus, t0 in {4, 4.5, ..,
     7.5}), compose 8 windows for the forward T = 4 FTLE of the 512x512x256
