@@ -153,10 +153,29 @@ def cpu_baseline(fs, g, t0, T, dt, target_s):
         oracle.advect_seeds(vel, g, t0, T, dt, idx=idx, threads=threads)
         el = time.perf_counter() - t
         m = m2
+    # one thread as well, the serial baseline the paper compares with
+    m1 = max(64, int(m * 2.0 / max(el * threads, 1e-3)))
+    idx1 = np.sort(rng.choice(g.count, size=m1, replace=False))
+    t = time.perf_counter()
+    oracle.advect_seeds(vel, g, t0, T, dt, idx=idx1, threads=1)
+    el1 = time.perf_counter() - t
     return {"value": m * nsteps / el, "unit": "tracer-RK4-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{m} seeds drawn from the 256^3 grid (seed 0), full T=8 ({nsteps} RK4 steps), "
-                      f"FP64, OpenMP, {el:.1f} s"}
+                      f"FP64, OpenMP, {el:.1f} s",
+            "single_thread_value": m1 * nsteps / el1,
+            "single_thread_sample": f"{m1} seeds, full T, one thread, {el1:.1f} s",
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_batched(torch, lcs, inputs, reps=3, layout="xyz"):
