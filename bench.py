@@ -134,6 +134,44 @@ def profiled_traffic(strategy, layout="soa"):
     return None
 
 
+def profiled_l2_hit_rate(kernel):
+    """L2 (TCC) hit rate of a kernel from the committed rocprofv3 counter
+    summary, or None if there is none or its source changed since."""
+    try:
+        names = sorted(os.listdir(PROFILES))
+    except OSError:
+        return None
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(PROFILES, name)).read().splitlines():
+            if not (line.startswith("{") and "l2_hit_rate" in line):
+                continue
+            rec = json.loads(line)
+            if rec.get("kernel") == kernel and \
+                    source_hash(rec["source_files"]) == rec["source_sha1"]:
+                return rec["l2_hit_rate"]
+    return None
+
+
+def measure_copy_gbs(torch, dev, mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of a plain
+    torch copy of mib MiB: the HBM rate this device reaches in practice."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(fs, g, t0, T, dt, target_s):
     """FP64 oracle on a bounded, deterministic sample of the seeds."""
     import oracle
@@ -740,6 +778,8 @@ def main():
     achieved = BYTES_PER_STEP_3D * tracer_steps / (adv_ms * 1e-3) / 1e9
     nflag = int((flags != 0).sum().item())
     traffic = profiled_traffic(choice, layout)
+    copy_gbs = measure_copy_gbs(torch, dev)
+    seg_kernel = "advect_grid_kernel<3>" if choice == "tiles" else "rebundle_segment_kernel<3, 0>"
     out = {
         "metric": "tracer-RK4-steps/s (whole hot path: advect + C + FTLE), 1 GPU",
         "value": value,
@@ -780,7 +820,13 @@ def main():
                              "L1, L2 and the MALL, so frac exceeds 1; traffic_gbs is the HBM rate "
                              "the counters measured",
                      "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
-                     "units_per_launch": tracer_steps},
+                     "units_per_launch": tracer_steps,
+                     "measured_copy_gbs": copy_gbs,
+                     "frac_of_measured_copy": achieved / copy_gbs,
+                     "traffic_frac_of_measured_copy":
+                         (traffic / (adv_ms * 1e-3) / 1e9 / copy_gbs) if traffic else None,
+                     "l2_hit_rate": profiled_l2_hit_rate(seg_kernel),
+                     "l2_hit_rate_kernel": seg_kernel},
         "cpu_baseline": None,
     }
     del frames, frames_soa, xf, cell, flags, Cm, sfl, lam, sig, ws
