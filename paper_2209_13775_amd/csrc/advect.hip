@@ -327,11 +327,13 @@ __device__ __forceinline__ uint32_t check_point(const VelDev &v, const float *p)
     return 0;
 }
 
-// Stage increments in grid-index units: (dt/2)/h_a and dt/h_a per axis, as
-// two-floats (the physical stage point x + c k sits at s(x) + (c/h) k).
+// Stage increments in grid-index units: (dt/2)/h_a per axis as a two-float
+// (the physical stage point x + c k sits at s(x) + (c/h) k).  The full-step
+// increment dt/h_a is twice it: its two-float is exactly twice this one, and
+// so is the increment formed from it, so only the half-step constants are held
+// (six fewer uniform registers in the step loops).
 struct IdxConsts {
     float hh[3], hl[3];
-    float fh[3], fl[3];
 };
 
 __device__ __forceinline__ IdxConsts idx_consts(const VelDev &v, double dt)
@@ -339,22 +341,23 @@ __device__ __forceinline__ IdxConsts idx_consts(const VelDev &v, double dt)
     IdxConsts c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double h = 0.5 * dt / v.spacing_d[a], f = dt / v.spacing_d[a];
+        const double h = 0.5 * dt / v.spacing_d[a];
         c.hh[a] = (float)h; c.hl[a] = (float)(h - (double)c.hh[a]);
-        c.fh[a] = (float)f; c.fl[a] = (float)(f - (double)c.fh[a]);
     }
     return c;
 }
 
 
-// Grid-index stage point (ph + pl) = (sh + sl) + (ch_a + cl_a) k_a.
-template <int D>
+// Grid-index stage point (ph + pl) = (sh + sl) + (ch_a + cl_a) k_a, or with
+// twice that increment when FULL (scaling by 2 is exact).
+template <int D, bool FULL = false>
 __device__ __forceinline__ void stage_point_s(const float *sh, const float *sl, const float *ch,
                                               const float *cl, const float *k, float *ph, float *pl)
 {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const float inc = fmaf(ch[a], k[a], cl[a] * k[a]);
+        float inc = fmaf(ch[a], k[a], cl[a] * k[a]);
+        if constexpr (FULL) inc = 2.0f * inc;
         two_sum(sh[a], sl[a] + inc, ph[a], pl[a]);
     }
 }
@@ -419,7 +422,7 @@ __device__ uint32_t advect_steps_l(const VelDev &v, float *xh, float *xl, double
 
         velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
         if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
-        stage_point_s<D>(sh, sl, ic.fh, ic.fl, k3, ph, pl);
+        stage_point_s<D, true>(sh, sl, ic.hh, ic.hl, k3, ph, pl);
         if ((fl = check_point_s<D>(v, ph))) break;
 
         velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
@@ -592,7 +595,7 @@ __device__ uint32_t advect_steps_ab_l(const VelDev &v, float *xh, float *xl, flo
             if ((fl = check_point_s<D>(v, ph))) break;
             velocity<D, L>(v, ph, pl, b2, al2, k3, cc);
             if (!finite_vec<D>(k3)) { fl = kNonFinite; break; }
-            stage_point_s<D>(sh, sl, ic.fh, ic.fl, k3, ph, pl);
+            stage_point_s<D, true>(sh, sl, ic.hh, ic.hl, k3, ph, pl);
             if ((fl = check_point_s<D>(v, ph))) break;
             velocity<D, L>(v, ph, pl, b4, al4, k4, cc);
             if (!finite_vec<D>(k4)) { fl = kNonFinite; break; }
