@@ -387,12 +387,17 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
 constexpr int kFT = 128;                  // samples per workgroup
 constexpr int kActStride = kMlpWidth + 8; // BF16 per LDS row (16-byte aligned rows)
 
-// tanh-form GELU written as z * sigmoid(2u) = z / (1 + exp(-2u)), with the
-// hardware reciprocal (the result is rounded to BF16 next)
+// tanh-form GELU written as z * sigmoid(2u) = z / (1 + exp(-2u)) with
+// u = sqrt(2/pi) (z + 0.044715 z^3), and -2u log2(e) folded into
+// z (A + B z^2): one multiply, one FMA and one multiply before the base-2
+// exponential, then the hardware reciprocal (the result is rounded to BF16
+// next; the folding moves it by at most ~5e-7 absolute)
 __device__ __forceinline__ float gelu_fast(float z)
 {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+    constexpr float A = -2.3022082f;    // -2 log2(e) sqrt(2/pi)
+    constexpr float B = -0.10294324f;   // A * 0.044715
+    const float w = fmaf(B, z * z, A);
+    return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * w));
 }
 
 // Four floats rounded to BF16 (to nearest even) and packed in 8 bytes, two
@@ -447,39 +452,59 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             // the transposed product out^T[n][m] = sum_k W^T[n][k] act[m][k]: weights
             // as the A operand, activations as B, so that a lane's four results
             // are four consecutive output columns n of one sample m
+            // the accumulators start from the bias of their output columns
             f32x4 acc[8][4];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 4; ++j) {
+                const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+                const f32x4 b4 = (f32x4){bias[n0], bias[n0 + 1], bias[n0 + 2], bias[n0 + 3]};
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+                for (int i = 0; i < 8; ++i) acc[i][j] = b4;
+            }
             const int ko = 8 * (lane / 16);
-            for (int kk = 0; kk < K; kk += 32) {
-                bf16x8 wfr[4];
+            // weight fragments of K-slice kk (32 wide) for this wave's 64 columns
+            auto load_w = [&](int kk, bf16x8 *w) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int n = wave * 64 + 16 * j + lane % 16;
-                    wfr[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
+                    w[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
                 }
+            };
+            auto mfma_slice = [&](int kk, const bf16x8 *w) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const bf16x8 xfr = *reinterpret_cast<const bf16x8 *>(
                         &act[(16 * i + lane % 16) * kActStride + kk + ko]);
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfr[j], xfr, acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], xfr, acc[i][j], 0, 0, 0);
                 }
+            };
+            // two fragment buffers: the next slice's weights are in flight from L2
+            // while the current slice's 32 products run (K is a multiple of 64)
+            static_assert(kMlpFeat % 64 == 0 && kMlpWidth % 64 == 0, "K must be a multiple of 64");
+            bf16x8 wa[4], wb[4];
+            load_w(0, wa);
+            // (the scheduling barriers keep each prefetch ahead of the products
+            // that overlap it)
+            for (int kk = 0; kk < K; kk += 64) {
+                load_w(kk + 32, wb);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_slice(kk, wa);
+                if (kk + 64 < K) load_w(kk + 64, wa);
+                __builtin_amdgcn_sched_barrier(0);
+                mfma_slice(kk + 32, wb);
             }
             __syncthreads();   // every wave has read this layer's input
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
-                const float b0 = bias[n0], b1 = bias[n0 + 1], b2 = bias[n0 + 2], b3 = bias[n0 + 3];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int m = 16 * i + lane % 16;
                     *reinterpret_cast<uint2 *>(&act[m * kActStride + n0]) =
-                        pack_bf16x4(gelu_fast(acc[i][j][0] + b0), gelu_fast(acc[i][j][1] + b1),
-                                    gelu_fast(acc[i][j][2] + b2), gelu_fast(acc[i][j][3] + b3));
+                        pack_bf16x4(gelu_fast(acc[i][j][0]), gelu_fast(acc[i][j][1]),
+                                    gelu_fast(acc[i][j][2]), gelu_fast(acc[i][j][3]));
                 }
             }
             __syncthreads();
