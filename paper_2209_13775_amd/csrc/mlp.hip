@@ -415,6 +415,8 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t act[kFT * kActStride];
     __shared__ float xs[3][kFT];
+    __shared__ float yp[3][kFT];
+    static_assert(2 * kFT == 256 && kMlpWidth == 256, "the head splits 256 inputs over 2 x 128 threads");
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const long long s0 = (long long)blockIdx.x * kFT;
     const SeedTiling &g = A.g;
@@ -439,10 +441,13 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             const float v2 = (xs[2][m] - P.in_shift[2]) * P.in_scale[2];
             const float v3 = (tk - P.in_shift[3]) * P.in_scale[3];
             const float *b = P.freq + 4 * f;
-            float sn, cs;
-            sincospif(2.0f * (b[0] * v0 + b[1] * v1 + b[2] * v2 + b[3] * v3), &sn, &cs);
-            act[m * kActStride + f] = f2bf(cs);
-            act[m * kActStride + kMlpFreq + f] = f2bf(sn);
+            // B_f . v in revolutions, reduced exactly to [-1/2, 1/2], then the
+            // hardware sine and cosine of 2 pi r (the features are rounded to
+            // BF16, far coarser than their error)
+            const float rev = b[0] * v0 + b[1] * v1 + b[2] * v2 + b[3] * v3;
+            const float r = rev - rintf(rev);
+            act[m * kActStride + f] = f2bf(__builtin_amdgcn_cosf(r));
+            act[m * kActStride + kMlpFreq + f] = f2bf(__builtin_amdgcn_sinf(r));
         }
         __syncthreads();
         for (int l = 0; l < kMlpHidden; ++l) {
@@ -509,24 +514,37 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             }
             __syncthreads();
         }
-        // head: two lanes per sample, each summing half of the 256 inputs
+        // head: two threads per sample, each summing half of the 256 inputs; the
+        // half is uniform over a wave (waves 0-1 the first, 2-3 the second), so
+        // the head weights are scalar loads, and the second half's partial sums
+        // reach the first through LDS
         {
-            const int m = tid / 2, h = tid % 2;
+            const int m = tid % kFT;
+            const int h = __builtin_amdgcn_readfirstlane(tid / kFT);
             float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
-            for (int q = h * 128; q < h * 128 + 128; ++q) {
-                const float x = bf2f(act[m * kActStride + q]);
-                y0 += x * Wh[3 * q];
-                y1 += x * Wh[3 * q + 1];
-                y2 += x * Wh[3 * q + 2];
+            for (int q0 = h * 128; q0 < h * 128 + 128; q0 += 8) {
+                // eight activations in one 16-byte LDS read (rows are 16-byte aligned)
+                const uint4 a8 = *reinterpret_cast<const uint4 *>(&act[m * kActStride + q0]);
+                const uint32_t w2[4] = {a8.x, a8.y, a8.z, a8.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float x = bf2f((uint16_t)(w2[e / 2] >> (16 * (e % 2))));
+                    const int q = q0 + e;
+                    y0 += x * Wh[3 * q];
+                    y1 += x * Wh[3 * q + 1];
+                    y2 += x * Wh[3 * q + 2];
+                }
             }
-            y0 += __shfl_xor(y0, 1, 64);
-            y1 += __shfl_xor(y1, 1, 64);
-            y2 += __shfl_xor(y2, 1, 64);
+            if (h == 1) {
+                yp[0][m] = y0;
+                yp[1][m] = y1;
+                yp[2][m] = y2;
+            }
             __syncthreads();   // all head reads of act done before the next window's features
             if (h == 0) {
-                xs[0][m] += P.out_scale * (y0 + bh[0]);
-                xs[1][m] += P.out_scale * (y1 + bh[1]);
-                xs[2][m] += P.out_scale * (y2 + bh[2]);
+                xs[0][m] += P.out_scale * ((y0 + yp[0][m]) + bh[0]);
+                xs[1][m] += P.out_scale * ((y1 + yp[1][m]) + bh[1]);
+                xs[2][m] += P.out_scale * ((y2 + yp[2][m]) + bh[2]);
             }
             __syncthreads();
         }
