@@ -134,9 +134,10 @@ def profiled_traffic(strategy, layout="soa"):
     return None
 
 
-def profiled_l2_hit_rate(kernel):
-    """L2 (TCC) hit rate of a kernel from the committed rocprofv3 counter
-    summary, or None if there is none or its source changed since."""
+def profiled_counter(kernel, field):
+    """A figure (l2_hit_rate, ta_busy, td_busy, ...) of a kernel from the
+    committed rocprofv3 counter summary, or None if there is none or its
+    source changed since."""
     try:
         names = sorted(os.listdir(PROFILES))
     except OSError:
@@ -145,12 +146,12 @@ def profiled_l2_hit_rate(kernel):
         if not name.endswith(".md"):
             continue
         for line in open(os.path.join(PROFILES, name)).read().splitlines():
-            if not (line.startswith("{") and "l2_hit_rate" in line):
+            if not (line.startswith("{") and f'"{field}"' in line):
                 continue
             rec = json.loads(line)
             if rec.get("kernel") == kernel and \
                     source_hash(rec["source_files"]) == rec["source_sha1"]:
-                return rec["l2_hit_rate"]
+                return rec[field]
     return None
 
 
@@ -825,8 +826,13 @@ def main():
                      "frac_of_measured_copy": achieved / copy_gbs,
                      "traffic_frac_of_measured_copy":
                          (traffic / (adv_ms * 1e-3) / 1e9 / copy_gbs) if traffic else None,
-                     "l2_hit_rate": profiled_l2_hit_rate(seg_kernel),
-                     "l2_hit_rate_kernel": seg_kernel},
+                     "l2_hit_rate": profiled_counter(seg_kernel, "l2_hit_rate"),
+                     "ta_busy": profiled_counter(seg_kernel, "ta_busy"),
+                     "td_busy": profiled_counter(seg_kernel, "td_busy"),
+                     "counters_kernel": seg_kernel,
+                     "binding_resource": "texture address / data units of the vector-memory "
+                                         "path (ta_busy, td_busy: fraction of the kernel's "
+                                         "cycles, rocprofv3 TA_TA_BUSY_sum / TD_TD_BUSY_sum)"},
         "cpu_baseline": None,
     }
     del frames, frames_soa, xf, cell, flags, Cm, sfl, lam, sig, ws

@@ -50,7 +50,7 @@ typedef enum {
     LCS_E_SEED_DOMAIN = -4,  /* a seed lies outside a non-periodic velocity axis   */
     LCS_E_STEP = -5,         /* T/dt not integral, sign(dt) != sign(T), or T == 0  */
     LCS_E_HIP = -6,          /* HIP launch or runtime failure                      */
-    LCS_E_UNSUPPORTED = -7   /* valid request this build does not handle           */
+    LCS_E_UNSUPPORTED = -7   /* valid request the library does not handle         */
 } lcs_status;
 
 /* Per-tracer flag bits (uint8). */
