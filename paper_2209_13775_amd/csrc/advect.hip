@@ -1038,33 +1038,38 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
     (void)run_atomic_inc(A.sk.counts, key);
 }
 
-// Steps [n_begin, n_end) for every tracer slot; then either the outputs (last
-// segment) or the state in place plus its new key and the histogram.
+// Steps [n_begin, n_end) for every tracer slot p of the sorted order, whose
+// state is read from slot perm[p] of the previous order; then either the
+// outputs (last segment) or the state at slot p of the other buffer plus its
+// new key and the histogram.
 template <int D, int S>
 __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_segment_kernel(SegmentArgs A)
 {
     const int nblocks = (int)gridDim.x;
     const long long p = (long long)xcd_remap((int)blockIdx.x, nblocks) * blockDim.x + threadIdx.x;
     if (p >= A.n) return;
+    const long long r = A.sk.perm[p];
+    if (r >= A.n) return;   // cannot happen: the permutation is a bijection of [0, n)
     float xh[3] = {0, 0, 0}, xl[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        xh[a] = A.st.xh[a][p];
-        xl[a] = A.st.xl[a][p];
+        xh[a] = A.st.xh[a][r];
+        xl[a] = A.st.xl[a][r];
     }
-    uint32_t fl = A.st.flag[p];
+    uint32_t fl = A.st.flag[r];
+    const int sid = A.st.idx[r];
     float hist[3][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
     if constexpr (S > 0) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int a = 0; a < D; ++a) hist[j][a] = A.st.hist[j * D + a][p];
+            for (int a = 0; a < D; ++a) hist[j][a] = A.st.hist[j * D + a][r];
         if (!fl) fl = advect_steps_ab<D, S>(A.v, xh, xl, hist, A.t0, A.dt, A.n_begin, A.n_end);
     } else {
         if (!fl) fl = advect_steps<D>(A.v, xh, xl, A.t0, A.dt, A.n_begin, A.n_end);
     }
     if (A.last) {
-        const long long s = A.st.idx[p];
+        const long long s = sid;
         float x[3] = {0, 0, 0};
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -1082,15 +1087,16 @@ __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        A.st.xh[a][p] = xh[a];
-        A.st.xl[a][p] = xl[a];
+        A.out.xh[a][p] = xh[a];
+        A.out.xl[a][p] = xl[a];
     }
-    A.st.flag[p] = (uint8_t)fl;
+    A.out.flag[p] = (uint8_t)fl;
+    A.out.idx[p] = sid;
     if constexpr (S > 0) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int a = 0; a < D; ++a) A.st.hist[j * D + a][p] = hist[j][a];
+            for (int a = 0; a < D; ++a) A.out.hist[j * D + a][p] = hist[j][a];
     }
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
@@ -1158,25 +1164,17 @@ __global__ __launch_bounds__(256) void scan_add_kernel(uint32_t *data, long long
     if (i < n) data[i] += sums[i / kScanBlock];
 }
 
-// Slot p moves to offset[key] + (its rank among the bin's arrivals).
-template <int D>
-__global__ __launch_bounds__(256) void scatter_kernel(SegmentArgs A, TracerState dst)
+// Slot p goes to sorted slot q = offset[key] + (its rank among the bin's
+// arrivals): perm[q] = p.  The next segment reads the state through perm, so
+// only the 4-byte slot index moves here, not the tracer state.
+__global__ __launch_bounds__(256) void permute_kernel(SortKeys sk, long long n)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= A.n) return;
-    const uint32_t key = A.sk.keys[p];
-    const long long q = run_atomic_inc(A.sk.counts, key);
-    if (q >= A.n) return;   // cannot happen when the histogram matches the keys
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        dst.xh[a][q] = A.st.xh[a][p];
-        dst.xl[a][q] = A.st.xl[a][p];
-    }
-    dst.idx[q] = A.st.idx[p];
-    dst.flag[q] = A.st.flag[p];
-    if (A.st.hist[0])
-#pragma unroll
-        for (int r = 0; r < 3 * D; ++r) dst.hist[r][q] = A.st.hist[r][p];
+    if (p >= n) return;
+    const uint32_t key = sk.keys[p];
+    const long long q = run_atomic_inc(sk.counts, key);
+    if (q >= n) return;   // cannot happen when the histogram matches the keys
+    sk.perm[q] = (uint32_t)p;
 }
 
 }  // namespace
@@ -1232,16 +1230,15 @@ hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// counts (histogram) -> exclusive offsets -> scatter into dst; then the counts
-// are cleared for the next histogram.
-hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s)
+// counts (histogram) -> exclusive offsets -> the permutation of the slots;
+// then the counts are cleared for the next histogram.
+hipError_t launch_rebundle_sort(const SegmentArgs &a, hipStream_t s)
 {
     const long long nk = a.sk.n_keys;
     const hipError_t e = launch_exclusive_scan_u32(a.sk.counts, nk, a.sk.block_sums, s);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
-    if (dim == 2) hipLaunchKernelGGL(scatter_kernel<2>, grid, block, 0, s, a, dst);
-    else hipLaunchKernelGGL(scatter_kernel<3>, grid, block, 0, s, a, dst);
+    hipLaunchKernelGGL(permute_kernel, grid, block, 0, s, a.sk, a.n);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s,
                        a.sk.counts, nk, 0u);
     return hipGetLastError();

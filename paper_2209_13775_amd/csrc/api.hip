@@ -792,6 +792,7 @@ SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, l
         }
     }
     L.sk.keys = reinterpret_cast<uint32_t *>(take(4 * n));
+    L.sk.perm = reinterpret_cast<uint32_t *>(take(4 * n));
     L.sk.counts = reinterpret_cast<uint32_t *>(take(4 * nk));
     L.sk.block_sums = reinterpret_cast<uint32_t *>(take(4 * ((nk + 1023) / 1024 + 1)));
     L.bytes = off;
@@ -880,18 +881,22 @@ lcs_status advect_sorted_impl(const lcs_velocity_t *vel, const lcs_seed_grid_t *
         A.ns_seeds = ns;
         for (int a = 0; a < vel->dim; ++a) A.delta[a] = delta[a];
     }
+    // the state lives in bufs[cur] in the order of the last histogram; a sort
+    // builds the permutation, and the next segment reads bufs[cur] through it
+    // and writes bufs[1 - cur] in sorted order
     hipError_t e = lcs::launch_fill_u32(L.sk.counts, L.sk.n_keys, 0u, s);
     if (e == hipSuccess) e = lcs::launch_rebundle_init(vel->dim, A, s);
-    if (e == hipSuccess) e = lcs::launch_rebundle_sort(vel->dim, A, bufs[1], s);
-    int cur = 1;
+    if (e == hipSuccess) e = lcs::launch_rebundle_sort(A, s);
+    int cur = 0;
     for (int n0 = 0; n0 < nsteps && e == hipSuccess; n0 += seg) {
         A.st = bufs[cur];
+        A.out = bufs[1 - cur];
         A.n_begin = n0;
         A.n_end = (nsteps - n0 < seg) ? nsteps : n0 + seg;
         A.last = (A.n_end == nsteps) ? 1 : 0;
         e = lcs::launch_rebundle_segment(vel->dim, A, s);
         if (!A.last && e == hipSuccess) {
-            e = lcs::launch_rebundle_sort(vel->dim, A, bufs[1 - cur], s);
+            e = lcs::launch_rebundle_sort(A, s);
             cur = 1 - cur;
         }
     }

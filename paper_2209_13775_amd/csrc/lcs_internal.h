@@ -314,6 +314,7 @@ struct SortKeys {
     uint32_t *keys;                   // [N]
     uint32_t *counts;                 // [n_keys]; turned into offsets by the scan
     uint32_t *block_sums;             // scan scratch
+    uint32_t *perm;                   // [N]: sorted slot -> slot of the state it reads
     long long n_keys;
 };
 
@@ -323,7 +324,8 @@ struct SegmentArgs {
     double t0, dt;
     int n_begin, n_end;
     long long n;                      // tracers
-    TracerState st;
+    TracerState st;                   // state read (slot sk.perm[p] for slot p)
+    TracerState out;                  // state written (slot p)
     SortKeys sk;
     int last;                         // 1: write outputs instead of state + keys
     int order;                        // 0: RK4; 2..4: Adams-Bashforth
@@ -338,7 +340,7 @@ struct SegmentArgs {
 
 hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s);
 hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s);
-hipError_t launch_rebundle_sort(int dim, const SegmentArgs &a, const TracerState &dst, hipStream_t s);
+hipError_t launch_rebundle_sort(const SegmentArgs &a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
 long long exclusive_scan_sums_needed(long long n);
 hipError_t launch_exclusive_scan_u32(uint32_t *data, long long n, uint32_t *block_sums,
