@@ -751,12 +751,20 @@ SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, l
 {
     SortedLayout L;
     memset(&L, 0, sizeof(L));
+    // bin edge in cells: the finest whose Morton keys fit in kMaxBinKeyBits bits
+    long long bc = 1;
+    for (;;) {
+        int key_bits = 0;
+        for (int a = 0; a < vel->dim; ++a) key_bits += ceil_log2((int)((vel->n[a] + bc - 1) / bc));
+        if (key_bits <= lcs::kMaxBinKeyBits || bc >= (1LL << 20)) break;
+        bc *= 2;
+    }
     long long nk = 1;
     for (int a = 0; a < 3; ++a) {
         if (a < vel->dim) {
-            L.sk.nb[a] = (int)((vel->n[a] + lcs::kBinCells - 1) / lcs::kBinCells);
+            L.sk.nb[a] = (int)((vel->n[a] + bc - 1) / bc);
             L.sk.bits[a] = ceil_log2(L.sk.nb[a]);
-            L.sk.inv_bin[a] = (float)(1.0 / (lcs::kBinCells * vel->spacing[a]));
+            L.sk.inv_bin[a] = (float)(1.0 / ((double)bc * vel->spacing[a]));
             L.sk.origin[a] = (float)vel->origin[a];
         } else {
             L.sk.nb[a] = 1;

@@ -295,7 +295,8 @@ hipError_t launch_sub(const float *a, const float *b, long long n, float *out, h
 // velocity cells) they occupy, so that the lanes of a wave gather from one
 // compact region again.  State is carried in HBM between segments.
 // ---------------------------------------------------------------------------
-constexpr int kBinCells = 2;          // velocity cells per sort bin along each axis
+constexpr int kMaxBinKeyBits = 24;   // sort bins are one cell wide while their Morton keys fit
+                                     // in this many bits (else 2, 4, ... cells wide)
 
 struct TracerState {
     float *xh[3];
