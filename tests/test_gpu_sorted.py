@@ -66,3 +66,16 @@ def test_sorted_equals_plain_full_size_abc(lcs):
     b = lcs.lcs_advect_sorted(frames, g, 0.0, 8.0, 0.02, segment_steps=50)
     lcs.lcs_sync_status()
     assert _same(a, b)
+
+
+def test_sorted_equals_plain_with_coarse_bins(lcs):
+    # 8193 x 2049 nodes need 14 + 12 Morton bits for one-cell bins, more than
+    # the 24 the sort allows, so its bins are two cells wide here
+    _say("case: sorted 2D on 8193 x 2049 nodes (two-cell sort bins)")
+    fs = inputs.double_gyre_frames(nx=8193, ny=2049, n_frames=3, dt_frame=5.0)
+    g = inputs.linspace_seeds(2, (300, 150), (0.0, 0.0), (2.0, 1.0))
+    frames = lcs.DeviceFrames(fs)
+    a = lcs.lcs_advect(frames, g, 0.0, 10.0, 0.05)
+    b = lcs.lcs_advect_sorted(frames, g, 0.0, 10.0, 0.05, segment_steps=37)
+    lcs.lcs_sync_status()
+    assert _same(a, b)
