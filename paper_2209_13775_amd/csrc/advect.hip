@@ -787,25 +787,27 @@ __global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const f
     if (S == 4) o[3] = 0.0f;
 }
 
-// Time-paired records: one thread per record of pair p (frames f_first + p and
-// f_first + p + 1) on the grid with n0 + 1 nodes per row, the last repeating
-// node 0 of the row.
+// Time-paired records: one thread per record q of pair p = pair0 + blockIdx.y
+// (frames f_first + p and f_first + p + 1) on the grid with n0 + 1 nodes per
+// row, the last repeating node 0 of the row.  The records of one pair number
+// fewer than 2^32 (the interleaved array is limited to 4 GiB), so the index
+// arithmetic within a pair is 32-bit.
 __global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *u0, const float *u1,
                                                                const float *u2, int n0, int n1,
                                                                int n2, long long f_first,
-                                                               long long n_rec, float *out)
+                                                               long long pair0, float *out)
 {
-    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rec) return;
-    const long long per_pair = (long long)(n0 + 1) * n1 * n2;
-    const long long p = r / per_pair;
-    const long long q = r - p * per_pair;
-    const long long row = q / (n0 + 1);            // j + n1*k
-    const int i = (int)(q - row * (n0 + 1));
+    const uint32_t w = (uint32_t)n0 + 1u;
+    const uint32_t per_pair = w * (uint32_t)n1 * (uint32_t)n2;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= per_pair) return;
+    const long long p = pair0 + (long long)blockIdx.y;
+    const uint32_t row = q / w;                    // j + n1*k
+    const uint32_t i = q - row * w;
     const long long nodes = (long long)n0 * n1 * n2;
-    const long long node = row * n0 + (i == n0 ? 0 : i);
+    const long long node = (long long)row * n0 + (i == (uint32_t)n0 ? 0u : i);
     const long long a = (f_first + p) * nodes + node, b = a + nodes;
-    float2 *o = reinterpret_cast<float2 *>(out + r * 6);
+    float2 *o = reinterpret_cast<float2 *>(out + (p * (long long)per_pair + q) * 6);
     o[0] = make_float2(u0[a], u1[a]);
     o[1] = make_float2(u2[a], u0[b]);
     o[2] = make_float2(u1[b], u2[b]);
@@ -1327,9 +1329,16 @@ hipError_t launch_interleave(int dim, int S, const float *const *u, long long no
 hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_count, int f_first,
                                   float *out, hipStream_t s)
 {
-    const long long n_rec = (long long)(f_count - 1) * (n[0] + 1) * n[1] * n[2];
-    hipLaunchKernelGGL(interleave_tpair_kernel, dim3((unsigned)((n_rec + 255) / 256)), dim3(256), 0,
-                       s, u[0], u[1], u[2], n[0], n[1], n[2], (long long)f_first, n_rec, out);
+    const long long per_pair = (long long)(n[0] + 1) * n[1] * n[2];
+    const long long pairs = f_count - 1;
+    if (per_pair <= 0 || pairs <= 0) return hipSuccess;
+    if (per_pair >= (1LL << 32)) return hipErrorInvalidValue;
+    const unsigned bx = (unsigned)((per_pair + 255) / 256);
+    for (long long p0 = 0; p0 < pairs; p0 += 65535) {   // grid y covers up to 65535 pairs
+        const unsigned by = (unsigned)(pairs - p0 < 65535 ? pairs - p0 : 65535);
+        hipLaunchKernelGGL(interleave_tpair_kernel, dim3(bx, by), dim3(256), 0, s, u[0], u[1], u[2],
+                           n[0], n[1], n[2], (long long)f_first, p0, out);
+    }
     return hipGetLastError();
 }
 
