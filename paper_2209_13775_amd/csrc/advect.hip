@@ -790,7 +790,7 @@ __global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const f
 // Time-paired records: one thread per record q of pair p = pair0 + blockIdx.y
 // (frames f_first + p and f_first + p + 1) on the grid with n0 + 1 nodes per
 // row, the last repeating node 0 of the row.  The records of one pair number
-// fewer than 2^32 (the interleaved array is limited to 4 GiB), so the index
+// fewer than 2^28 (a frame-pair block is limited to 4 GiB), so the index
 // arithmetic within a pair is 32-bit.
 __global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *u0, const float *u1,
                                                                const float *u2, int n0, int n1,
