@@ -234,6 +234,28 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restr
     out[i] = s;
 }
 
+// The same sum for short outputs with many chunks (bias and head gradients):
+// one block per output, thread t summing chunks t, t + 256, ... in order, then
+// a fixed pairwise tree in LDS (deterministic, and 256-way parallel where the
+// per-output loop above would run nchunk dependent loads in one thread).
+__global__ __launch_bounds__(256) void reduce_chunks_tree_kernel(const float *__restrict__ part,
+                                                                 int nchunk, long long len,
+                                                                 float *__restrict__ out)
+{
+    __shared__ float sh[256];
+    const long long i = blockIdx.x;
+    const int t = threadIdx.x;
+    float s = 0.0f;
+    for (int c = t; c < nchunk; c += 256) s += part[(long long)c * len + i];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    if (t == 0) out[i] = sh[0];
+}
+
 // ---------------------------------------------------------------------------
 // Head: dx[c][m] = out_scale * (sum_k H4[m][k] Wh[k][c] + bh[c]), FP32.
 // ---------------------------------------------------------------------------
@@ -610,8 +632,13 @@ hipError_t launch_colsum(const uint16_t *D, long long M, int N, long long chunk,
 
 hipError_t launch_reduce_chunks(const float *part, int nchunk, long long len, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
-                       part, nchunk, len, out);
+    if (len <= 0) return hipSuccess;
+    if (len <= 4096 && nchunk > 64)
+        hipLaunchKernelGGL(reduce_chunks_tree_kernel, dim3((unsigned)len), dim3(256), 0, s, part,
+                           nchunk, len, out);
+    else
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
+                           part, nchunk, len, out);
     return hipGetLastError();
 }
 
