@@ -46,23 +46,25 @@ __device__ __forceinline__ float gelu_prime(float z)
 // ---------------------------------------------------------------------------
 // Fourier features: H0[m][f] = cos(2 pi B_f . v), H0[m][64+f] = sin(...)
 // ---------------------------------------------------------------------------
+// one thread per (sample m, frequency f), f fastest, so that the BF16 stores of
+// a wave fill consecutive bytes of the sample rows
 __global__ __launch_bounds__(256) void features_kernel(MlpDev P, const float *__restrict__ xt,
                                                        long long M, uint16_t *__restrict__ H0)
 {
-    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * kMlpFreq) return;
+    const long long m = idx / kMlpFreq;
+    const int f = (int)(idx - m * kMlpFreq);
     float v[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) v[a] = (xt[a * M + m] - P.in_shift[a]) * P.in_scale[a];
     uint16_t *row = H0 + m * kMlpFeat;
-    for (int f = 0; f < kMlpFreq; ++f) {
-        const float *b = P.freq + 4 * f;
-        const float ph = b[0] * v[0] + b[1] * v[1] + b[2] * v[2] + b[3] * v[3];
-        float s, c;
-        sincospif(2.0f * ph, &s, &c);
-        row[f] = f2bf(c);
-        row[kMlpFreq + f] = f2bf(s);
-    }
+    const float *b = P.freq + 4 * f;
+    const float ph = b[0] * v[0] + b[1] * v[1] + b[2] * v[2] + b[3] * v[3];
+    float s, c;
+    sincospif(2.0f * ph, &s, &c);
+    row[f] = f2bf(c);
+    row[kMlpFreq + f] = f2bf(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,8 +605,8 @@ hipError_t launch_sub(const float *a, const float *b, long long n, float *out, h
 // ---------------------------------------------------------------------------
 hipError_t launch_features(const MlpDev &P, const float *xt, long long M, uint16_t *H0, hipStream_t s)
 {
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, P, xt,
-                       M, H0);
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((M * kMlpFreq + 255) / 256)), dim3(256), 0, s,
+                       P, xt, M, H0);
     return hipGetLastError();
 }
 
