@@ -247,3 +247,24 @@ def test_frames_interleave_validates():
     v.layout = lcs.LCS_LAYOUT_XYZ
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 2, 0x1000, C.byref(out_desc),
                                    None) == lcs.LCS_E_ARG          # source must be SoA
+
+
+def test_sorted_workspace_follows_the_bin_rule():
+    """Sort bins are one cell wide while their Morton keys fit in 24 bits, else
+    two cells: a 4097 x 4096 grid (25 bits at one cell, 23 at two) needs the
+    same bin histogram as a 2048 x 4096 grid and half that of 4096 x 4096."""
+    L = lcs.lib()
+    s = _seeds()
+
+    def ws(n):
+        v = _vel(n=n)
+        return L.lcs_advect_sorted_workspace_bytes(C.byref(v), C.byref(s))
+
+    def hist_bytes(key_bits):   # counts + scan block sums, each rounded up to 256 B
+        nk = 1 << key_bits
+        return 4 * nk + (4 * (nk // 1024 + 1) + 255) // 256 * 256
+
+    a, b, c = ws((4096, 4096, 1)), ws((4097, 4096, 1)), ws((2048, 4096, 1))
+    assert a > 0 and b > 0 and c > 0
+    assert b == c
+    assert a - c == hist_bytes(24) - hist_bytes(23)
