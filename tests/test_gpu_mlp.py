@@ -101,7 +101,7 @@ def test_forward_matches_reference(lcs, torch, n):
     assert err <= 1e-2
 
 
-@pytest.mark.parametrize("n", [6000, 300])
+@pytest.mark.parametrize("n", [6000, 300, 9000])   # 9000: over 64 bias chunks (tree reduction)
 def test_backward_matches_reference(lcs, torch, n):
     _say(f"case: mlp backward batch {n}")
     params, freq = _model(3)
