@@ -133,6 +133,15 @@ lcs_status check_seed_domain(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
         const bool vper = (vel->periodic_mask >> a) & 1u;
         const bool sper = (seeds->periodic_mask >> a) & 1u;
         if (sper && !vper) return lcs::set_error(LCS_E_ARG, "seed axis %d periodic but velocity axis is not", a);
+        if (sper) {
+            // the gradient shifts a seam neighbour by the seed period, which is
+            // right only when it is the velocity period
+            const double Lv = (double)vel->n[a] * vel->spacing[a];
+            const double Ls = (double)seeds->n[a] * seeds->spacing[a];
+            if (!(fabs(Ls - Lv) <= 1e-9 * Lv))
+                return lcs::set_error(LCS_E_ARG, "periodic seed axis %d has period %g, the velocity "
+                                      "period is %g", a, Ls, Lv);
+        }
         if (vper) continue;
         const double lo = vel->origin[a];
         const double hi = vel->origin[a] + (double)(vel->n[a] - 1) * vel->spacing[a];

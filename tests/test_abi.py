@@ -62,6 +62,8 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("time_range", lcs.LCS_E_TIME_RANGE),
     ("seed_outside", lcs.LCS_E_SEED_DOMAIN),
     ("periodic_seed_on_closed_axis", lcs.LCS_E_ARG),
+    ("periodic_seed_partial_period", lcs.LCS_E_ARG),
+    ("periodic_seed_full_period_passes", lcs.LCS_E_TIME_RANGE),
     ("bad_layout", lcs.LCS_E_ARG),
     ("xyzw_in_2d", lcs.LCS_E_ARG),
     ("misaligned_interleaved", lcs.LCS_E_ARG),
@@ -96,6 +98,12 @@ def test_advect_validation(case, expect):
         s.origin[0] = 0.7  # 0.7 + 2*0.2 = 1.1 > 4*0.25
     elif case == "periodic_seed_on_closed_axis":
         s.periodic_mask = 1
+    elif case in ("periodic_seed_partial_period", "periodic_seed_full_period_passes"):
+        # velocity period 5 x 0.25 = 1.25; seeds 3 x 0.2 = 0.6 cover part of it
+        v.periodic_mask = s.periodic_mask = 1
+        if case.endswith("passes"):
+            s.spacing[0] = 1.25 / 3        # full period: validation goes on to the
+            T = 2.5                        # time range, which fails instead
     elif case == "bad_layout":
         v.layout = 7
     elif case == "xyzw_in_2d":

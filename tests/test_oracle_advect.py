@@ -170,3 +170,36 @@ def test_time_span_rule(orc):
     xf, _, flags = orc.advect_points(vel, x0, t0, 0.5, 0.1)
     np.testing.assert_array_equal(flags, [0, 8, 0, 8])
     np.testing.assert_allclose(xf[0], [0.25, 0.2, 0.25, 0.2], atol=1e-14)
+
+
+def test_trajectory_recording_closed_form_and_freeze(orc):
+    # positions after every step on the steady linear saddle: the interpolant is
+    # exact and RK4 multiplies x by R(lam dt) and y by R(-lam dt) per step, so
+    # step n holds R^n x0 (the e_S(t) curves of the FP32 / FP64 comparison read
+    # these positions)
+    lam, dt, T = 0.5, 0.05, 2.0
+    N = int(round(T / dt))
+    R = lambda z: 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    vel = orc.Velocity(inputs.saddle_frames(lam=lam))
+    x0 = np.array([[0.3, -0.2, 0.05], [0.1, 0.4, -0.35]])
+    traj, flags = orc.advect_points_traj(vel, x0, 0.0, T, dt)
+    assert traj.shape == (N, 2, 3) and not flags.any()
+    n = np.arange(1, N + 1)[:, None]
+    np.testing.assert_allclose(traj[:, 0], x0[0] * R(lam * dt) ** n, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(traj[:, 1], x0[1] * R(-lam * dt) ** n, rtol=1e-13, atol=1e-15)
+    # a tracer that leaves: the x-growth R(lam dt)^n carries x = 2.9 past the
+    # wall at 3 in the first step whose end point (or stage) is outside; from
+    # then on every recorded position is the frozen one
+    x1 = np.array([[2.9], [0.0]])
+    traj, flags = orc.advect_points_traj(vel, x1, 0.0, T, dt)
+    assert flags[0] == 1
+    n_exit = next(k for k in range(1, N + 1) if 2.9 * R(lam * dt) ** k > 3.0)
+    # steps before the exit step are the closed form; the exit step and all
+    # later ones repeat the last accepted position (stage points of the exit
+    # step may leave first, so allow it to come one step earlier)
+    frozen = traj[-1, 0, 0]
+    first_frozen = int(np.argmax(traj[:, 0, 0] == frozen))
+    assert n_exit - 2 <= first_frozen <= n_exit - 1
+    np.testing.assert_allclose(traj[:first_frozen, 0, 0],
+                               2.9 * R(lam * dt) ** np.arange(1, first_frozen + 1), rtol=1e-13)
+    assert np.all(traj[first_frozen:, 0, 0] == frozen)

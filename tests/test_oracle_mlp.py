@@ -93,3 +93,59 @@ def test_bf16_rounding_matches_torch():
 
 def test_parameter_count():
     assert M.N_PARAMS == 128 * 256 + 256 + 3 * (256 * 256 + 256) + 256 * 3 + 3
+
+
+def _torch_network(params, freq, shift, scale, out_scale):
+    """The surrogate written a second time with torch modules (FP64): Linear
+    layers (weight stored [out][in]), the tanh-form GELU of torch, cos/sin
+    features of 2 pi B v.  Shares nothing with mlp_ref but the flat layout."""
+    import torch
+    import torch.nn.functional as F
+    p = torch.tensor(np.asarray(params, np.float64), dtype=torch.float64, requires_grad=True)
+    B = torch.tensor(np.asarray(freq, np.float64))
+    sh = torch.tensor(np.asarray(shift, np.float64))
+    sc = torch.tensor(np.asarray(scale, np.float64))
+    widths = [(128, 256), (256, 256), (256, 256), (256, 256)]
+
+    def run(xt):
+        v = (torch.tensor(xt).T - sh) * sc                       # (n, 4)
+        ph = 2.0 * math.pi * (v @ B.T)                            # (n, 64)
+        h = torch.cat([torch.cos(ph), torch.sin(ph)], dim=1)      # (n, 128)
+        off = 0
+        for fin, fout in widths:
+            W = p[off:off + fin * fout].view(fin, fout)
+            off += fin * fout
+            b = p[off:off + fout]
+            off += fout
+            h = F.gelu(F.linear(h, W.T.contiguous(), b), approximate="tanh")
+        Wh = p[off:off + 256 * 3].view(256, 3)
+        bh = p[off + 768:off + 771]
+        assert off + 771 == p.numel()
+        return out_scale * F.linear(h, Wh.T.contiguous(), bh).T   # (3, n)
+    return p, run
+
+
+def test_forward_and_backward_match_independent_torch_network():
+    # pins features (frequency layout, 2 pi, cos-then-sin order, shift and
+    # scale), the layer stack, the GELU form, the head and out_scale, which a
+    # finite-difference check of backward against forward cannot see
+    import torch
+    params, freq, xt, shift, scale, target = _setup(n=33, seed=4)
+    out_scale = 0.35
+    y, cache = M.forward(params, freq, xt, shift, scale, out_scale)
+    p, run = _torch_network(params, freq, shift, scale, out_scale)
+    yt = run(xt)
+    np.testing.assert_allclose(y, yt.detach().numpy(), rtol=1e-12, atol=1e-14)
+    # backward of sum(ddx * dx) against autograd
+    ddx = np.random.default_rng(9).standard_normal(y.shape)
+    g = M.backward(params, cache, ddx)
+    (yt * torch.tensor(ddx)).sum().backward()
+    gt = p.grad.numpy()
+    np.testing.assert_allclose(g, gt, rtol=1e-10, atol=1e-13)
+    # and the feature map alone: the first 64 features are cosines of
+    # 2 pi B (xt - shift) * scale, the last 64 sines
+    f = M.features(xt, freq, shift, scale)
+    v = (xt - np.array(shift)[:, None]) * np.array(scale)[:, None]
+    k, s = 5, 7
+    ph = 2 * math.pi * sum(freq[k, a] * v[a, s] for a in range(4))
+    assert abs(f[s, k] - math.cos(ph)) < 1e-13 and abs(f[s, 64 + k] - math.sin(ph)) < 1e-13
