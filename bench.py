@@ -1,15 +1,21 @@
 """Benchmark of the LCS hot path on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input:
-lcs_advect (seed grid -> RK4 flow map) -> lcs_cg_tensor (grad F, C) ->
-lcs_ftle (lambda_max, FTLE), on the time-dependent ABC flow sampled on a
-128^3 periodic grid (33 FP32 frames, t in [0, 16]) with 256^3 seeds,
-t0 = 0, T = 8, dt = 0.02 (400 RK4 steps).
+One step = the whole hot path over one batch of synthetic input, on the
+largest single-GPU workload: the divergence-free random-Fourier velocity field
+(256^3 periodic grid, 65 FP32 frames at t = 0.125 f), 512 x 512 x 256 seeds,
+forward and backward FTLE from t0 = 4 with |T| = 4, |dt| = 0.01 (400 RK4 steps
+each way).  Per step: staging of the structure-of-arrays frames into the
+time-paired records the kernels read, then for each direction lcs_advect
+(re-bundled segments, autotuned) and lcs_cg_ftle (gradient, C, lambda_max and
+the FTLE, FP64).
 
 Prints one JSON line.  ``value`` is tracer-RK4-steps per second of the whole
-step; the roofline object covers the advection kernel (the dominant one),
-timed with events on the stream it is launched on; the CPU baseline is the
-FP64 oracle on a bounded sample of the same seeds, on the host cores.
+step (FTLE points per second beside it); the roofline object covers the
+dominant kernel (the re-bundled RK4 segment kernel), its launches timed with
+HIP events on the stream they run on; the CPU baseline is the FP64 oracle on a
+bounded sample of the same seeds (with their difference stencils) on the host
+cores, and the same oracle run gives the error of each GPU result against
+FP64.
 """
 from __future__ import annotations
 
@@ -27,9 +33,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+# vector L1 data path: 128 B per clock per CU (the vL1D speed-of-light figure of
+# AMD's profiler for this chip) x 256 CUs x 2.4 GHz peak engine clock
+VL1D_PEAK_GBS = 128 * 256 * 2.4
 BYTES_PER_STEP_3D = 768      # 4 evals x 8 corners x 2 frames x 3 comps x 4 B
-WORKLOAD = dict(name="abc_128cubed_seeds256cubed", grid=128, frames=33, dt_frame=0.5,
-                seeds=(256, 256, 256), t0=0.0, T=8.0, dt=0.02)
+WORKLOAD = dict(name="random_fourier_256cubed_65frames_seeds512x512x256_T4_forward_backward",
+                grid=256, frames=65, dt_frame=0.125, seeds=(512, 512, 256), t0=4.0, T=4.0,
+                dt=0.01)
+ABC_WORKLOAD = dict(name="abc_128cubed_seeds256cubed", grid=128, frames=33, dt_frame=0.5,
+                    seeds=(256, 256, 256), t0=0.0, T=8.0, dt=0.02)
 
 
 def parse():
@@ -41,12 +53,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the oracle sample")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched-window, random-Fourier and surrogate workloads")
+                    help="skip the extra workloads (surrogate, ABC, batched windows, meshes, "
+                         "multistep, auxiliary points, time-resolved)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate workload")
     ap.add_argument("--layout", default="tpair", choices=("soa", "xyz", "xyzw", "tpair"),
                     help="frame layout the kernels read; with an interleaved layout the main "
                          "step converts the structure-of-arrays frames inside its timed region")
-    ap.add_argument("--extras", default="batched,random_fourier,surrogate,mesh,ab,aux,time_resolved",
+    ap.add_argument("--extras", default="surrogate,abc,batched,mesh,ab,aux,time_resolved",
                     help="comma-separated extra workloads to run after the main step")
     ap.add_argument("--strategy", default=None,
                     help="advection strategy of the main workload ('tiles' or 'sorted:S'); "
@@ -75,27 +88,6 @@ def source_hash(files):
     return h.hexdigest()[:16]
 
 
-def profiled_traffic_kernel(kernel):
-    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
-    summary, or None if there is none or its source changed since."""
-    try:
-        names = sorted(os.listdir(PROFILES))
-    except OSError:
-        return None
-    for name in names:
-        if not name.endswith(".md"):
-            continue
-        for line in open(os.path.join(PROFILES, name)).read().splitlines():
-            if not (line.startswith("{") and "traffic_bytes_per_launch" in line):
-                continue
-            rec = json.loads(line)
-            if rec.get("kernel") != kernel:
-                continue
-            if source_hash(rec["source_files"]) == rec["source_sha1"]:
-                return rec["traffic_bytes_per_launch"]
-    return None
-
-
 # frame layout of the 3D workloads (set from --layout in main)
 LAYOUT_3D = "tpair"
 
@@ -111,11 +103,10 @@ def stage_frames(lcs, fs, layout, tensors=None):
     return fr
 
 
-def profiled_traffic(strategy, layout="soa"):
-    """HBM bytes of one advection call (all its kernels) from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain
-    copy of known size), or None if it was taken for another strategy or the
-    kernel source changed since."""
+def profiled_record(kernel, workload):
+    """The committed rocprofv3 counter record of a kernel on a workload (HBM
+    bytes per launch, busy fractions, hit rates), or None if there is none or
+    the kernel sources changed since it was taken."""
     try:
         names = sorted(os.listdir(PROFILES))
     except OSError:
@@ -124,35 +115,47 @@ def profiled_traffic(strategy, layout="soa"):
         if not name.endswith(".md"):
             continue
         for line in open(os.path.join(PROFILES, name)).read().splitlines():
-            if not (line.startswith("{") and "traffic_bytes_per_launch" in line):
+            if not line.startswith("{"):
                 continue
             rec = json.loads(line)
-            if rec.get("strategy", "tiles") != strategy or rec.get("layout", "soa") != layout:
+            if rec.get("kernel") != kernel or rec.get("workload") != workload:
                 continue
             if source_hash(rec["source_files"]) == rec["source_sha1"]:
-                return rec["traffic_bytes_per_launch"]
+                return rec
     return None
 
 
-def profiled_counter(kernel, field):
-    """A figure (l2_hit_rate, ta_busy, td_busy, ...) of a kernel from the
-    committed rocprofv3 counter summary, or None if there is none or its
-    source changed since."""
-    try:
-        names = sorted(os.listdir(PROFILES))
-    except OSError:
-        return None
-    for name in names:
-        if not name.endswith(".md"):
-            continue
-        for line in open(os.path.join(PROFILES, name)).read().splitlines():
-            if not (line.startswith("{") and f'"{field}"' in line):
-                continue
-            rec = json.loads(line)
-            if rec.get("kernel") == kernel and \
-                    source_hash(rec["source_files"]) == rec["source_sha1"]:
-                return rec[field]
-    return None
+def roofline_record(kernel, avg_ms, launches, units_per_launch, workload):
+    """Roofline of an RK4 advection kernel: algorithmic stencil bytes per
+    launch over its average launch duration (HIP events around each launch on
+    its stream), against the vector L1 data path that binds these gathers,
+    with the HBM traffic and busy fractions from the committed counter
+    profile."""
+    A = BYTES_PER_STEP_3D * units_per_launch / (avg_ms * 1e-3) / 1e9
+    prof = profiled_record(kernel, workload) or {}
+    traffic = prof.get("traffic_bytes_per_launch")
+    hbm = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
+    return {"kernel": kernel, "bound": "vl1d", "achieved": A, "peak": VL1D_PEAK_GBS,
+            "unit": "GB/s", "frac": A / VL1D_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, each "
+                            "scaled by the same counter on a plain copy of known size)",
+            "bytes_per_unit": BYTES_PER_STEP_3D,
+            "unit_of_work": "3D tracer-RK4-step (4 evaluations x 8 corners x 2 frames x 3 "
+                            "components x 4 B of stencil data)",
+            "units_per_launch": units_per_launch, "launches_timed": launches,
+            "avg_launch_ms": avg_ms,
+            "timing": "HIP events recorded by the library around every launch of the kernel, "
+                      "on the stream it runs on, over the timed region",
+            "peak_basis": "vector L1 data path: 128 B per clock per CU x 256 CUs x 2.4 GHz",
+            "hbm_gbs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS if hbm else None,
+            "algorithmic_bytes_over_hbm_peak": A / HBM_PEAK_GBS,
+            "l2_hit_rate": prof.get("l2_hit_rate"), "l1_hit_rate": prof.get("l1_hit_rate"),
+            "ta_busy": prof.get("ta_busy"), "td_busy": prof.get("td_busy"),
+            "counters_workload": workload if prof else None,
+            "note": "the stencil gathers are served from the per-tracer register cache, L1 and "
+                    "L2: the kernel is not HBM-bound (hbm_frac); the texture address / data "
+                    "units of the vector-memory path are busy for most of its cycles (ta_busy, "
+                    "td_busy), so the vector L1 data path is the roofline it is held to"}
 
 
 def measure_copy_gbs(torch, dev, mib=1024, reps=5):
@@ -173,38 +176,170 @@ def measure_copy_gbs(torch, dev, mib=1024, reps=5):
     return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(fs, g, t0, T, dt, target_s):
-    """FP64 oracle on a bounded, deterministic sample of the seeds."""
+def host_threads():
+    """Threads the oracle uses: the CPU share of this process (its affinity
+    set, capped by OMP_NUM_THREADS where the environment sets one), and the
+    host's logical CPU count for the record."""
+    try:
+        share = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        share = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    n = min(share, int(env)) if env.isdigit() and int(env) > 0 else share
+    return max(1, n), share, os.cpu_count()
+
+
+def stencil_sample(g, m, seed):
+    """m seed indices drawn without replacement (deterministic), the indices of
+    their -/+ neighbours along each axis (wrapped on periodic axes, clamped
+    otherwise) and the union of all of them."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(g.count, size=min(m, g.count), replace=False))
+    c = g.coords_of(idx)
+    nb_m, nb_p = [], []
+    for b in range(g.dim):
+        cm, cp = c.copy(), c.copy()
+        if g.periodic[b]:
+            cm[b] = (c[b] - 1) % g.n[b]
+            cp[b] = (c[b] + 1) % g.n[b]
+        else:
+            cm[b] = np.maximum(c[b] - 1, 0)
+            cp[b] = np.minimum(c[b] + 1, g.n[b] - 1)
+        nb_m.append(g.index_of(cm))
+        nb_p.append(g.index_of(cp))
+    allidx = np.unique(np.concatenate([idx] + nb_m + nb_p))
+    return idx, c, nb_m, nb_p, allidx
+
+
+def err_stats(e):
+    e = np.asarray(e, dtype=np.float64)
+    return {"mean": float(e.mean()), "p99": float(np.quantile(e, 0.99)), "max": float(e.max()),
+            "n": int(e.size)}
+
+
+def fp64_errors(oracle, g, gpu, idx, c, nb_m, nb_p, allidx, xo, flo, T, L):
+    """Error of each GPU result (positions, C, lambda_max, FTLE) against the
+    FP64 oracle at the sampled seeds: the oracle's C comes from its own
+    positions of each seed and its stencil."""
+    pos = {int(k): p for p, k in enumerate(allidx)}
+    nq = g.dim * (g.dim + 1) // 2
+    Co = np.empty((nq, idx.size))
+    bad = np.zeros(idx.size, dtype=bool)
+    for q, s in enumerate(idx):
+        ps = pos[int(s)]
+        xm = [xo[:, pos[int(nb_m[b][q])]] for b in range(g.dim)]
+        xp = [xo[:, pos[int(nb_p[b][q])]] for b in range(g.dim)]
+        Co[:, q] = oracle.cg_point(g, c[:, q], xo[:, ps], xm, xp)
+        used = [ps] + [pos[int(nb_m[b][q])] for b in range(g.dim)] + \
+            [pos[int(nb_p[b][q])] for b in range(g.dim)]
+        bad[q] = bool(np.any(flo[used]))
+    lo, so = oracle.ftle(g.dim, Co, T)
+    sel = np.array([pos[int(s)] for s in idx])
+    ok = ~bad & (gpu["sflags"] == 0)
+    ex = np.linalg.norm(gpu["xf"].astype(np.float64) - xo[:, sel], axis=0)
+    # Frobenius norm of the packed symmetric difference (off-diagonals twice)
+    w = np.array([1.0 if r == s_ else 2.0 for r in range(g.dim) for s_ in range(r, g.dim)])
+    fro = lambda M: np.sqrt((w[:, None] * M * M).sum(axis=0))
+    eC = fro(gpu["C"] - Co) / fro(Co)
+    return {"seeds": int(idx.size), "clean_stencils": int(ok.sum()),
+            "xf_abs": err_stats(ex), "xf_over_domain_length": err_stats(ex / L),
+            "C_rel_frobenius": err_stats(eC[ok]),
+            "lambda_max_rel": err_stats(np.abs(gpu["lam"][ok] - lo[ok]) / np.abs(lo[ok])),
+            "ftle_abs": err_stats(np.abs(gpu["ftle"][ok] - so[ok])),
+            "flags_equal": bool(np.array_equal(gpu["flags"], flo[sel]))}
+
+
+def cpu_baseline(fs_host, g, t0, T, dt, target_s, gpu_at, L):
+    """FP64 oracle on a bounded, deterministic sample of the seeds, each with
+    its difference stencil, on the host cores: the rate in tracer-RK4-steps/s,
+    and the error of the GPU's results at those seeds against it."""
     import oracle
-    vel = oracle.Velocity(fs)
-    threads = oracle.default_threads()
+    vel = oracle.Velocity(fs_host, keep_f32=True)
+    threads, share, ncpu = host_threads()
     nsteps = int(round(T / dt))
-    rng = np.random.default_rng(0)
-    m = 4096
-    idx = np.sort(rng.choice(g.count, size=m, replace=False))
+    # calibrate on a small sample, then size the timed one to ~target_s
+    _, _, _, _, cal = stencil_sample(g, 256, seed=1)
     t = time.perf_counter()
-    oracle.advect_seeds(vel, g, t0, T, dt, idx=idx, threads=threads)
+    oracle.advect_seeds(vel, g, t0, T, dt, idx=cal, threads=threads)
+    el = max(time.perf_counter() - t, 1e-3)
+    per_tracer = el / cal.size
+    m = int(max(256, min(g.count // 8, target_s / per_tracer / 6.5)))
+    idx, c, nb_m, nb_p, allidx = stencil_sample(g, m, seed=0)
+    gpu = gpu_at(idx)
+    t = time.perf_counter()
+    xo, _, flo = oracle.advect_seeds(vel, g, t0, T, dt, idx=allidx, threads=threads)
     el = time.perf_counter() - t
-    m2 = int(min(g.count, max(m, m * target_s / max(el, 1e-3))))
-    if m2 > m * 1.5:
-        idx = np.sort(rng.choice(g.count, size=m2, replace=False))
-        t = time.perf_counter()
-        oracle.advect_seeds(vel, g, t0, T, dt, idx=idx, threads=threads)
-        el = time.perf_counter() - t
-        m = m2
-    # one thread as well, the serial baseline the paper compares with
-    m1 = max(64, int(m * 2.0 / max(el * threads, 1e-3)))
-    idx1 = np.sort(rng.choice(g.count, size=m1, replace=False))
+    errs = fp64_errors(oracle, g, gpu, idx, c, nb_m, nb_p, allidx, xo, flo, T, L)
+    # one thread as well, the serial baseline the paper quotes its speedups against
+    m1 = max(64, int(2.0 / per_tracer / threads))
+    idx1 = np.sort(np.random.default_rng(3).choice(g.count, size=m1, replace=False))
     t = time.perf_counter()
     oracle.advect_seeds(vel, g, t0, T, dt, idx=idx1, threads=1)
     el1 = time.perf_counter() - t
-    return {"value": m * nsteps / el, "unit": "tracer-RK4-steps/s", "cores": threads,
+    return {"value": allidx.size * nsteps / el, "unit": "tracer-RK4-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{m} seeds drawn from the 256^3 grid (seed 0), full T=8 ({nsteps} RK4 steps), "
-                      f"FP64, OpenMP, {el:.1f} s",
+            "sample": f"{idx.size} seeds drawn from the 512x512x256 grid (seed 0) with their "
+                      f"difference stencils ({allidx.size} tracers), forward T={T:g} "
+                      f"({nsteps} RK4 steps), FP64, OpenMP on {threads} threads, {el:.1f} s",
+            "host_cpu_share": share, "host_logical_cpus": ncpu,
+            "threads_note": "the oracle uses every CPU of this process's share (its affinity "
+                            "set, capped by OMP_NUM_THREADS where set)",
             "single_thread_value": m1 * nsteps / el1,
             "single_thread_sample": f"{m1} seeds, full T, one thread, {el1:.1f} s",
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(),
+            "fp64_error": errs}
+
+
+def precision_double_gyre(torch, lcs, inputs):
+    """Error against FP64 on the full double-gyre workload (201 x 101 nodes, 21
+    frames sampled in FP64, 256 x 128 seeds, T = 10, dt = 0.05): the mean
+    trajectory error e_S(t) of the FP32 GPU run against the FP64 oracle every
+    5 steps (the comparison of single- and double-precision trajectories), and
+    the error of each final result (positions, C, lambda_max, FTLE).  The GPU
+    reads the FP32 rounding of the frames; e_S against the oracle run on those
+    same FP32 frames separates input rounding from arithmetic rounding."""
+    import oracle
+    fs = inputs.double_gyre_frames(nx=201, ny=101, n_frames=21)
+    g = inputs.linspace_seeds(2, (256, 128), (0.0, 0.0), (2.0, 1.0))
+    t0, T, dt = 0.0, 10.0, 0.05
+    frames = lcs.DeviceFrames(fs)
+    steps = list(range(5, 201, 5))
+    xs, _, _ = lcs.lcs_advect_snapshots(frames, g, t0, dt, steps, want_flags=False,
+                                        want_steps=False)
+    xf, cell, flags = lcs.lcs_advect(frames, g, t0, T, dt)
+    Cm, sfl = lcs.lcs_cg_tensor(g, xf, flags)
+    lam, sig = lcs.lcs_ftle(2, Cm, T)
+    lcs.lcs_sync_status()
+    xs = xs.cpu().numpy()
+    x0 = oracle.seed_points(g)
+    curves = {}
+    for name, f in (("fp64_frames", fs), ("fp32_frames", fs.astype(np.float32))):
+        traj, tfl = oracle.advect_points_traj(oracle.Velocity(f), x0, t0, T, dt)
+        ok = tfl == 0
+        e = [float(np.linalg.norm(xs[k].astype(np.float64) - traj[s - 1], axis=0)[ok].mean())
+             for k, s in enumerate(steps)]
+        curves[name] = e
+    vel = oracle.Velocity(fs)
+    xo, _, flo = oracle.advect_seeds(vel, g, t0, T, dt)
+    Co, so_fl = oracle.cg_tensor(g, xo, flo)
+    lo, so = oracle.ftle(2, Co, T)
+    ok = (so_fl == 0) & (sfl.cpu().numpy() == 0)
+    gC = Cm.cpu().numpy()
+    w = np.array([1.0, 2.0, 1.0])
+    fro = lambda M: np.sqrt((w[:, None] * M * M).sum(axis=0))
+    ex = np.linalg.norm(xf.cpu().numpy().astype(np.float64) - xo, axis=0)
+    gl, gs = lam.cpu().numpy(), sig.cpu().numpy()
+    return {"workload": "double_gyre_201x101_21frames_seeds256x128_T10",
+            "e_S_steps": steps, "e_S_times": [t0 + s * dt for s in steps],
+            "e_S_vs_fp64_oracle": curves["fp64_frames"],
+            "e_S_vs_oracle_on_fp32_frames": curves["fp32_frames"],
+            "domain_length": 2.0,
+            "final": {"xf_abs": err_stats(ex), "xf_over_domain_length": err_stats(ex / 2.0),
+                      "C_rel_frobenius": err_stats((fro(gC - Co) / fro(Co))[ok]),
+                      "lambda_max_rel": err_stats((np.abs(gl - lo) / np.abs(lo))[ok]),
+                      "ftle_abs": err_stats(np.abs(gs - so)[ok]),
+                      "flags_equal": bool(np.array_equal(flags.cpu().numpy(), flo)),
+                      "clean_stencils": int(ok.sum())}}
 
 
 def cpu_model():
@@ -259,65 +394,68 @@ def bench_batched(torch, lcs, inputs, reps=3, layout="xyz"):
     return out
 
 
-def bench_random_fourier(torch, lcs, inputs, reps=1, keep=None):
-    """Divergence-free random-Fourier field, 256^3 x 65 FP32 frames, 512x512x256
-    seeds, forward and backward FTLE from t0 = 4 with |T| = 4, dt = 0.01."""
-    fs = inputs.random_fourier_frames(n=256, n_frames=65, dt_frame=0.125, device="cuda")
-    L = 2 * math.pi
-    g = inputs.SeedGrid(3, (512, 512, 256), (0.0, 0.0, 0.0), (L / 512, L / 512, L / 256),
-                        (True, True, True))
-    frames = stage_frames(lcs, fs, LAYOUT_3D, tensors=fs.u)
-    ns = g.count
+def bench_abc(torch, lcs, inputs, reps=5):
+    """Time-dependent ABC flow, 128^3 periodic grid, 33 FP32 frames, 256^3 seeds,
+    t0 = 0, T = 8, dt = 0.02: staging + lcs_advect (autotuned) + lcs_cg_ftle."""
     from paper_2209_13775_amd import autotune
-    tuned = autotune.tune(frames, g, 4.0, 4.0, 0.01, candidates=("sorted:100", "sorted:50",
-                                                                    "sorted:25"))
+    W = ABC_WORKLOAD
+    L = 2 * math.pi
+    fs = inputs.abc_frames(n=W["grid"], n_frames=W["frames"], dt_frame=W["dt_frame"])
+    g = inputs.periodic_seeds(3, W["seeds"], (L, L, L))
+    ns = g.count
+    nsteps = int(round(W["T"] / W["dt"]))
+    soa = lcs.DeviceFrames(fs)
+    frames = lcs.lcs_frames_interleave(soa, LAYOUT_3D)
+    tuned = autotune.tune(frames, g, W["t0"], W["T"], W["dt"], candidates=("tiles", "sorted:100"))
     choice = tuned["choice"]
-    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
-                     device="cuda")
+    ws = None if choice == "tiles" else torch.empty(
+        lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8, device="cuda")
     xf = torch.empty((3, ns), dtype=torch.float32, device="cuda")
+    cell = torch.empty(ns, dtype=torch.int64, device="cuda")
     flags = torch.empty(ns, dtype=torch.uint8, device="cuda")
     lam = torch.empty(ns, dtype=torch.float64, device="cuda")
     sig = torch.empty(ns, dtype=torch.float64, device="cuda")
     sfl = torch.empty(ns, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    res = {}
-    for T, dt in [(4.0, 0.01), (-4.0, -0.01)]:
-        ta, tc = [], []
-        for _ in range(reps):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            e[0].record(stream)
-            autotune.run(choice, frames, g, 4.0, T, dt, xf, None, flags, ws, want_cell=False,
-                         stream=stream)
-            e[1].record(stream)
-            lcs.lcs_cg_ftle(g, xf, T, flags=flags, lambda_max=lam, ftle=sig, stencil_flags=sfl,
-                            stream=stream)
-            e[2].record(stream)
-            torch.cuda.synchronize()
-            ta.append(e[0].elapsed_time(e[1]))
-            tc.append(e[1].elapsed_time(e[2]))
-        res["forward" if T > 0 else "backward"] = (float(np.median(ta)), float(np.median(tc)),
-                                                   float(sig.mean().item()))
-        if T > 0 and keep is not None:
-            keep.update(fs=fs, frames=frames, seeds=g, ref_ftle=sig.clone(),
-                        rk4_ms=float(np.median(ta)) + float(np.median(tc)))
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        lcs.lcs_frames_interleave(soa, LAYOUT_3D, out=frames.u[0], stream=stream)
+        autotune.run(choice, frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, ws,
+                     stream=stream)
+        if ev:
+            ev[1].record(stream)
+        lcs.lcs_cg_ftle(g, xf, W["T"], flags=flags, lambda_max=lam, ftle=sig, stencil_flags=sfl,
+                        stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    step()
+    torch.cuda.synchronize()
+    kernel = "advect_grid_kernel<3>" if choice == "tiles" else "rebundle_segment_kernel<3, 0>"
+    lcs.lcs_timing_enable(True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for k in range(reps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    launches, kms = lcs.lcs_timing_query(kernel)
+    lcs.lcs_timing_enable(False)
     lcs.lcs_sync_status()
-    nsteps = 400
-    steps = 2 * ns * nsteps
-    adv = res["forward"][0] + res["backward"][0]
-    cgf = res["forward"][1] + res["backward"][1]
-    del ws
-    return {"workload": "random_fourier_256cubed_seeds512x512x256", "frame_layout": LAYOUT_3D,
-            "seeds": ns,
-            "advect_strategy": choice, "autotune_ms": tuned["ms"],
-            "tracer_steps": steps, "advect_ms_forward": res["forward"][0],
-            "advect_ms_backward": res["backward"][0], "cg_ftle_ms": cgf,
-            "tracer_steps_per_s": steps / ((adv + cgf) * 1e-3),
-            "ftle_points_per_s": 2 * ns / (cgf * 1e-3),
-            "mean_ftle_forward": res["forward"][2], "mean_ftle_backward": res["backward"][2],
-            "roofline": {"kernel": "advection call (%s)" % choice, "bound": "hbm",
-                         "achieved": 768 * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": 768 * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "bytes_per_unit": 768, "unit_of_work": "3D tracer-RK4-step"}}
+    tot = [e[0].elapsed_time(e[2]) for e in evs]
+    adv = float(np.median([e[0].elapsed_time(e[1]) for e in evs]))
+    cgf = float(np.median([e[1].elapsed_time(e[2]) for e in evs]))
+    ms = float(np.median(tot))
+    steps = ns * nsteps
+    seg = nsteps if choice == "tiles" else int(choice.split(":")[1])
+    out = {"workload": W["name"], "field": "time-dependent ABC flow", "frame_layout": LAYOUT_3D,
+           "seeds": ns, "rk4_steps": nsteps, "advect_strategy": choice, "autotune_ms": tuned["ms"],
+           "ms_per_step_median": ms, "advect_ms": adv, "cg_ftle_ms": cgf,
+           "tracer_steps_per_s": steps / (ms * 1e-3), "ftle_points_per_s": ns / (cgf * 1e-3),
+           "roofline": roofline_record(kernel, kms / max(launches, 1), launches,
+                                       ns * seg, "abc_128cubed_seeds256cubed")}
+    del frames, soa, ws, xf, cell, flags, lam, sig, sfl
+    return out
 
 
 MESH_BYTES_PER_STEP_3D = 640   # 4 x (cell map 48 B + node ids 16 B + 2 frames x 4 nodes x 12 B)
@@ -388,7 +526,8 @@ def bench_mesh(torch, lcs, inputs, reps=3, cpu_sample=0):
                             "achieved": bps * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s",
                             "frac": bps * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                            "traffic": profiled_traffic_kernel("mesh_advect_grid_kernel<%d>" % dim),
+                            "traffic": (profiled_record("mesh_advect_grid_kernel<%d>" % dim, name) or {}).get(
+                                "traffic_bytes_per_launch"),
                             "bytes_per_unit": bps, "unit_of_work": "%dD mesh tracer-RK4-step" % dim}}
         if cpu_sample and dim == 3:
             import oracle
@@ -640,38 +779,62 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
     base = S.evaluate(mlp, vxt, vdx)
     log = S.train(mlp, xt, dx, epochs=epochs, batch=65536, lr=2e-3, val=(vxt, vdx))
     del xt, dx
+    flop = 2.0 * 230144 * g.count * cfg.n_windows    # 2 x multiply-adds of all layers
+    lcs.lcs_timing_enable(True)
     e0.record(stream)
     comp = lcs.lcs_surrogate_compose(mlp, g, cfg.t0, cfg.tau, cfg.n_windows, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     compose_ms = e0.elapsed_time(e1)
-    flop = 2.0 * 230144 * g.count * cfg.n_windows    # 2 x multiply-adds of all layers
+    nl, kms = lcs.lcs_timing_query("compose_fused_kernel")
+    lcs.lcs_timing_enable(False)
     del comp
-    e0.record(stream)
-    xf, flags, n_fail, err = S.surrogate_flowmap(mlp, frames, g, cfg, 1e-3, stream=stream)
-    _, sig, _ = lcs.lcs_cg_ftle(g, xf, T, flags=flags, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    path_ms = e0.elapsed_time(e1)
-    e = (sig - ref).abs()
     nt = lcs.lcs_check_tile_count(g)
+    wsb = lcs.lcs_surrogate_flowmap_workspace_bytes(frames, g, 0.25)
+    fws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    points = {}
+    for name, tol in (("check_tol_1e-3", 1e-3), ("check_tol_1e-2", 1e-2),
+                      ("composition_only", float("inf"))):
+        e0.record(stream)
+        xf, flags, nf, whole, err = lcs.lcs_surrogate_flowmap(
+            mlp, frames, g, cfg.t0, cfg.tau, cfg.n_windows, tol, cfg.dt, whole_grid_fraction=0.25,
+            workspace=fws, stream=stream)
+        _, sig, _ = lcs.lcs_cg_ftle(g, xf, T, flags=flags, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        path_ms = e0.elapsed_time(e1)
+        e = (sig - ref).abs()
+        ev_ = err.float()
+        points[name] = {"tolerance": tol, "fallback_tiles": nf, "tiles": nt,
+                        "fallback_fraction": nf / nt, "whole_grid_fallback": whole,
+                        "tile_err_median": float(ev_.median().item()),
+                        "tile_err_min": float(ev_.min().item()),
+                        "surrogate_path_ms": path_ms, "speedup_vs_rk4": keep["rk4_ms"] / path_ms,
+                        "ftle_err_mean": float(e.mean().item()),
+                        "ftle_err_p99": float(torch.quantile(e[::97].float(), 0.99).item()),
+                        "ftle_err_max": float(e.max().item())}
+        del xf, flags, sig, err, e
+    del fws
     out = {"workload": "surrogate_on_random_fourier_256cubed_seeds512x512x256",
            "train_samples": n_train, "train_epochs": epochs, "train_steps": log.steps,
            "train_seconds": log.seconds, "data_ms": data_ms,
            "val_mse_before": base, "val_mse_after": log.val_loss,
+           "val_rms_per_window": math.sqrt(log.val_loss),
+           "sigma_x": cfg.sigma_x, "sigma_t": cfg.sigma_t,
            "compose_ms": compose_ms,
            "compose_tflops": flop / (compose_ms * 1e-3) / 1e12,
-           "compose_mfma_frac": flop / (compose_ms * 1e-3) / 2.5e15,
-           "check_tolerance": 1e-3, "fallback_tiles": int(n_fail.item()), "tiles": nt,
-           "fallback_fraction": int(n_fail.item()) / nt,
-           "tile_err_median": float(err.median().item()),
-           "surrogate_path_ms": path_ms, "rk4_ms": keep["rk4_ms"],
-           "speedup_vs_rk4": keep["rk4_ms"] / path_ms,
-           "ftle_err_mean": float(e.mean().item()), "ftle_err_max": float(e.max().item())}
-    del xf, flags, sig
+           "roofline": {"kernel": "compose_fused_kernel", "bound": "mfma",
+                        "achieved": flop / (kms / max(nl, 1) * 1e-3) / 1e12 if nl else None,
+                        "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": flop / (kms / max(nl, 1) * 1e-3) / 1e12 / 2500.0 if nl else None,
+                        "traffic": None, "flops_per_unit": 2 * 230144,
+                        "unit_of_work": "point-window (BF16 MFMA, FP32 accumulation)",
+                        "units_per_launch": g.count * cfg.n_windows, "avg_launch_ms":
+                            kms / max(nl, 1)},
+           "rk4_ms": keep["rk4_ms"], "rk4": "forward T = 4, dt = 0.01, re-bundled, + FTLE",
+           "points": points}
     curve = []
-    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
-                     device="cuda")
+    ws = keep["ws"]
     for dtc in [0.02, 0.05, 0.1, 0.25]:
         e0.record(stream)
         seg = max(1, int(round(0.5 / dtc)))        # re-bundle every 0.5 time units
@@ -686,6 +849,8 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
         del xc, fc, sc
     out["coarse_rk4"] = curve
     out["coarse_rk4_strategy"] = "sorted, re-bundled every 0.5 time units"
+    ok = [c for c in curve if c["ftle_err_mean"] <= 1e-2]
+    out["fastest_rk4_within_1e-2"] = min(ok, key=lambda c: c["ms"]) if ok else None
     return out
 
 
@@ -696,7 +861,7 @@ def main():
               "--gpus above 1 is not supported", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2209_13775_amd import inputs, lcs
+    from paper_2209_13775_amd import autotune, inputs, lcs
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
@@ -711,24 +876,29 @@ def main():
         print(f"bench: calibration copy of {args.calibrate_copy_mib} MiB done", file=sys.stderr,
               flush=True)
         del src, dst
+    global LAYOUT_3D
+    LAYOUT_3D = args.layout
     W = WORKLOAD
     L = 2 * math.pi
-    fs = inputs.abc_frames(n=W["grid"], n_frames=W["frames"], dt_frame=W["dt_frame"])
-    g = inputs.periodic_seeds(3, W["seeds"], (L, L, L))
+    print("bench: generating the random-Fourier field", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    fs = inputs.random_fourier_frames(n=W["grid"], n_frames=W["frames"], dt_frame=W["dt_frame"],
+                                      device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    g = inputs.SeedGrid(3, W["seeds"], (0.0, 0.0, 0.0), tuple(L / k for k in W["seeds"]),
+                        (True, True, True))
     ns = g.count
     nsteps = int(round(W["T"] / W["dt"]))
-    frames_soa = lcs.DeviceFrames(fs, device=dev)
+    frames_soa = lcs.DeviceFrames(fs, tensors=fs.u)
     layout = args.layout
-    global LAYOUT_3D
-    LAYOUT_3D = layout
     frames = frames_soa if layout == "soa" else lcs.lcs_frames_interleave(frames_soa, layout)
-    from paper_2209_13775_amd import autotune
     if args.strategy:
         tuned = {"choice": args.strategy, "ms": None}
     else:
         print("bench: autotuning the seed ordering", file=sys.stderr, flush=True)
         tuned = autotune.tune(frames, g, W["t0"], W["T"], W["dt"],
-                              candidates=("tiles", "sorted:100"))
+                              candidates=("sorted:100", "sorted:50", "sorted:25"))
     choice = tuned["choice"]
     ws = None
     if choice != "tiles":
@@ -737,32 +907,39 @@ def main():
     xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
     cell = torch.empty(ns, dtype=torch.int64, device=dev)
     flags = torch.empty(ns, dtype=torch.uint8, device=dev)
-    Cm = torch.empty((6, ns), dtype=torch.float64, device=dev)
-    sfl = torch.empty(ns, dtype=torch.uint8, device=dev)
-    lam = torch.empty(ns, dtype=torch.float64, device=dev)
-    sig = torch.empty(ns, dtype=torch.float64, device=dev)
+    dirs = [(W["T"], W["dt"]), (-W["T"], -W["dt"])]
+    lam = [torch.empty(ns, dtype=torch.float64, device=dev) for _ in dirs]
+    sig = [torch.empty(ns, dtype=torch.float64, device=dev) for _ in dirs]
+    sfl = [torch.empty(ns, dtype=torch.uint8, device=dev) for _ in dirs]
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
+        # ev: 6 events -- start, staged, forward advected, forward FTLE,
+        # backward advected, backward FTLE
         if ev is not None:
             ev[0].record(stream)
         if layout != "soa":      # the step starts from the structure-of-arrays frames
             lcs.lcs_frames_interleave(frames_soa, layout, out=frames.u[0], stream=stream)
-        autotune.run(choice, frames, g, W["t0"], W["T"], W["dt"], xf, cell, flags, ws, stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        lcs.lcs_cg_tensor(g, xf, flags, Cm, sfl, stream=stream)
-        lcs.lcs_ftle(3, Cm, W["T"], lam, sig, stream=stream)
-        if ev is not None:
-            ev[2].record(stream)
+        for d, (T, dt) in enumerate(dirs):
+            autotune.run(choice, frames, g, W["t0"], T, dt, xf, cell, flags, ws, stream=stream)
+            if ev is not None:
+                ev[2 + 2 * d].record(stream)
+            lcs.lcs_cg_ftle(g, xf, T, flags=flags, lambda_max=lam[d], ftle=sig[d],
+                            stencil_flags=sfl[d], stream=stream)
+            if ev is not None:
+                ev[3 + 2 * d].record(stream)
 
-    print(f"bench: workload {W['name']}: {ns} seeds x {nsteps} steps; warmup {args.warmup}",
-          file=sys.stderr, flush=True)
+    print(f"bench: workload {W['name']}: {ns} seeds x {nsteps} steps x 2 directions; "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     lcs.lcs_sync_status()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    seg_kernel = "advect_grid_kernel<3>" if choice == "tiles" else "rebundle_segment_kernel<3, 0>"
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    lcs.lcs_timing_enable(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
@@ -770,19 +947,32 @@ def main():
         print(f"bench: step {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    launches, kms = lcs.lcs_timing_query(seg_kernel)
+    cg_launches, cg_ms = lcs.lcs_timing_query("cg_kernel<3, true>")
+    lcs.lcs_timing_enable(False)
     lcs.lcs_sync_status()
-    adv_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    cgf_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    el = lambda a, b: float(np.median([e[a].elapsed_time(e[b]) for e in evs]))
+    stage_ms = el(0, 1)
+    adv_ms = el(1, 2) + el(3, 4)
+    cgf_ms = el(2, 3) + el(4, 5)
     ms_per_step = wall * 1e3 / args.steps
-    tracer_steps = ns * nsteps
+    tracer_steps = 2 * ns * nsteps
     value = tracer_steps / (ms_per_step * 1e-3)
-    achieved = BYTES_PER_STEP_3D * tracer_steps / (adv_ms * 1e-3) / 1e9
+    seg = nsteps if choice == "tiles" else int(choice.split(":")[1])
+    avg_launch = kms / max(launches, 1)
     nflag = int((flags != 0).sum().item())
-    traffic = profiled_traffic(choice, layout)
     copy_gbs = measure_copy_gbs(torch, dev)
-    seg_kernel = "advect_grid_kernel<3>" if choice == "tiles" else "rebundle_segment_kernel<3, 0>"
+    roof = roofline_record(seg_kernel, avg_launch, launches, ns * seg, W["name"])
+    roof["measured_copy_gbs"] = copy_gbs
+    roof["cg_ftle_kernel"] = {"kernel": "cg_kernel<3, true>", "launches_timed": cg_launches,
+                              "avg_launch_ms": cg_ms / max(cg_launches, 1),
+                              "compulsory_bytes_per_point": 29,
+                              "hbm_gbs_compulsory": 29 * ns / (cg_ms / max(cg_launches, 1) * 1e-3) / 1e9,
+                              "note": "reads 12 B of xf and 1 B of flags, writes 8 B FTLE + 8 B "
+                                      "lambda_max per point (stencil flags not asked for)"}
     out = {
-        "metric": "tracer-RK4-steps/s (whole hot path: advect + C + FTLE), 1 GPU",
+        "metric": "tracer-RK4-steps/s (whole hot path: stage + advect + C + FTLE, forward and "
+                  "backward), 1 GPU",
         "value": value,
         "unit": "tracer-RK4-steps/s",
         "n_gpus": 1,
@@ -793,69 +983,71 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "dtype_detail": "advection and interpolation f32; gradient, C, lambda_max, FTLE f64",
+        "dtype_detail": "advection and interpolation f32 (two-float positions); gradient, C, "
+                        "lambda_max, FTLE f64",
         "data": "synthetic",
-        "config": {"workload": W["name"], "field": "time-dependent ABC flow",
-                   "grid": [W["grid"]] * 3, "frames": W["frames"], "seeds": list(W["seeds"]),
-                   "t0": W["t0"], "T": W["T"], "dt": W["dt"], "rk4_steps": nsteps,
+        "config": {"workload": W["name"],
+                   "field": "divergence-free random-Fourier velocity, |k| <= 32, E(k) ~ k^-5/3, "
+                            "OU time decorrelation 2, RMS speed 1 (seed 1)",
+                   "grid": [W["grid"]] * 3, "frames": W["frames"], "dt_frame": W["dt_frame"],
+                   "seeds": list(W["seeds"]), "t0": W["t0"], "T": [W["T"], -W["T"]],
+                   "dt": [W["dt"], -W["dt"]], "rk4_steps_per_direction": nsteps,
                    "frame_layout": layout},
-        "advect_ms": adv_ms,
-        "cg_ftle_ms": cgf_ms,
-        "tracer_steps_per_s_advect_kernel": tracer_steps / (adv_ms * 1e-3),
-        "ftle_points_per_s": ns / (cgf_ms * 1e-3),
-        "flagged_tracers": nflag,
+        "ftle_points_per_s": 2 * ns / (cgf_ms * 1e-3),
+        "stage_ms": stage_ms, "advect_ms": adv_ms, "cg_ftle_ms": cgf_ms,
+        "tracer_steps_per_s_advect": tracer_steps / (adv_ms * 1e-3),
+        "field_generation_s": gen_s,
+        "flagged_tracers_backward": nflag,
+        "mean_ftle": [float(sig[0].mean().item()), float(sig[1].mean().item())],
         "advect_strategy": choice,
         "autotune_ms": tuned["ms"],
-        "roofline": {"kernel": ("advect_grid_kernel<3>" if choice == "tiles" else
-                                "advection call: rebundle_segment_kernel<3, 0> x %d + re-bundling "
-                                "sorts (+ frame interleave)"
-                                % math.ceil(nsteps / int(choice.split(":")[1]))),
-                     "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
-                     "traffic_gbs": (traffic / (adv_ms * 1e-3) / 1e9) if traffic else None,
-                     "traffic_frac": (traffic / (adv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
-                     "note": "achieved = algorithmic stencil bytes (768 B per tracer-RK4-step) per "
-                             "second; they are served mostly from the per-tracer register cache, "
-                             "L1, L2 and the MALL, so frac exceeds 1; traffic_gbs is the HBM rate "
-                             "the counters measured",
-                     "bytes_per_unit": BYTES_PER_STEP_3D, "unit_of_work": "3D tracer-RK4-step",
-                     "units_per_launch": tracer_steps,
-                     "measured_copy_gbs": copy_gbs,
-                     "frac_of_measured_copy": achieved / copy_gbs,
-                     "traffic_frac_of_measured_copy":
-                         (traffic / (adv_ms * 1e-3) / 1e9 / copy_gbs) if traffic else None,
-                     "l2_hit_rate": profiled_counter(seg_kernel, "l2_hit_rate"),
-                     "ta_busy": profiled_counter(seg_kernel, "ta_busy"),
-                     "td_busy": profiled_counter(seg_kernel, "td_busy"),
-                     "counters_kernel": seg_kernel,
-                     "binding_resource": "texture address / data units of the vector-memory "
-                                         "path (ta_busy, td_busy: fraction of the kernel's "
-                                         "cycles, rocprofv3 TA_TA_BUSY_sum / TD_TD_BUSY_sum)"},
+        "roofline": roof,
         "cpu_baseline": None,
     }
-    del frames, frames_soa, xf, cell, flags, Cm, sfl, lam, sig, ws
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on a sample (forward)", file=sys.stderr, flush=True)
+        T, dt = dirs[0]
+        autotune.run(choice, frames, g, W["t0"], T, dt, xf, cell, flags, ws, stream=stream)
+        lcs.lcs_cg_ftle(g, xf, T, flags=flags, lambda_max=lam[0], ftle=sig[0],
+                        stencil_flags=sfl[0], stream=stream)
+        torch.cuda.synchronize()
+
+        def gpu_at(idx):
+            it = torch.from_numpy(idx).to(dev)
+            Cs = lcs.lcs_cg_tensor(g, xf, flags, want_stencil=False)[0][:, it]
+            return {"xf": xf[:, it].cpu().numpy(), "C": Cs.cpu().numpy(),
+                    "lam": lam[0][it].cpu().numpy(), "ftle": sig[0][it].cpu().numpy(),
+                    "flags": flags[it].cpu().numpy(), "sflags": sfl[0][it].cpu().numpy()}
+
+        f0 = int(round((W["t0"] - fs.t_first) / fs.dt_frame))
+        host = inputs.FrameSet(3, fs.n, fs.origin, fs.spacing, fs.periodic, W["t0"], fs.dt_frame,
+                               [u[f0:].cpu().numpy() for u in fs.u])
+        out["cpu_baseline"] = cpu_baseline(host, g, W["t0"], T, dt, args.cpu_seconds, gpu_at, L)
+        del host
+        print("bench: double-gyre precision (e_S curve, FP64 errors)", file=sys.stderr, flush=True)
+        out["cpu_baseline"]["precision_double_gyre"] = precision_double_gyre(torch, lcs, inputs)
+    keep = {"fs": fs, "frames": frames, "seeds": g, "ref_ftle": sig[0], "ws": ws,
+            "rk4_ms": el(1, 3)}
+    del frames_soa, xf, cell, flags, lam, sfl
     if not args.no_extra:
         want = set(x.strip() for x in args.extras.split(",") if x.strip())
         if args.no_surrogate:
             want.discard("surrogate")
         extra = {}
-        keep = {}
-        torch.cuda.empty_cache()
-        if "batched" in want:
-            print("bench: batched double gyre windows", file=sys.stderr, flush=True)
-            extra["batched"] = bench_batched(torch, lcs, inputs)
-            torch.cuda.empty_cache()
-        if "random_fourier" in want or "surrogate" in want:
-            print("bench: random-Fourier forward/backward", file=sys.stderr, flush=True)
-            extra["random_fourier"] = bench_random_fourier(torch, lcs, inputs, keep=keep)
-            torch.cuda.empty_cache()
         if "surrogate" in want:
             print("bench: surrogate (train, compose, check, fallback)", file=sys.stderr, flush=True)
             extra["surrogate"] = bench_surrogate(torch, lcs, keep)
         keep.clear()
+        del fs, sig
         torch.cuda.empty_cache()
+        if "abc" in want:
+            print("bench: ABC 128^3 workload", file=sys.stderr, flush=True)
+            extra["abc"] = bench_abc(torch, lcs, inputs)
+            torch.cuda.empty_cache()
+        if "batched" in want:
+            print("bench: batched double gyre windows", file=sys.stderr, flush=True)
+            extra["batched"] = bench_batched(torch, lcs, inputs)
+            torch.cuda.empty_cache()
         if "mesh" in want:
             print("bench: unstructured meshes", file=sys.stderr, flush=True)
             extra["mesh"] = bench_mesh(torch, lcs, inputs,
@@ -873,9 +1065,6 @@ def main():
             extra["time_resolved"] = bench_time_resolved(torch, lcs, inputs)
             torch.cuda.empty_cache()
         out["extra_workloads"] = extra
-    if not args.no_cpu_baseline:
-        print("bench: timing the oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(fs, g, W["t0"], W["T"], W["dt"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

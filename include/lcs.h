@@ -144,8 +144,9 @@ typedef struct {
 } lcs_window_t;
 
 /* Opaque plan: device state the library owns for batched launches (a work
- * counter, a capture stream and the captured HIP graph).  One plan per device
- * and per host thread at a time; calls that share a plan must not overlap. */
+ * counter, a capture stream and the captured HIP graph) and the autotuner's
+ * choices (lcs_advect_tuned).  One plan per device and per host thread at a
+ * time; calls that share a plan must not overlap. */
 typedef struct lcs_plan *lcs_plan_t;
 
 /* Maximum number of windows of one lcs_advect_batched call. */
@@ -313,13 +314,48 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
 
 /* lcs_plan_create / lcs_plan_destroy -- allocate / free a plan on the current
  * device (hipMalloc of a 4-byte counter, one non-blocking stream).
- * lcs_plan_destroy waits for the plan's stream and accepts NULL. */
-lcs_status lcs_plan_create(lcs_plan_t *plan);
+ * autotune_cache_path [host] NUL-terminated file name or NULL: the
+ * autotuner's choices are read from it now (one JSON object per line, as
+ * lcs_advect_tuned appends them; a missing file is an empty cache) and every
+ * new choice is appended to it.  lcs_plan_destroy waits for the plan's stream
+ * and accepts NULL. */
+lcs_status lcs_plan_create(lcs_plan_t *plan, const char *autotune_cache_path);
 lcs_status lcs_plan_destroy(lcs_plan_t plan);
 
 /* lcs_plan_stats -- number of graph launches and graph captures so far
  * (either pointer may be NULL). */
 lcs_status lcs_plan_stats(lcs_plan_t plan, int64_t *graph_launches, int64_t *graph_captures);
+
+/*
+ * lcs_advect_tuned -- lcs_advect with the seed ordering picked by the plan's
+ * autotuner (the tracer locality the paper found decisive, Sec. 3.2, depends
+ * on the field and the seed grid, so the choice is measured, not fixed).
+ * Candidates are segment lengths: 0 = the single launch of lcs_advect,
+ * S > 0 = lcs_advect_sorted re-bundling every S steps; NULL takes
+ * {0, 200, 100, 50, 25}.  The first call for a workload key (device
+ * architecture, velocity grid, layout, periodicity and frame count, seed grid,
+ * step count and direction) runs the first runnable candidate once untimed,
+ * then every runnable candidate once, timed with HIP events on `stream`
+ * (this call synchronises), keeps the fastest in the plan and appends it to
+ * the plan's cache file; later calls for that key (also in a later process
+ * through the cache) run the choice directly, asynchronously.  Re-bundled
+ * candidates need `workspace` of lcs_advect_sorted_workspace_bytes (else they
+ * are skipped, and a cached re-bundled choice falls back to the single
+ * launch).  Every candidate computes the same bits, so xf / cell / flags are
+ * those of lcs_advect whatever the choice.
+ * chosen        [host] int32 or NULL: the segment length that ran (0 = single).
+ * candidate_ms  [host] FP32 x n_candidates or NULL: on a tuning call, each
+ *               candidate's time (NaN if skipped); untouched otherwise.
+ * Errors: LCS_E_ARG (NULL plan, plan of another device, n_candidates outside
+ *   1..16, a negative candidate, no runnable candidate) and those of
+ *   lcs_advect / lcs_advect_sorted.
+ */
+lcs_status lcs_advect_tuned(lcs_plan_t plan, const lcs_velocity_t *vel,
+                            const lcs_seed_grid_t *seeds, double t0, double T, double dt,
+                            float *xf, int64_t *cell, uint8_t *flags, void *workspace,
+                            int64_t workspace_bytes, const int32_t *candidates,
+                            int32_t n_candidates, int32_t *chosen, float *candidate_ms,
+                            void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned flow-map surrogate: a Fourier-feature MLP that predicts the
@@ -433,6 +469,48 @@ lcs_status lcs_surrogate_check(const lcs_velocity_t *vel, const lcs_seed_grid_t 
 lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, double t0,
                             double T, double dt, const uint8_t *tile_fail, float *xf,
                             int64_t *cell, uint8_t *flags, void *stream);
+
+/*
+ * lcs_surrogate_flowmap -- the whole surrogate flow map of a 3D seed grid over
+ * T = n_windows * tau (a local flow-map approximation, Sec. 4, with plain RK4
+ * as the judge and the fallback): lcs_surrogate_compose, then
+ * lcs_surrogate_check with RK4 step dt and tolerance tol, then plain RK4 for
+ * the seeds of every failing tile.  When more than whole_grid_fraction of the
+ * check tiles fail, the whole grid is re-advected instead with the re-bundled
+ * RK4 of lcs_advect_sorted (the same per-tracer arithmetic, so the same
+ * results as tile by tile; faster when most tiles fail); whole_grid_fraction
+ * >= 1 never takes that branch.  tol = +inf accepts every tile (composition
+ * only; the check samples still run and tile_err still reports their error).
+ *
+ * The call reads the number of failing tiles back to the host: it
+ * synchronises `stream` once, after the check, and returns after enqueuing the
+ * fallback.
+ *
+ * xf               [device] FP32, 3 x Ns: composed positions of accepted tiles,
+ *                  RK4 positions (bit-identical to lcs_advect) of failing ones.
+ * flags            [device] uint8, Ns, or NULL: 0 for seeds of accepted tiles,
+ *                  lcs_advect's flags for re-advected seeds.
+ * tile_err         [device] FP32, lcs_check_tile_count(seeds), or NULL: the
+ *                  per-tile check error (as lcs_surrogate_check).
+ * n_fallback_tiles [host] int32 or NULL: number of failing tiles.
+ * whole_grid       [host] int32 or NULL: 1 if the whole grid was re-advected.
+ * workspace        [device], at least
+ *                  lcs_surrogate_flowmap_workspace_bytes(vel, seeds,
+ *                  whole_grid_fraction) bytes (per-tile scratch, plus the
+ *                  re-bundling workspace when whole_grid_fraction < 1).
+ * Errors: LCS_E_ARG (NULL xf / workspace, tol < 0 or NaN, whole_grid_fraction
+ *   < 0, n_windows < 1, tau 0), LCS_E_SHAPE (workspace too small), and those
+ *   of lcs_surrogate_check; LCS_E_HIP.
+ */
+int64_t lcs_surrogate_flowmap_workspace_bytes(const lcs_velocity_t *vel,
+                                              const lcs_seed_grid_t *seeds,
+                                              double whole_grid_fraction);
+lcs_status lcs_surrogate_flowmap(const lcs_mlp_t *mlp, const lcs_velocity_t *vel,
+                                 const lcs_seed_grid_t *seeds, double t0, double tau,
+                                 int32_t n_windows, double tol, double dt,
+                                 double whole_grid_fraction, float *xf, uint8_t *flags,
+                                 float *tile_err, int32_t *n_fallback_tiles, int32_t *whole_grid,
+                                 void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
  * lcs_advect_ab -- as lcs_advect with an explicit Adams-Bashforth multistep
@@ -725,6 +803,23 @@ lcs_status lcs_mesh_advect_points(lcs_mesh_t mesh, const lcs_mesh_frames_t *fram
                                   const float *x0, const double *t0, int64_t n, double T,
                                   double dt, float *xf, int64_t *cell, uint8_t *flags,
                                   void *stream);
+
+/*
+ * lcs_timing_enable / lcs_timing_query -- measurement of the library's main
+ * kernels (not part of the method).  While timing is enabled, every launch of
+ * advect_grid_kernel<D>, rebundle_segment_kernel<D, S>, cg_kernel<D, fused>,
+ * compose_fused_kernel, gemm_kernel<EPI_FWD|EPI_BWD> and wgrad_kernel is
+ * bracketed by two HIP events recorded on the stream the kernel is launched
+ * on (two event creations and records per launch).  lcs_timing_enable(on)
+ * discards earlier records and turns recording on (on != 0) or off.
+ * lcs_timing_query(kernel, launches, total_ms) -- after the recorded work has
+ * completed (synchronise first) -- gives the number of recorded launches of
+ * the kernel named exactly as above (e.g. "rebundle_segment_kernel<3, 0>") and
+ * their summed duration in milliseconds.  Thread safe; records are global to
+ * the process.  Errors: LCS_E_ARG (NULL pointer), LCS_E_HIP (work not done).
+ */
+lcs_status lcs_timing_enable(int32_t on);
+lcs_status lcs_timing_query(const char *kernel, int64_t *launches, double *total_ms);
 
 /* lcs_sync_status -- waits for the stream and reports a pending HIP error. */
 lcs_status lcs_sync_status(void *stream);

@@ -14,6 +14,8 @@
 // or position rounding by exp(sigma T), so only the FP32 interpolation
 // arithmetic itself is left to round.
 
+#include <stdio.h>
+
 #include "lcs_internal.h"
 #include "device_common.h"
 
@@ -1008,6 +1010,12 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, long long n,
     if (i < n) p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void fill_u8_kernel(uint8_t *p, long long n, uint8_t v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // State of every seed in natural order, its flag for a start outside the
 // domain, its key and the bin histogram.
 template <int D>
@@ -1203,6 +1211,12 @@ hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
@@ -1214,6 +1228,9 @@ hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s)
 hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    char name[64];
+    snprintf(name, sizeof(name), "rebundle_segment_kernel<%d, %d>", dim, a.order);
+    LaunchTimer timer(name, s);
     if (dim == 2) {
         switch (a.order) {
         case 2: hipLaunchKernelGGL((rebundle_segment_kernel<2, 2>), grid, block, 0, s, a); break;
@@ -1229,6 +1246,7 @@ hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s)
         default: hipLaunchKernelGGL((rebundle_segment_kernel<3, 0>), grid, block, 0, s, a);
         }
     }
+    timer.stop(s);
     return hipGetLastError();
 }
 
@@ -1270,10 +1288,12 @@ hipError_t launch_advect_tiles(const AdvectArgs &a, const uint8_t *tile_fail, in
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s)
 {
     dim3 grid((unsigned)a.g.n_blocks), block(256);
+    LaunchTimer timer(dim == 2 ? "advect_grid_kernel<2>" : "advect_grid_kernel<3>", s);
     if (dim == 2)
         hipLaunchKernelGGL(advect_grid_kernel<2>, grid, block, 0, s, a);
     else
         hipLaunchKernelGGL(advect_grid_kernel<3>, grid, block, 0, s, a);
+    timer.stop(s);
     return hipGetLastError();
 }
 

@@ -7,7 +7,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "lcs_internal.h"
 
@@ -255,6 +258,10 @@ struct lcs_plan {
     int key_grid = 0;
     long long launches = 0;
     long long captures = 0;
+    // autotuner: chosen segment length (0 = single launch) per workload key,
+    // and the file the choices are read from / appended to (may be empty)
+    std::string cache_path;
+    std::vector<std::pair<std::string, int>> tuned;
 };
 
 namespace {
@@ -268,16 +275,140 @@ void drop_graph(lcs_plan *p)
     p->have_graph = false;
 }
 
+// Autotuner cache: one JSON object per line,
+//   {"key": "<workload key>", "segment_steps": S, "ms": [...]}
+// later lines for the same key override earlier ones.
+void read_tune_cache(lcs_plan *p)
+{
+    FILE *f = fopen(p->cache_path.c_str(), "r");
+    if (!f) return;
+    char line[1024], key[512];
+    int seg = 0;
+    while (fgets(line, sizeof(line), f)) {
+        if (sscanf(line, " {\"key\": \"%511[^\"]\", \"segment_steps\": %d", key, &seg) != 2) continue;
+        bool found = false;
+        for (auto &kv : p->tuned)
+            if (kv.first == key) { kv.second = seg; found = true; }
+        if (!found) p->tuned.emplace_back(key, seg);
+    }
+    fclose(f);
+}
+
+// Workload key: device architecture, velocity grid and layout, frame count,
+// periodicity, seed grid, step count and direction.
+std::string tune_key(const lcs_velocity_t *v, const lcs_seed_grid_t *g, int nsteps, double dt,
+                     int device)
+{
+    hipDeviceProp_t prop;
+    char arch[64] = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+        char *colon = strchr(arch, ':');
+        if (colon) *colon = '\0';
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s:%dd:grid%lldx%lldx%lld:layout%u:per%u:frames%d:seeds%lldx%lldx%lld:"
+             "steps%d%s", arch, v->dim, (long long)v->n[0], (long long)v->n[1], (long long)v->n[2],
+             v->layout, v->periodic_mask, v->n_frames, (long long)g->n[0], (long long)g->n[1],
+             (long long)g->n[2], nsteps, dt < 0 ? "b" : "f");
+    return buf;
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Launch timing: event pairs per kernel launch, kept until queried or cleared.
+// ---------------------------------------------------------------------------
+namespace {
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t ev[2];
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedLaunch> g_timing;
+
+void timing_clear_locked()
+{
+    for (auto &t : g_timing) {
+        if (t.ev[0]) (void)hipEventDestroy(t.ev[0]);
+        if (t.ev[1]) (void)hipEventDestroy(t.ev[1]);
+    }
+    g_timing.clear();
+}
+}  // namespace
+
+namespace lcs {
+LaunchTimer::LaunchTimer(const char *name, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (!g_timing_on) return;
+    TimedLaunch t;
+    t.name = name;
+    t.ev[0] = t.ev[1] = nullptr;
+    if (hipEventCreate(&t.ev[0]) != hipSuccess || hipEventCreate(&t.ev[1]) != hipSuccess ||
+        hipEventRecord(t.ev[0], s) != hipSuccess) {
+        if (t.ev[0]) (void)hipEventDestroy(t.ev[0]);
+        if (t.ev[1]) (void)hipEventDestroy(t.ev[1]);
+        return;
+    }
+    slot = (int)g_timing.size();
+    g_timing.push_back(t);
+}
+
+void LaunchTimer::stop(hipStream_t s)
+{
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    if (slot < (int)g_timing.size()) (void)hipEventRecord(g_timing[slot].ev[1], s);
+    slot = -1;
+}
+}  // namespace lcs
 
 extern "C" {
 
-lcs_status lcs_plan_create(lcs_plan_t *plan)
+lcs_status lcs_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    timing_clear_locked();
+    g_timing_on = (on != 0);
+    return lcs::clear_error();
+}
+
+lcs_status lcs_timing_query(const char *kernel, int64_t *launches, double *total_ms)
+{
+    if (!kernel || !launches || !total_ms)
+        return lcs::set_error(LCS_E_ARG, "kernel, launches and total_ms must not be NULL");
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    long long n = 0;
+    double ms = 0.0;
+    for (auto &t : g_timing) {
+        if (t.name != kernel) continue;
+        float e = 0.0f;
+        const hipError_t r = hipEventElapsedTime(&e, t.ev[0], t.ev[1]);
+        if (r != hipSuccess) return lcs::hip_error(r, "timing query (synchronize first)");
+        ++n;
+        ms += e;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return lcs::clear_error();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+lcs_status lcs_plan_create(lcs_plan_t *plan, const char *autotune_cache_path)
 {
     if (!plan) return lcs::set_error(LCS_E_ARG, "plan pointer is NULL");
     *plan = nullptr;
     lcs_plan *p = new (std::nothrow) lcs_plan();
     if (!p) return lcs::set_error(LCS_E_ARG, "out of host memory");
+    if (autotune_cache_path && autotune_cache_path[0]) {
+        p->cache_path = autotune_cache_path;
+        read_tune_cache(p);
+    }
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc((void **)&p->d_counter, sizeof(int));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
@@ -1059,6 +1190,107 @@ lcs_status lcs_ftle(int32_t dim, int64_t n_points, const double *C, double T, do
     A.inv_two_T = 1.0 / (2.0 * fabs(T));
     hipError_t e = lcs::launch_ftle(dim, A, (hipStream_t)stream);
     if (e != hipSuccess) return lcs::hip_error(e, "ftle launch");
+    return lcs::clear_error();
+}
+
+}  // extern "C"
+
+extern "C" {
+
+lcs_status lcs_advect_tuned(lcs_plan_t plan, const lcs_velocity_t *vel,
+                            const lcs_seed_grid_t *seeds, double t0, double T, double dt,
+                            float *xf, int64_t *cell, uint8_t *flags, void *workspace,
+                            int64_t workspace_bytes, const int32_t *candidates,
+                            int32_t n_candidates, int32_t *chosen, float *candidate_ms,
+                            void *stream)
+{
+    if (!plan) return lcs::set_error(LCS_E_ARG, "plan is NULL");
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    int nsteps = 0;
+    if ((st = check_steps(T, dt, &nsteps)) != LCS_OK) return st;
+    static const int32_t kDefault[] = {0, 200, 100, 50, 25};
+    if (!candidates) {
+        candidates = kDefault;
+        n_candidates = 5;
+    }
+    if (n_candidates < 1 || n_candidates > 16)
+        return lcs::set_error(LCS_E_ARG, "n_candidates must be 1..16");
+    for (int i = 0; i < n_candidates; ++i)
+        if (candidates[i] < 0) return lcs::set_error(LCS_E_ARG, "candidate segment lengths must be >= 0");
+    int device = -1;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return lcs::hip_error(e, "hipGetDevice");
+    if (device != plan->device) return lcs::set_error(LCS_E_ARG, "plan belongs to device %d", plan->device);
+    const bool ws_ok = workspace &&
+                       workspace_bytes >= lcs_advect_sorted_workspace_bytes(vel, seeds);
+    auto run = [&](int seg) {
+        return seg == 0 ? lcs_advect(vel, seeds, t0, T, dt, xf, cell, flags, stream)
+                        : lcs_advect_sorted(vel, seeds, t0, T, dt, seg, xf, cell, flags, workspace,
+                                            workspace_bytes, stream);
+    };
+    const std::string key = tune_key(vel, seeds, nsteps, dt, device);
+    for (auto &kv : plan->tuned) {
+        if (kv.first != key) continue;
+        const int seg = (kv.second != 0 && !ws_ok) ? 0 : kv.second;
+        if (chosen) *chosen = seg;
+        return run(seg);
+    }
+    // tune: one untimed run of the first eligible candidate, then each
+    // eligible candidate once, timed with events on the caller's stream
+    int first = -1;
+    for (int i = 0; i < n_candidates && first < 0; ++i)
+        if (candidates[i] == 0 || ws_ok) first = i;
+    if (first < 0)
+        return lcs::set_error(LCS_E_ARG, "no candidate can run: re-bundled candidates need a "
+                              "workspace of lcs_advect_sorted_workspace_bytes");
+    if ((st = run(candidates[first])) != LCS_OK) return st;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    int best = -1;
+    float best_ms = INFINITY;
+    char msbuf[256] = "";
+    for (int i = 0; i < n_candidates && e == hipSuccess; ++i) {
+        const int seg = candidates[i];
+        float ms = NAN;
+        if (seg == 0 || ws_ok) {
+            e = hipEventRecord(ev[0], (hipStream_t)stream);
+            if (e != hipSuccess) break;
+            if ((st = run(seg)) != LCS_OK) {
+                (void)hipEventDestroy(ev[0]);
+                (void)hipEventDestroy(ev[1]);
+                return st;
+            }
+            e = hipEventRecord(ev[1], (hipStream_t)stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = seg;
+            }
+        }
+        if (candidate_ms) candidate_ms[i] = ms;
+        const size_t used = strlen(msbuf);
+        snprintf(msbuf + used, sizeof(msbuf) - used, "%s[%d, %.4g]", i ? ", " : "", seg,
+                 isnan(ms) ? -1.0 : (double)ms);
+    }
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    if (ev[1]) (void)hipEventDestroy(ev[1]);
+    if (e != hipSuccess) return lcs::hip_error(e, "autotune timing");
+    plan->tuned.emplace_back(key, best);
+    if (!plan->cache_path.empty()) {
+        FILE *f = fopen(plan->cache_path.c_str(), "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"segment_steps\": %d, \"ms\": [%s]}\n", key.c_str(), best,
+                    msbuf);
+            fclose(f);
+        }
+    }
+    if (chosen) *chosen = best;
+    // every candidate computes the same bits, so the outputs of the last run
+    // are the tuned call's outputs
     return lcs::clear_error();
 }
 

@@ -209,6 +209,146 @@ lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *se
 }
 
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of lcs_surrogate_flowmap: per-tile errors and failure marks, the
+// failure counter, then (if the whole-grid fallback may be taken) the
+// re-bundling workspace of lcs_advect_sorted; each part 256-byte aligned.
+struct FlowmapWs {
+    float *tile_err;
+    uint8_t *tile_fail;
+    int *n_fail;
+    void *sorted;
+    long long sorted_bytes;
+    long long bytes;
+};
+
+long long align256(long long b) { return (b + 255) / 256 * 256; }
+
+FlowmapWs flowmap_layout(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds, bool whole,
+                         void *base)
+{
+    int ct[3];
+    const long long nt = check_tiles(seeds, ct);
+    FlowmapWs w;
+    memset(&w, 0, sizeof(w));
+    char *p = static_cast<char *>(base);
+    long long off = 0;
+    w.tile_err = reinterpret_cast<float *>(p + off);
+    off += align256(4 * nt);
+    w.tile_fail = reinterpret_cast<uint8_t *>(p + off);
+    off += align256(nt);
+    w.n_fail = reinterpret_cast<int *>(p + off);
+    off += 256;
+    w.sorted = p + off;
+    w.sorted_bytes = whole ? lcs_advect_sorted_workspace_bytes(vel, seeds) : 0;
+    off += align256(w.sorted_bytes);
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lcs_surrogate_flowmap_workspace_bytes(const lcs_velocity_t *vel,
+                                              const lcs_seed_grid_t *seeds,
+                                              double whole_grid_fraction)
+{
+    if (!vel || !seeds || lcs::validate_velocity(vel) != LCS_OK ||
+        lcs::validate_seeds(seeds, 3) != LCS_OK)
+        return 0;
+    return flowmap_layout(vel, seeds, whole_grid_fraction < 1.0, nullptr).bytes;
+}
+
+lcs_status lcs_surrogate_flowmap(const lcs_mlp_t *mlp, const lcs_velocity_t *vel,
+                                 const lcs_seed_grid_t *seeds, double t0, double tau,
+                                 int32_t n_windows, double tol, double dt,
+                                 double whole_grid_fraction, float *xf, uint8_t *flags,
+                                 float *tile_err, int32_t *n_fallback_tiles, int32_t *whole_grid,
+                                 void *workspace, int64_t workspace_bytes, void *stream)
+{
+    lcs_status st;
+    if ((st = check_mlp(mlp)) != LCS_OK) return st;
+    if (n_windows < 1 || !isfinite(tau) || tau == 0.0)
+        return lcs::set_error(LCS_E_ARG, "need n_windows >= 1 and finite non-zero tau");
+    const double T = (double)n_windows * tau;
+    int nsteps = 0;
+    if ((st = check_window(vel, seeds, t0, T, dt, &nsteps)) != LCS_OK) return st;
+    if (!xf || !workspace) return lcs::set_error(LCS_E_ARG, "xf and workspace must not be NULL");
+    if (!(tol >= 0.0)) return lcs::set_error(LCS_E_ARG, "tol must be >= 0 (inf accepts every tile)");
+    if (!(whole_grid_fraction >= 0.0)) return lcs::set_error(LCS_E_ARG, "whole_grid_fraction must be >= 0");
+    const bool whole_ok = whole_grid_fraction < 1.0;
+    const FlowmapWs w = flowmap_layout(vel, seeds, whole_ok, workspace);
+    if (workspace_bytes < w.bytes)
+        return lcs::set_error(LCS_E_SHAPE, "workspace of %lld bytes is smaller than the %lld needed",
+                              (long long)workspace_bytes, w.bytes);
+    hipStream_t s = (hipStream_t)stream;
+    const long long ns = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    int ct[3];
+    const long long nt = check_tiles(seeds, ct);
+
+    // 1. composition of the windows
+    lcs::ComposeArgs A;
+    memset(&A, 0, sizeof(A));
+    A.P = make_dev(mlp);
+    A.g = lcs::seed_tiling(seeds);
+    A.ns = ns;
+    A.t0 = t0;
+    A.tau = tau;
+    A.n_windows = n_windows;
+    A.xf = xf;
+    hipError_t e = lcs::launch_compose_fused(A, s);
+    if (e != hipSuccess) return lcs::hip_error(e, "surrogate compose launch");
+    // 2. check samples against plain RK4 over the whole interval
+    lcs::CheckArgs K;
+    memset(&K, 0, sizeof(K));
+    K.v = lcs::velocity_dev(vel);
+    K.g = A.g;
+    K.t0 = t0;
+    K.dt = dt;
+    K.nsteps = nsteps;
+    K.ns = ns;
+    K.xf = xf;
+    K.tile_err = tile_err ? tile_err : w.tile_err;
+    K.n_tiles = check_tiles(seeds, K.ct);
+    e = lcs::launch_surrogate_check(K, (float)fmin(tol, (double)INFINITY), w.tile_fail, w.n_fail, s);
+    if (e == hipSuccess && flags) e = lcs::launch_fill_u8(flags, ns, 0, s);
+    if (e != hipSuccess) return lcs::hip_error(e, "surrogate check launch");
+    // 3. the number of failing tiles decides the fallback (one synchronisation)
+    int nf = 0;
+    e = hipMemcpyAsync(&nf, w.n_fail, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return lcs::hip_error(e, "reading the failing-tile count");
+    const bool whole = whole_ok && nf > 0 && (double)nf > whole_grid_fraction * (double)nt;
+    if (n_fallback_tiles) *n_fallback_tiles = nf;
+    if (whole_grid) *whole_grid = whole ? 1 : 0;
+    if (whole) {
+        // re-bundled RK4 of every seed: the same per-tracer arithmetic as the
+        // tile fallback, faster when most tiles fail
+        return lcs_advect_sorted(vel, seeds, t0, T, dt, 0, xf, nullptr, flags, w.sorted,
+                                 w.sorted_bytes, stream);
+    }
+    if (nf > 0) {
+        lcs::AdvectArgs R;
+        memset(&R, 0, sizeof(R));
+        R.v = K.v;
+        R.g = A.g;
+        R.t0 = t0;
+        R.dt = dt;
+        R.nsteps = nsteps;
+        R.ns = ns;
+        R.xf = xf;
+        R.flags = flags;
+        if (nt * 8 > 2147483647LL) return lcs::set_error(LCS_E_SHAPE, "too many tiles");
+        e = lcs::launch_advect_tiles(R, w.tile_fail, ct[0], ct[1], nt, s);
+        if (e != hipSuccess) return lcs::hip_error(e, "advect_tiles launch");
+    }
+    return lcs::clear_error();
+}
+
 int64_t lcs_mlp_workspace_bytes(int64_t batch, int32_t training)
 {
     return batch > 0 ? ws_bytes(batch, training != 0) : 0;

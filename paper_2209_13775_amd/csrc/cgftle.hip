@@ -7,6 +7,8 @@
 // segment (and seam/edge cases) read their x-neighbour from memory.  The y-
 // and z-neighbours are coalesced row reads of the FP32 positions.
 
+#include <stdio.h>
+
 #include "lcs_internal.h"
 
 namespace lcs {
@@ -576,6 +578,9 @@ hipError_t launch_cg(const CgArgs &a, bool fused, hipStream_t s)
     dim3 grid((unsigned)((a.n[0] + kWave - 1) / kWave), (unsigned)((a.n[1] + kRows - 1) / kRows),
               (unsigned)(a.dim == 3 ? a.n[2] : 1));
     dim3 block(kWave * kRows);
+    char name[48];
+    snprintf(name, sizeof(name), "cg_kernel<%d, %s>", a.dim, fused ? "true" : "false");
+    LaunchTimer timer(name, s);
     if (a.dim == 2) {
         if (fused) hipLaunchKernelGGL((cg_kernel<2, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((cg_kernel<2, false>), grid, block, 0, s, a);
@@ -583,6 +588,7 @@ hipError_t launch_cg(const CgArgs &a, bool fused, hipStream_t s)
         if (fused) hipLaunchKernelGGL((cg_kernel<3, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((cg_kernel<3, false>), grid, block, 0, s, a);
     }
+    timer.stop(s);
     return hipGetLastError();
 }
 

@@ -343,6 +343,7 @@ hipError_t launch_rebundle_init(int dim, const SegmentArgs &a, hipStream_t s);
 hipError_t launch_rebundle_segment(int dim, const SegmentArgs &a, hipStream_t s);
 hipError_t launch_rebundle_sort(const SegmentArgs &a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, long long n, uint8_t v, hipStream_t s);
 long long exclusive_scan_sums_needed(long long n);
 hipError_t launch_exclusive_scan_u32(uint32_t *data, long long n, uint32_t *block_sums,
                                      hipStream_t s);
@@ -354,6 +355,15 @@ lcs_status validate_steps(double T, double dt, int *nsteps);
 lcs_status validate_seed_domain(const lcs_velocity_t *v, const lcs_seed_grid_t *g);
 VelDev velocity_dev(const lcs_velocity_t *v);
 SeedTiling seed_tiling(const lcs_seed_grid_t *g);
+
+// Launch timing (lcs_timing_enable): while enabled, a LaunchTimer brackets a
+// kernel launch with two HIP events recorded on the launch's stream, filed
+// under the kernel's name; disabled, it does nothing.
+struct LaunchTimer {
+    int slot = -1;
+    LaunchTimer(const char *name, hipStream_t s);
+    void stop(hipStream_t s);
+};
 
 // error reporting shared by the ABI translation units
 lcs_status set_error(lcs_status st, const char *fmt, ...);

@@ -590,7 +590,9 @@ __global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a, c
 
 hipError_t launch_compose_fused(const ComposeArgs &a, hipStream_t s)
 {
+    LaunchTimer timer("compose_fused_kernel", s);
     hipLaunchKernelGGL(compose_fused_kernel, dim3((unsigned)((a.ns + kFT - 1) / kFT)), dim3(256), 0, s, a);
+    timer.stop(s);
     return hipGetLastError();
 }
 
@@ -613,15 +615,19 @@ hipError_t launch_features(const MlpDev &P, const float *xt, long long M, uint16
 hipError_t launch_gemm(const GemmArgs &g, bool backward, hipStream_t s)
 {
     dim3 grid((unsigned)(g.N / kBN), (unsigned)((g.M + kBM - 1) / kBM)), block(256);
+    LaunchTimer timer(backward ? "gemm_kernel<EPI_BWD>" : "gemm_kernel<EPI_FWD>", s);
     if (backward) hipLaunchKernelGGL(gemm_kernel<EPI_BWD>, grid, block, 0, s, g);
     else hipLaunchKernelGGL(gemm_kernel<EPI_FWD>, grid, block, 0, s, g);
+    timer.stop(s);
     return hipGetLastError();
 }
 
 hipError_t launch_wgrad(const WgradArgs &g, int nchunk, hipStream_t s)
 {
     dim3 grid((unsigned)(g.N / kWT), (unsigned)(g.K / kWT), (unsigned)nchunk), block(256);
+    LaunchTimer timer("wgrad_kernel", s);
     hipLaunchKernelGGL(wgrad_kernel, grid, block, 0, s, g);
+    timer.stop(s);
     return hipGetLastError();
 }
 

@@ -76,8 +76,11 @@ def _load(path: str = LIB_PATH):
         "lcs_ftle": [I32, I64, P, D, P, P, P],
         "lcs_cg_ftle": [P, P, P, D, P, P, P, P],
         "lcs_sync_status": [P],
+        "lcs_timing_enable": [I32],
+        "lcs_timing_query": [C.c_char_p, P, P],
         "lcs_advect_batched": [P, P, P, P, I32, D, P, P, P, P],
-        "lcs_plan_create": [P],
+        "lcs_plan_create": [P, C.c_char_p],
+        "lcs_advect_tuned": [P, P, P, D, D, D, P, P, P, P, I64, P, I32, P, P, P],
         "lcs_plan_destroy": [P],
         "lcs_plan_stats": [P, P, P],
         "lcs_mlp_refresh_bf16": [P, P, P],
@@ -88,6 +91,7 @@ def _load(path: str = LIB_PATH):
         "lcs_surrogate_compose": [P, P, D, D, I32, P, P],
         "lcs_surrogate_check": [P, P, D, D, D, P, C.c_float, P, P, P, P],
         "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
+        "lcs_surrogate_flowmap": [P, P, P, D, D, I32, D, D, D, P, P, P, P, P, P, I64, P],
         "lcs_sub": [P, P, I64, P, P],
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
@@ -128,6 +132,8 @@ def _load(path: str = LIB_PATH):
     L.lcs_advect_ab_sorted_workspace_bytes.argtypes = [P, P]
     L.lcs_ftle_early_workspace_bytes.restype = C.c_int64
     L.lcs_ftle_early_workspace_bytes.argtypes = [P]
+    L.lcs_surrogate_flowmap_workspace_bytes.restype = C.c_int64
+    L.lcs_surrogate_flowmap_workspace_bytes.argtypes = [P, P, D]
     L.lcs_check_tile_count.restype = C.c_int64
     L.lcs_check_tile_count.argtypes = [P]
     L.lcs_frames_interleave_floats.restype = C.c_int64
@@ -655,6 +661,19 @@ def lcs_cg_ftle(seeds, xf, T: float, flags=None, lambda_max=None, ftle=None, ste
     return lambda_max, ftle, stencil_flags
 
 
+def lcs_timing_enable(on: bool = True):
+    """Record HIP events around every launch of the library's main kernels."""
+    _check(_lib.lcs_timing_enable(1 if on else 0))
+
+
+def lcs_timing_query(kernel: str):
+    """(launches, total ms) of the recorded launches of ``kernel`` (after the
+    recorded work has completed)."""
+    n, ms = C.c_int64(), C.c_double()
+    _check(_lib.lcs_timing_query(kernel.encode(), C.byref(n), C.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
 def lcs_sync_status(stream=None):
     _check(_lib.lcs_sync_status(_stream_handle(stream)))
 
@@ -663,11 +682,13 @@ LCS_MAX_WINDOWS = 192
 
 
 class Plan:
-    """Owns an ``lcs_plan_t`` (work counter, capture stream, cached graph)."""
+    """Owns an ``lcs_plan_t`` (work counter, capture stream, cached graph, the
+    autotuner's choices; ``autotune_cache`` names the file they persist in)."""
 
-    def __init__(self):
+    def __init__(self, autotune_cache: Optional[str] = None):
         h = C.c_void_p()
-        _check(_lib.lcs_plan_create(C.byref(h)))
+        _check(_lib.lcs_plan_create(C.byref(h),
+                                    autotune_cache.encode() if autotune_cache else None))
         self.handle = h
 
     def stats(self):
@@ -685,6 +706,42 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def lcs_advect_tuned(plan: Plan, frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
+                     xf=None, cell=None, flags=None, workspace=None, candidates=None,
+                     want_cell=True, want_flags=True, stream=None):
+    """lcs_advect with the plan's autotuned seed ordering.  Returns (xf, cell,
+    flags, chosen segment length, {candidate: ms} on a tuning call else None)."""
+    torch = _torch()
+    dev = frames.u[0].device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    if xf is None:
+        xf = torch.empty((d, ns), dtype=torch.float32, device=dev)
+    if cell is None and want_cell:
+        cell = torch.empty(ns, dtype=torch.int64, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    cand = None if candidates is None else [int(c) for c in candidates]
+    nc = 5 if cand is None else len(cand)
+    carr = None if cand is None else (C.c_int32 * nc)(*cand)
+    ms = (C.c_float * nc)(*([float("nan")] * nc))
+    chosen = C.c_int32(-1)
+    sd = seed_grid_desc(seeds)
+    wsb = 0 if workspace is None else int(workspace.numel() * workspace.element_size())
+    _check(_lib.lcs_advect_tuned(plan.handle, frames.ref, C.byref(sd), float(t0), float(T),
+                                 float(dt), _ptr(xf), _ptr(cell), _ptr(flags), _ptr(workspace), wsb,
+                                 carr, nc if cand is not None else 0, C.byref(chosen), ms,
+                                 _stream_handle(stream)))
+    tuned = None
+    if any(x == x for x in ms):          # a tuning call fills the times (NaN = skipped)
+        names = cand if cand is not None else [0, 200, 100, 50, 25]
+        tuned = {int(c): (None if v != v else float(v)) for c, v in zip(names, ms)}
+    return xf, cell, flags, int(chosen.value), tuned
 
 
 def lcs_advect_batched(plan: Plan, frames: DeviceFrames, seeds, windows, dt: float,
@@ -891,6 +948,47 @@ def lcs_advect_tiles(frames: DeviceFrames, seeds, t0: float, T: float, dt: float
                                  _ptr(tile_fail), _ptr(xf), _ptr(cell), _ptr(flags),
                                  _stream_handle(stream)))
     return xf
+
+
+def lcs_surrogate_flowmap_workspace_bytes(frames: DeviceFrames, seeds,
+                                          whole_grid_fraction: float = 0.25) -> int:
+    sd = seed_grid_desc(seeds)
+    return int(_lib.lcs_surrogate_flowmap_workspace_bytes(frames.ref, C.byref(sd),
+                                                          float(whole_grid_fraction)))
+
+
+def lcs_surrogate_flowmap(mlp: Mlp, frames: DeviceFrames, seeds, t0: float, tau: float,
+                          n_windows: int, tol: float, dt: float, whole_grid_fraction: float = 0.25,
+                          xf=None, flags=None, tile_err=None, want_flags=True, workspace=None,
+                          stream=None):
+    """Composed surrogate flow map with RK4 check samples and RK4 fallback of
+    failing tiles (or of the whole grid), all inside the library.  Returns
+    (xf, flags, n_fallback_tiles, whole_grid, tile_err)."""
+    torch = _torch()
+    dev = mlp.params.device
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    nt = lcs_check_tile_count(seeds)
+    if xf is None:
+        xf = torch.empty((3, ns), dtype=torch.float32, device=dev)
+    if flags is None and want_flags:
+        flags = torch.empty(ns, dtype=torch.uint8, device=dev)
+    if tile_err is None:
+        tile_err = torch.empty(nt, dtype=torch.float32, device=dev)
+    _need(xf, torch.float32, (3, ns), "xf")
+    _need(flags, torch.uint8, (ns,), "flags")
+    _need(tile_err, torch.float32, (nt,), "tile_err")
+    if workspace is None:
+        workspace = _bytes_buffer(
+            lcs_surrogate_flowmap_workspace_bytes(frames, seeds, whole_grid_fraction), dev)
+    nf, whole = C.c_int32(), C.c_int32()
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_surrogate_flowmap(mlp.ref, frames.ref, C.byref(sd), float(t0), float(tau),
+                                      int(n_windows), float(tol), float(dt),
+                                      float(whole_grid_fraction), _ptr(xf), _ptr(flags),
+                                      _ptr(tile_err), C.byref(nf), C.byref(whole), _ptr(workspace),
+                                      int(workspace.numel() * workspace.element_size()),
+                                      _stream_handle(stream)))
+    return xf, flags, int(nf.value), bool(whole.value), tile_err
 
 
 def lcs_sub(a, b, out=None, stream=None):

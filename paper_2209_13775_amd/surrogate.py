@@ -4,8 +4,7 @@ Every arithmetic step runs in the HIP library through the C ABI: RK4 training
 pairs (lcs_advect_points), displacements (lcs_sub), network forward/backward
 (lcs_mlp_forward / lcs_mlp_backward), loss gradient (lcs_mse_grad), Adam
 (lcs_adam_step), composition over windows (lcs_surrogate_compose), check
-samples (lcs_surrogate_check), RK4 fallback (lcs_advect_tiles) and the FTLE
-(lcs_cg_ftle).  torch provides device memory, random draws of the training
+samples and RK4 fallback (lcs_surrogate_flowmap) and the FTLE (lcs_cg_ftle).  torch provides device memory, random draws of the training
 inputs and streams.
 
 The surrogate predicts the displacement over a window tau of a point starting
@@ -153,24 +152,13 @@ def surrogate_flowmap(mlp: lcs.Mlp, frames: lcs.DeviceFrames, seeds, cfg: Surrog
                       tol: float, full_fallback_fraction: float = 0.25, workspace=None,
                       stream=None):
     """Composed surrogate flow map with RK4 check samples and RK4 fallback on
-    failing tiles.  When more than ``full_fallback_fraction`` of the tiles fail,
-    the whole grid is re-advected with the re-bundled RK4 path instead (same
-    results, faster than tile by tile).  Returns (xf, flags, n_fail, tile_err)."""
-    torch = lcs._torch()
-    T = cfg.n_windows * cfg.tau
-    xf = lcs.lcs_surrogate_compose(mlp, seeds, cfg.t0, cfg.tau, cfg.n_windows, stream=stream)
-    err, fail, n_fail = lcs.lcs_surrogate_check(frames, seeds, cfg.t0, T, cfg.dt, xf, tol,
-                                                stream=stream)
-    flags = torch.zeros(xf.shape[1], dtype=torch.uint8, device=xf.device)
-    nf = int(n_fail.item())                       # host decision: one small copy
-    if nf > full_fallback_fraction * lcs.lcs_check_tile_count(seeds):
-        seg = max(1, int(round(0.5 / abs(cfg.dt))))
-        lcs.lcs_advect_sorted(frames, seeds, cfg.t0, T, cfg.dt, seg, xf, None, flags, workspace,
-                              want_cell=False, stream=stream)
-    elif nf > 0:
-        lcs.lcs_advect_tiles(frames, seeds, cfg.t0, T, cfg.dt, fail, xf, None, flags,
-                             stream=stream)
-    return xf, flags, n_fail, err
+    failing tiles (lcs_surrogate_flowmap; the fallback policy is the
+    library's: more than ``full_fallback_fraction`` of the tiles failing
+    re-advects the whole grid).  Returns (xf, flags, n_fail, tile_err)."""
+    xf, flags, nf, _, err = lcs.lcs_surrogate_flowmap(
+        mlp, frames, seeds, cfg.t0, cfg.tau, cfg.n_windows, tol, cfg.dt,
+        whole_grid_fraction=full_fallback_fraction, workspace=workspace, stream=stream)
+    return xf, flags, nf, err
 
 
 def save(mlp: lcs.Mlp, cfg: SurrogateConfig, path: str):

@@ -170,7 +170,7 @@ def test_batched_validation():
     bad2 = (lcs.lcs_window_t * 2)(lcs.lcs_window_t(0.0, 1.0), lcs.lcs_window_t(0.5, 0.35))
     assert L.lcs_advect_batched(fake_plan, C.byref(v), C.byref(s), bad2, 2, 0.1, 0x10, None,
                                 None, None) == lcs.LCS_E_STEP
-    assert L.lcs_plan_create(None) == lcs.LCS_E_ARG
+    assert L.lcs_plan_create(None, None) == lcs.LCS_E_ARG
     assert L.lcs_plan_destroy(None) == lcs.LCS_OK
 
 
@@ -276,3 +276,48 @@ def test_sorted_workspace_follows_the_bin_rule():
     assert a > 0 and b > 0 and c > 0
     assert b == c
     assert a - c == hist_bytes(24) - hist_bytes(23)
+
+
+def test_tuned_and_surrogate_flowmap_validate():
+    """lcs_advect_tuned and lcs_surrogate_flowmap reject bad arguments before
+    any device work (the fake pointers are never dereferenced)."""
+    L = lcs.lib()
+    v, s = _vel(), _seeds()
+    fake_plan = C.c_void_p(0x1)
+    c1 = (C.c_int32 * 2)(0, 100)
+    cneg = (C.c_int32 * 2)(0, -5)
+    args = lambda plan, cand, nc: (plan, C.byref(v), C.byref(s), 0.0, 1.0, 0.1, 0x10, None, None,
+                                   None, 0, cand, nc, None, None, None)
+    assert L.lcs_advect_tuned(*args(None, c1, 2)) == lcs.LCS_E_ARG
+    assert L.lcs_advect_tuned(*args(fake_plan, c1, 0)) == lcs.LCS_E_ARG
+    assert L.lcs_advect_tuned(*args(fake_plan, c1, 17)) == lcs.LCS_E_ARG
+    assert L.lcs_advect_tuned(*args(fake_plan, cneg, 2)) == lcs.LCS_E_ARG
+    v3 = _vel(dim=3, n=(6, 6, 6), periodic=7)
+    v3.spacing[0] = v3.spacing[1] = v3.spacing[2] = 1.0
+    s3 = _seeds(dim=3, n=(4, 4, 4), origin=(0.0, 0.0, 0.0), spacing=(1.5, 1.5, 1.5), periodic=7)
+    m = lcs.lcs_mlp_t()
+    m.freq, m.params, m.params_bf16 = 0x100, 0x200, 0x300
+    for a in range(4):
+        m.in_scale[a] = 1.0
+    m.out_scale = 1.0
+    ws_need = L.lcs_surrogate_flowmap_workspace_bytes(C.byref(v3), C.byref(s3), 0.25)
+    assert ws_need > L.lcs_surrogate_flowmap_workspace_bytes(C.byref(v3), C.byref(s3), 1.0) > 0
+    nf, wh = C.c_int32(), C.c_int32()
+
+    def call(mlp=C.byref(m), tol=1e-3, frac=0.25, xf=0x10, ws=0x1000, wsb=None, tau=0.5, nw=2):
+        return L.lcs_surrogate_flowmap(mlp, C.byref(v3), C.byref(s3), 0.0, tau, nw, tol, 0.1, frac,
+                                       xf, None, None, C.byref(nf), C.byref(wh), ws,
+                                       ws_need if wsb is None else wsb, None)
+    assert call(mlp=None) == lcs.LCS_E_ARG
+    assert call(tol=-1.0) == lcs.LCS_E_ARG
+    assert call(tol=float("nan")) == lcs.LCS_E_ARG
+    assert call(frac=-0.5) == lcs.LCS_E_ARG
+    assert call(xf=None) == lcs.LCS_E_ARG
+    assert call(ws=None) == lcs.LCS_E_ARG
+    assert call(nw=0) == lcs.LCS_E_ARG
+    assert call(wsb=ws_need - 1) == lcs.LCS_E_SHAPE
+    assert call(tau=1.5) == lcs.LCS_E_TIME_RANGE       # 2 x 1.5 leaves the frames' [0, 2]
+    v2 = _vel()
+    assert L.lcs_surrogate_flowmap(C.byref(m), C.byref(v2), C.byref(s), 0.0, 0.5, 2, 1e-3, 0.1,
+                                   0.25, 0x10, None, None, None, None, 0x1000, 1 << 20,
+                                   None) == lcs.LCS_E_UNSUPPORTED

@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -51,21 +52,38 @@ def test_profile_figure_reported_only_for_unchanged_sources(fake_profiles):
     src, prof = fake_profiles
     h = bench.source_hash([str(src)])
     _write(prof, [
-        {"kernel": "k<3>", "l2_hit_rate": 0.5, "td_busy": 0.9, "source_files": [str(src)],
-         "source_sha1": h},
-        {"kernel": "advection call (sorted:100)", "strategy": "sorted:100", "layout": "tpair",
+        {"kernel": "k<3>", "workload": "w1", "l2_hit_rate": 0.5, "td_busy": 0.9,
          "traffic_bytes_per_launch": 123.0, "source_files": [str(src)], "source_sha1": h},
+        {"kernel": "k<3>", "workload": "w2", "l2_hit_rate": 0.7, "source_files": [str(src)],
+         "source_sha1": h},
     ])
-    assert bench.profiled_counter("k<3>", "l2_hit_rate") == 0.5
-    assert bench.profiled_counter("k<3>", "td_busy") == 0.9
-    assert bench.profiled_counter("k<3>", "ta_busy") is None
-    assert bench.profiled_counter("other<3>", "l2_hit_rate") is None
-    assert bench.profiled_traffic("sorted:100", "tpair") == 123.0
-    assert bench.profiled_traffic("sorted:100", "soa") is None
-    assert bench.profiled_traffic("tiles", "tpair") is None
+    assert bench.profiled_record("k<3>", "w1")["l2_hit_rate"] == 0.5
+    assert bench.profiled_record("k<3>", "w1")["traffic_bytes_per_launch"] == 123.0
+    assert bench.profiled_record("k<3>", "w2")["l2_hit_rate"] == 0.7
+    assert bench.profiled_record("k<3>", "w3") is None
+    assert bench.profiled_record("other<3>", "w1") is None
+    r = bench.roofline_record("k<3>", 10.0, 4, 1000, "w1")
+    assert r["traffic"] == 123.0 and r["td_busy"] == 0.9 and r["ta_busy"] is None
+    assert abs(r["achieved"] - 768 * 1000 / 1e-2 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / bench.VL1D_PEAK_GBS) < 1e-15
+    assert abs(r["hbm_gbs"] - 123.0 / 1e-2 / 1e9) < 1e-12
     src.write_text("void k() { int changed = 1; }\n")
-    assert bench.profiled_counter("k<3>", "l2_hit_rate") is None
-    assert bench.profiled_traffic("sorted:100", "tpair") is None
+    assert bench.profiled_record("k<3>", "w1") is None
+    r = bench.roofline_record("k<3>", 10.0, 4, 1000, "w1")
+    assert r["traffic"] is None and r["hbm_gbs"] is None
+
+
+def test_stencil_sample_neighbours():
+    from paper_2209_13775_amd import inputs
+    g = inputs.SeedGrid(3, (8, 6, 5), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (True, False, True))
+    idx, c, nm, npl, allidx = bench.stencil_sample(g, 50, seed=0)
+    assert idx.size == 50 and np.all(np.diff(idx) > 0)
+    for q, s in enumerate(idx):
+        i, j, k = g.coords_of(np.array([s]))[:, 0]
+        assert nm[0][q] == g.index_of(np.array([[(i - 1) % 8], [j], [k]]))[0]
+        assert npl[1][q] == g.index_of(np.array([[i], [min(j + 1, 5)], [k]]))[0]
+        assert nm[2][q] == g.index_of(np.array([[i], [j], [(k - 1) % 5]]))[0]
+    assert set(idx) <= set(allidx) and all(set(a) <= set(allidx) for a in nm + npl)
 
 
 def test_committed_profiles_carry_their_source_hashes():
@@ -81,3 +99,26 @@ def test_committed_profiles_carry_their_source_hashes():
             for f in r["source_files"]:
                 assert os.path.exists(os.path.join(ROOT, f)), (n, f)
     assert n_recs > 0
+
+
+def test_fp64_error_table_is_zero_for_the_oracle_itself():
+    # the bench's error table, fed the oracle's own results as the "GPU" side,
+    # must report zero error (it recomputes C from the stencil positions)
+    import oracle
+    from paper_2209_13775_amd import inputs
+    fs = inputs.abc_frames(n=16, n_frames=5, dt_frame=0.5, dtype=np.float64)
+    L = 2 * np.pi
+    g = inputs.periodic_seeds(3, (12, 10, 8), (L, L, L))
+    vel = oracle.Velocity(fs)
+    xo_all, _, fl_all = oracle.advect_seeds(vel, g, 0.0, 1.0, 0.05)
+    Cm, sfl = oracle.cg_tensor(g, xo_all, fl_all)
+    lam, sig = oracle.ftle(3, Cm, 1.0)
+    idx, c, nm, npl, allidx = bench.stencil_sample(g, 40, seed=0)
+    gpu = {"xf": xo_all[:, idx].astype(np.float32).astype(np.float64), "C": Cm[:, idx],
+           "lam": lam[idx], "ftle": sig[idx], "flags": fl_all[idx], "sflags": sfl[idx]}
+    gpu["xf"] = xo_all[:, idx]
+    errs = bench.fp64_errors(oracle, g, gpu, idx, c, nm, npl, allidx, xo_all[:, allidx],
+                             fl_all[allidx], 1.0, L)
+    assert errs["clean_stencils"] == 40 and errs["flags_equal"]
+    for k in ("xf_abs", "C_rel_frobenius", "lambda_max_rel", "ftle_abs"):
+        assert errs[k]["max"] <= 1e-14, (k, errs[k])

@@ -79,3 +79,47 @@ def test_sorted_equals_plain_with_coarse_bins(lcs):
     b = lcs.lcs_advect_sorted(frames, g, 0.0, 10.0, 0.05, segment_steps=37)
     lcs.lcs_sync_status()
     assert _same(a, b)
+
+
+def test_tuned_equals_plain_and_cache_round_trip(lcs, tmp_path):
+    # the autotuner times every candidate once, keeps the fastest, writes it to
+    # the cache; a second plan reads the cache and runs the choice without
+    # timing; every run gives lcs_advect's bits
+    _say("case: autotuned advection and its cache")
+    import torch
+    fs = inputs.abc_frames(n=32, n_frames=17, dt_frame=0.5)
+    L = 2 * math.pi
+    g = inputs.periodic_seeds(3, (45, 38, 29), (L, L, L))
+    frames = lcs.DeviceFrames(fs)
+    a = lcs.lcs_advect(frames, g, 0.0, 6.0, 0.02)
+    ws = torch.empty(lcs.lcs_advect_sorted_workspace_bytes(frames, g), dtype=torch.uint8,
+                     device="cuda")
+    cache = str(tmp_path / "tune.jsonl")
+    p1 = lcs.Plan(autotune_cache=cache)
+    x1, c1, f1, seg1, ms1 = lcs.lcs_advect_tuned(p1, frames, g, 0.0, 6.0, 0.02, workspace=ws,
+                                                 candidates=[0, 100, 25])
+    lcs.lcs_sync_status()
+    assert ms1 is not None and set(ms1) == {0, 100, 25} and all(v > 0 for v in ms1.values())
+    assert seg1 == min(ms1, key=ms1.get)
+    assert _same(a, (x1, c1, f1))
+    # same plan, same workload: no timing
+    x2, c2, f2, seg2, ms2 = lcs.lcs_advect_tuned(p1, frames, g, 0.0, 6.0, 0.02, workspace=ws,
+                                                 candidates=[0, 100, 25])
+    lcs.lcs_sync_status()
+    assert ms2 is None and seg2 == seg1 and _same(a, (x2, c2, f2))
+    p1.close()
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and f'"segment_steps": {seg1}' in lines[0]
+    p2 = lcs.Plan(autotune_cache=cache)
+    x3, c3, f3, seg3, ms3 = lcs.lcs_advect_tuned(p2, frames, g, 0.0, 6.0, 0.02, workspace=ws)
+    lcs.lcs_sync_status()
+    assert ms3 is None and seg3 == seg1 and _same(a, (x3, c3, f3))
+    # without a workspace only the single launch can run
+    x4, c4, f4, seg4, _ = lcs.lcs_advect_tuned(p2, frames, g, 0.0, 4.0, 0.02,
+                                               candidates=[100, 0])
+    lcs.lcs_sync_status()
+    assert seg4 == 0
+    p2.close()
+    b = lcs.lcs_advect(frames, g, 0.0, 4.0, 0.02)
+    lcs.lcs_sync_status()
+    assert _same(b, (x4, c4, f4))
