@@ -221,6 +221,27 @@ lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
                              void *workspace, int64_t workspace_bytes, void *stream);
 
 /*
+ * lcs_advect_sorted_noalloc -- lcs_advect_sorted for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the re-bundling workspace is a fixed
+ * device array inside the library, LCS_NOALLOC_SCRATCH_BYTES (64 MiB) per
+ * device, held from library load until the process ends.  No hipMalloc,
+ * hipFree or other allocation happens in the call.  Same arithmetic and
+ * results as lcs_advect_sorted (bit-identical to lcs_advect).
+ * Every call on one device uses the same array and leaves its contents there
+ * (the histogram is cleared at the start of each call): calls that overlap on
+ * one device -- on different streams or host threads -- race and give wrong
+ * results; serialise them.
+ * Errors: those of lcs_advect_sorted, and LCS_E_SHAPE when the grid needs
+ * more workspace than the array holds (lcs_advect_sorted_workspace_bytes >
+ * LCS_NOALLOC_SCRATCH_BYTES; about 65 B per seed plus 4 B per sort bin).
+ */
+#define LCS_NOALLOC_SCRATCH_BYTES (64LL << 20)
+lcs_status lcs_advect_sorted_noalloc(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                     double t0, double T, double dt, int32_t segment_steps,
+                                     float *xf, int64_t *cell, uint8_t *flags, void *stream);
+
+/*
  * lcs_advect_points -- flow map of arbitrary points, each with its own start
  * time (Eq. 2): the same integrator as lcs_advect over the duration T.
  * Used to resume segments, to draw check samples and to produce training

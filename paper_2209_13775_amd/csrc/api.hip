@@ -1295,3 +1295,60 @@ lcs_status lcs_advect_tuned(lcs_plan_t plan, const lcs_velocity_t *vel,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// lcs_advect_sorted_noalloc: the re-bundled advection with its workspace in a
+// fixed device array of this file instead of a caller buffer.  Each device
+// that loads the library holds one copy (LCS_NOALLOC_SCRATCH_BYTES) until the
+// process ends; its device address is looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LCS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (host code must not pass
+// the array's name itself to a kernel: on the host it is only a stand-in).
+lcs_status scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return lcs::hip_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return lcs::set_error(LCS_E_UNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return lcs::hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return lcs::set_error(LCS_E_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LCS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lcs_status lcs_advect_sorted_noalloc(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
+                                     double t0, double T, double dt, int32_t segment_steps,
+                                     float *xf, int64_t *cell, uint8_t *flags, void *stream)
+{
+    lcs_status st;
+    if ((st = check_velocity(vel)) != LCS_OK) return st;
+    if ((st = check_seeds(seeds, vel->dim)) != LCS_OK) return st;
+    const long long n = seeds->n[0] * seeds->n[1] * seeds->n[2];
+    const long long need = sorted_layout(vel, n, nullptr, nullptr).bytes;
+    if (need > (long long)LCS_NOALLOC_SCRATCH_BYTES)
+        return lcs::set_error(LCS_E_SHAPE, "this grid needs %lld bytes of scratch, more than the "
+                              "%lld of lcs_advect_sorted_noalloc (use lcs_advect_sorted)",
+                              need, (long long)LCS_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if ((st = scratch_address(&ws)) != LCS_OK) return st;
+    return advect_sorted_impl(vel, seeds, 0, t0, T, dt, segment_steps, xf, cell, flags, ws,
+                              (int64_t)LCS_NOALLOC_SCRATCH_BYTES, stream);
+}
+
+}  // extern "C"

@@ -94,6 +94,7 @@ def _load(path: str = LIB_PATH):
         "lcs_surrogate_flowmap": [P, P, P, D, D, I32, D, D, D, P, P, P, P, P, P, I64, P],
         "lcs_sub": [P, P, I64, P, P],
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
+        "lcs_advect_sorted_noalloc": [P, P, D, D, D, I32, P, P, P, P],
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
         "lcs_frames_interleave": [P, C.c_uint32, I32, I32, P, P, P],
         "lcs_advect_aux": [P, P, P, D, D, D, P, P, P, P],
@@ -568,6 +569,26 @@ def lcs_advect_sorted(frames: DeviceFrames, seeds, t0: float, T: float, dt: floa
                                   int(segment_steps), _ptr(xf), _ptr(cell), _ptr(flags),
                                   _ptr(workspace), int(workspace.numel() * workspace.element_size()),
                                   _stream_handle(stream)))
+    return xf, cell, flags
+
+
+LCS_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def lcs_advect_sorted_noalloc(frames: DeviceFrames, seeds, t0: float, T: float, dt: float,
+                              segment_steps: int, xf, cell=None, flags=None, stream=None):
+    """lcs_advect_sorted with the library's fixed device scratch as workspace
+    (nothing is allocated by the call; xf / cell / flags are the caller's)."""
+    torch = _torch()
+    ns = int(seeds.n[0] * seeds.n[1] * seeds.n[2])
+    d = seeds.dim
+    _need(xf, torch.float32, (d, ns), "xf")
+    _need(cell, torch.int64, (ns,), "cell")
+    _need(flags, torch.uint8, (ns,), "flags")
+    sd = seed_grid_desc(seeds)
+    _check(_lib.lcs_advect_sorted_noalloc(frames.ref, C.byref(sd), float(t0), float(T), float(dt),
+                                          int(segment_steps), _ptr(xf), _ptr(cell), _ptr(flags),
+                                          _stream_handle(stream)))
     return xf, cell, flags
 
 
