@@ -462,6 +462,35 @@ lcs_status lcs_adam_step(float *params, const float *grads, float *m, float *v, 
  * form training displacements xf - x0.  Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
 lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *stream);
 
+/* lcs_mlp_train -- n_steps Adam steps of the surrogate on the mean squared
+ * error of its displacement (training from trajectories the integrator
+ * generated; the local flow-map approximation the paper's Sec. 4 cites).
+ * Step s (global, counting from first_step >= 1) trains on batch
+ * b = (s - 1) mod floor(n / batch): columns b*batch .. b*batch + batch - 1 of
+ * xt [device] FP32 4 x n (rows x, y, z, t; row stride n) and target [device]
+ * FP32 3 x n (displacements), with the learning rate decayed along a cosine
+ * from lr at step 1 to lr_final at step total_steps, and Adam (Kingma & Ba,
+ * bias-corrected) moments m, v [device] FP32, LCS_MLP_PARAMS each.  params and
+ * params_bf16 must be the descriptor's own buffers; both are updated after
+ * every step.  losses [device] FP64, n_steps values (or NULL): the MSE of each
+ * step's batch before its update.  grads [device] FP32 LCS_MLP_PARAMS (or
+ * NULL): the last step's gradient.  The arithmetic and rounding points are
+ * those of lcs_mlp_forward / lcs_mse_grad / lcs_mlp_backward / lcs_adam_step
+ * (BF16 operands, FP32 accumulation); every sum runs in a fixed order, so a
+ * call is bit-reproducible.  Four launches per step: forward with the loss
+ * gradient, backward through the hidden layers, weight gradients over
+ * 2048-sample chunks, and the reduction with Adam and the BF16 copies.
+ * workspace [device] of at least lcs_mlp_train_workspace_bytes(batch) bytes
+ * (about 6.2 kB per sample).  Nothing is allocated.
+ * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_HIP. */
+int64_t lcs_mlp_train_workspace_bytes(int64_t batch);
+lcs_status lcs_mlp_train(const lcs_mlp_t *mlp, float *params, uint16_t *params_bf16,
+                         const float *xt, const float *target, int64_t n, int64_t batch,
+                         int32_t first_step, int32_t n_steps, int32_t total_steps, float lr,
+                         float lr_final, float beta1, float beta2, float eps, float *m, float *v,
+                         double *losses, float *grads, void *workspace, int64_t workspace_bytes,
+                         void *stream);
+
 /*
  * Surrogate flow map of a seed grid (3D): composition, check samples, fallback.
  *

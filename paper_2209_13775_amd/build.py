@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "liblcs_hip.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "api_mlp.hip", "api_mesh.hip", "advect.hip", "cgftle.hip", "mlp.hip",
-           "mesh.hip"]
+           "mesh.hip", "train.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}",

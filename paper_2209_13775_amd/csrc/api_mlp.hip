@@ -493,3 +493,130 @@ lcs_status lcs_adam_step(float *params, const float *grads, float *m, float *v, 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Fused training: lcs_mlp_train runs Adam steps on consecutive batches of a
+// resident training set, four launches per step (train.hip).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TrainWs {
+    uint16_t *dgelu[lcs::kMlpHidden], *ht[lcs::kMlpHidden], *dzt[lcs::kMlpHidden];
+    float *dy, *part_head, *part_bias, *part_w;
+    double *part_loss;
+    long long bytes;
+};
+
+long long train_tiles(long long B) { return (B + 127) / 128; }
+
+TrainWs train_layout(long long B, void *base)
+{
+    const long long nt = train_tiles(B), Bp = nt * 128;
+    const long long nch = (Bp + lcs::kWgradChunk - 1) / lcs::kWgradChunk;
+    TrainWs w;
+    memset(&w, 0, sizeof(w));
+    char *p = static_cast<char *>(base);
+    long long off = 0;
+    auto take = [&](long long bytes) {
+        char *q = p ? p + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    for (int l = 0; l < lcs::kMlpHidden; ++l) {
+        w.dgelu[l] = reinterpret_cast<uint16_t *>(take(2 * Bp * lcs::kMlpWidth));
+        w.ht[l] = reinterpret_cast<uint16_t *>(take(2 * Bp * lcs::mlp_in_width(l)));
+        w.dzt[l] = reinterpret_cast<uint16_t *>(take(2 * Bp * lcs::kMlpWidth));
+    }
+    w.dy = reinterpret_cast<float *>(take(4 * 3 * Bp));
+    w.part_head = reinterpret_cast<float *>(take(4 * nt * lcs::kHeadPart));
+    w.part_bias = reinterpret_cast<float *>(take(4 * nt * lcs::kMlpHidden * lcs::kMlpWidth));
+    w.part_loss = reinterpret_cast<double *>(take(8 * nt));
+    w.part_w = reinterpret_cast<float *>(take(4 * nch * lcs::kMlpParams));
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lcs_mlp_train_workspace_bytes(int64_t batch)
+{
+    if (batch < 1 || batch > (1LL << 31) - 1) return 0;
+    return train_layout(batch, nullptr).bytes;
+}
+
+lcs_status lcs_mlp_train(const lcs_mlp_t *mlp, float *params, uint16_t *params_bf16, const float *xt,
+                         const float *target, int64_t n, int64_t batch, int32_t first_step,
+                         int32_t n_steps, int32_t total_steps, float lr, float lr_final, float beta1,
+                         float beta2, float eps, float *m, float *v, double *losses, float *grads,
+                         void *workspace, int64_t workspace_bytes, void *stream)
+{
+    lcs_status st;
+    if ((st = check_mlp(mlp)) != LCS_OK) return st;
+    if (!params || params != mlp->params || !params_bf16 || params_bf16 != mlp->params_bf16)
+        return lcs::set_error(LCS_E_ARG, "params and params_bf16 must be the descriptor's buffers");
+    if (!xt || !target || !m || !v || !workspace)
+        return lcs::set_error(LCS_E_ARG, "xt, target, m, v and workspace must not be NULL");
+    if (batch < 1 || batch > (1LL << 31) - 1 || n < batch)
+        return lcs::set_error(LCS_E_SHAPE, "need 1 <= batch <= n and batch < 2^31");
+    if (first_step < 1 || n_steps < 0 || total_steps < 1)
+        return lcs::set_error(LCS_E_ARG, "steps count from 1; n_steps >= 0; total_steps >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f &&
+          isfinite(lr) && isfinite(lr_final)))
+        return lcs::set_error(LCS_E_ARG, "bad Adam hyper-parameters");
+    const TrainWs need = train_layout(batch, nullptr);
+    if (workspace_bytes < need.bytes)
+        return lcs::set_error(LCS_E_SHAPE, "workspace of %lld bytes is smaller than the %lld needed",
+                              (long long)workspace_bytes, need.bytes);
+    const TrainWs w = train_layout(batch, workspace);
+    hipStream_t s = (hipStream_t)stream;
+    lcs::TrainArgs A;
+    memset(&A, 0, sizeof(A));
+    A.P = make_dev(mlp);
+    A.ld = n;
+    A.B = batch;
+    A.n_tiles = train_tiles(batch);
+    A.Bp = A.n_tiles * 128;
+    A.n_chunks = (A.Bp + lcs::kWgradChunk - 1) / lcs::kWgradChunk;
+    A.mse_scale = (float)(2.0 / (3.0 * (double)batch));
+    A.loss_mult = 1.0 / (3.0 * (double)batch);
+    for (int l = 0; l < lcs::kMlpHidden; ++l) {
+        A.dgelu[l] = w.dgelu[l];
+        A.ht[l] = w.ht[l];
+        A.dzt[l] = w.dzt[l];
+    }
+    A.dy = w.dy;
+    A.part_head = w.part_head;
+    A.part_bias = w.part_bias;
+    A.part_loss = w.part_loss;
+    A.part_w = w.part_w;
+    A.params = params;
+    A.wbf = params_bf16;
+    A.m = m;
+    A.v = v;
+    const long long nb = n / batch;
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < n_steps && e == hipSuccess; ++k) {
+        const long long step = (long long)first_step + k;
+        const long long b = (step - 1) % nb;
+        A.xt = xt + b * batch;
+        A.target = target + b * batch;
+        A.loss = losses ? losses + k : nullptr;
+        A.grads = (k + 1 == n_steps) ? grads : nullptr;
+        // cosine decay from lr (step 1) to lr_final (step total_steps)
+        const double frac = (double)(step - 1) / (double)(total_steps > 1 ? total_steps - 1 : 1);
+        lcs::AdamArgs ad;
+        ad.lr = (float)(lr_final + 0.5 * ((double)lr - lr_final) * (1.0 + cos(M_PI * fmin(frac, 1.0))));
+        ad.beta1 = beta1;
+        ad.beta2 = beta2;
+        ad.eps = eps;
+        ad.c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+        ad.c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+        e = lcs::launch_train_step(A, ad, s);
+    }
+    if (e != hipSuccess) return lcs::hip_error(e, "mlp train launch");
+    return lcs::clear_error();
+}
+
+}  // extern "C"

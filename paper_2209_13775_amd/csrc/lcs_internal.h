@@ -259,6 +259,35 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n
                        hipStream_t s);
 hipError_t launch_refresh_bf16(const float *params, uint16_t *out, hipStream_t s);
 
+// Fused training step (train.hip): forward + MSE gradient, backward-data,
+// weight gradients, then fixed-order reduction + Adam + BF16 copies.
+constexpr long long kWgradChunk = 2048;   // samples per weight-gradient partial (multiple of 128)
+struct TrainArgs {
+    MlpDev P;
+    const float *xt;          // [4][ld] inputs of the batch (already offset to its first sample)
+    const float *target;      // [3][ld] target displacements
+    long long ld;             // row stride of xt and target
+    long long B, Bp;          // samples, samples padded to whole 128-sample tiles
+    long long n_tiles, n_chunks;
+    float mse_scale;          // 2 / (3 B)
+    double loss_mult;         // 1 / (3 B)
+    uint16_t *dgelu[kMlpHidden];   // gelu'(z_l), fragment layout
+    uint16_t *ht[kMlpHidden];      // layer inputs h_l, T8 layout
+    uint16_t *dzt[kMlpHidden];     // dz_l, T8 layout
+    float *dy;                // [3][Bp] gradient at the head output
+    float *part_head;         // [n_tiles][kHeadPart]
+    float *part_bias;         // [n_tiles][kMlpHidden][256]
+    double *part_loss;        // [n_tiles]
+    float *part_w;            // [n_chunks][kMlpParams] (hidden-weight slots used)
+    float *pred;              // optional [3][B] predictions
+    float *params;            // FP32 masters (updated in place; = P.params)
+    uint16_t *wbf;            // BF16 copies (updated; = P.wbf)
+    float *m, *v;             // Adam moments
+    float *grads;             // optional: the step's gradient
+    double *loss;             // optional: the step's MSE
+};
+hipError_t launch_train_step(const TrainArgs &a, const AdamArgs &ad, hipStream_t s);
+
 // Surrogate check samples (3D): tiles of 16 x 16 x 8 seeds.
 constexpr int kCheckTile[3] = {16, 16, 8};
 

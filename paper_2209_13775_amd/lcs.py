@@ -93,6 +93,8 @@ def _load(path: str = LIB_PATH):
         "lcs_advect_tiles": [P, P, D, D, D, P, P, P, P, P],
         "lcs_surrogate_flowmap": [P, P, P, D, D, I32, D, D, D, P, P, P, P, P, P, I64, P],
         "lcs_sub": [P, P, I64, P, P],
+        "lcs_mlp_train": [P, P, P, P, P, I64, I64, I32, I32, I32, C.c_float, C.c_float,
+                          C.c_float, C.c_float, C.c_float, P, P, P, P, P, I64, P],
         "lcs_advect_sorted": [P, P, D, D, D, I32, P, P, P, P, I64, P],
         "lcs_advect_sorted_noalloc": [P, P, D, D, D, I32, P, P, P, P],
         "lcs_advect_ab": [P, P, I32, D, D, D, P, P, P, P],
@@ -140,6 +142,8 @@ def _load(path: str = LIB_PATH):
     L.lcs_frames_interleave_floats.restype = C.c_int64
     L.lcs_frames_interleave_floats.argtypes = [P, C.c_uint32, I32]
     L.lcs_mlp_backward_scratch_bytes.argtypes = [I64]
+    L.lcs_mlp_train_workspace_bytes.restype = C.c_int64
+    L.lcs_mlp_train_workspace_bytes.argtypes = [I64]
     return L
 
 
@@ -911,6 +915,37 @@ def lcs_adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, ep
     _check(_lib.lcs_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), n, float(lr),
                               float(beta1), float(beta2), float(eps), int(step),
                               _stream_handle(stream)))
+
+
+def lcs_mlp_train_workspace_bytes(batch: int) -> int:
+    return int(_lib.lcs_mlp_train_workspace_bytes(int(batch)))
+
+
+def lcs_mlp_train(mlp: Mlp, xt, target, batch: int, first_step: int, n_steps: int,
+                  total_steps: int, m, v, lr=2e-3, lr_final=1e-4, beta1=0.9, beta2=0.999,
+                  eps=1e-8, losses=None, grads=None, workspace=None, stream=None):
+    """n_steps fused Adam steps on consecutive batches of (xt [4, n], target [3, n]);
+    returns (losses [n_steps] f64 or None, grads or None)."""
+    torch = _torch()
+    n = int(xt.shape[1])
+    dev = xt.device
+    _need(xt, torch.float32, (4, n), "xt")
+    _need(target, torch.float32, (3, n), "target")
+    for t, nm in ((m, "m"), (v, "v")):
+        _need(t, torch.float32, (LCS_MLP_PARAMS,), nm)
+    if losses is not None:
+        _need(losses, torch.float64, (n_steps,), "losses")
+    if grads is not None:
+        _need(grads, torch.float32, (LCS_MLP_PARAMS,), "grads")
+    if workspace is None:
+        workspace = _bytes_buffer(lcs_mlp_train_workspace_bytes(batch), dev)
+    _check(_lib.lcs_mlp_train(mlp.ref, _ptr(mlp.params), _ptr(mlp.bf16), _ptr(xt), _ptr(target), n,
+                              int(batch), int(first_step), int(n_steps), int(total_steps),
+                              float(lr), float(lr_final), float(beta1), float(beta2), float(eps),
+                              _ptr(m), _ptr(v), _ptr(losses), _ptr(grads), _ptr(workspace),
+                              int(workspace.numel() * workspace.element_size()),
+                              _stream_handle(stream)))
+    return losses, grads
 
 
 def lcs_check_tile_count(seeds) -> int:

@@ -1,9 +1,9 @@
 """Training and use of the learned flow-map surrogate (orchestration only).
 
 Every arithmetic step runs in the HIP library through the C ABI: RK4 training
-pairs (lcs_advect_points), displacements (lcs_sub), network forward/backward
-(lcs_mlp_forward / lcs_mlp_backward), loss gradient (lcs_mse_grad), Adam
-(lcs_adam_step), composition over windows (lcs_surrogate_compose), check
+pairs (lcs_advect_points), displacements (lcs_sub), the training steps
+(lcs_mlp_train: forward, loss gradient, backward, Adam), evaluation
+(lcs_mlp_forward, lcs_mse_grad), composition over windows (lcs_surrogate_compose), check
 samples and RK4 fallback (lcs_surrogate_flowmap) and the FTLE (lcs_cg_ftle).  torch provides device memory, random draws of the training
 inputs and streams.
 
@@ -95,41 +95,26 @@ class TrainLog:
 
 def train(mlp: lcs.Mlp, xt, dx, epochs: int, batch: int = 65536, lr: float = 2e-3,
           lr_final: float = 1e-4, val=None, log_every: int = 50) -> TrainLog:
-    """Adam on the MSE of the displacement, cosine learning-rate decay."""
+    """Adam on the MSE of the displacement, cosine learning-rate decay: one
+    lcs_mlp_train call runs every step (batches in order, epoch after epoch)."""
     torch = lcs._torch()
     n = int(xt.shape[1])
     nb = n // batch
     total = epochs * nb
     m = torch.zeros_like(mlp.params)
     v = torch.zeros_like(mlp.params)
-    ws = torch.empty(lcs.lcs_mlp_workspace_bytes(batch, True), dtype=torch.uint8, device=xt.device)
-    scratch = torch.empty(lcs.lcs_mlp_backward_scratch_bytes(batch), dtype=torch.uint8,
-                          device=xt.device)
-    out = torch.empty((3, batch), dtype=torch.float32, device=xt.device)
-    grad_out = torch.empty_like(out)
-    grads = torch.empty_like(mlp.params)
-    loss = torch.empty(1, dtype=torch.float64, device=xt.device)
+    losses = torch.empty(total, dtype=torch.float64, device=xt.device)
+    ws = torch.empty(lcs.lcs_mlp_train_workspace_bytes(batch), dtype=torch.uint8, device=xt.device)
     log = TrainLog()
     torch.cuda.synchronize()
     t = time.perf_counter()
-    step = 0
-    for ep in range(epochs):
-        for b in range(nb):
-            step += 1
-            xb = xt[:, b * batch:(b + 1) * batch].contiguous()
-            yb = dx[:, b * batch:(b + 1) * batch].contiguous()
-            lcs.lcs_mlp_forward(mlp, xb, out, ws, training=True)
-            lcs.lcs_mse_grad(out, yb, grad_out, loss)
-            lcs.lcs_mlp_backward(mlp, ws, grad_out, grads, scratch)
-            frac = (step - 1) / max(1, total - 1)
-            lr_t = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * frac))
-            lcs.lcs_adam_step(mlp.params, grads, m, v, step, lr=lr_t)
-            mlp.refresh()
-            if step % log_every == 0 or step == total:
-                log.losses.append((step, float(loss.item())))
+    lcs.lcs_mlp_train(mlp, xt, dx, batch, 1, total, total, m, v, lr=lr, lr_final=lr_final,
+                      losses=losses, workspace=ws)
     torch.cuda.synchronize()
-    log.steps = step
     log.seconds = time.perf_counter() - t
+    log.steps = total
+    lh = losses.cpu().numpy()
+    log.losses = [(k, float(lh[k - 1])) for k in range(1, total + 1) if k % log_every == 0 or k == total]
     if val is not None:
         log.val_loss = evaluate(mlp, *val)
     return log

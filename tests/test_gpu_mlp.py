@@ -174,3 +174,105 @@ def test_short_training_reduces_loss(lcs, torch):
     lcs.lcs_sync_status()
     _say(f"losses {losses}")
     assert losses[-1] < 0.1 * losses[0]
+
+
+def _cosine_lr(step, total, lr, lr_final):
+    frac = (step - 1) / max(1, total - 1)
+    return lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * min(frac, 1.0)))
+
+
+@pytest.mark.parametrize("n", [6000, 300, 4096])
+def test_fused_train_step_matches_reference(lcs, torch, n):
+    # one fused step (lcs_mlp_train): the loss and every gradient tensor
+    # against the FP64 reference at the same BF16 rounding points, the update
+    # against Adam applied to that gradient, the BF16 copies against the
+    # rounded masters; a repeat from the same state is bit-identical
+    _say(f"case: fused training step, batch {n}")
+    params, freq = _model(5)
+    xt = _inputs(n, 6)
+    rng = np.random.default_rng(11)
+    target = (rng.standard_normal((3, n)) * 0.3).astype(np.float32)
+    dxt, dtg = torch.from_numpy(xt).cuda(), torch.from_numpy(target).cuda()
+    outs = []
+    for rep in range(2):
+        mlp = lcs.Mlp(params, freq, SHIFT, SCALE, OUT_SCALE)
+        m = torch.zeros_like(mlp.params)
+        v = torch.zeros_like(mlp.params)
+        losses = torch.empty(1, dtype=torch.float64, device="cuda")
+        grads = torch.empty_like(mlp.params)
+        lcs.lcs_mlp_train(mlp, dxt, dtg, n, 1, 1, 1, m, v, lr=2e-3, losses=losses, grads=grads)
+        lcs.lcs_sync_status()
+        outs.append((mlp.params.clone(), mlp.bf16.clone(), m.clone(), v.clone(), grads.clone(),
+                     float(losses.item())))
+    for a, b in zip(outs[0][:5], outs[1][:5]):
+        assert torch.equal(a, b), "fused training step is not deterministic"
+    p_new, bf_new, m_new, v_new, g, loss = outs[0]
+    po = _oracle_params(params)
+    y, cache = M.forward(po, freq.astype(np.float64), xt.astype(np.float64), SHIFT, SCALE,
+                         OUT_SCALE, round_bf16=M.round_to_bf16)
+    L, dy = M.mse(y, target.astype(np.float64))
+    _say(f"loss {loss:.6e} reference {L:.6e}")
+    assert abs(loss - L) <= 2e-2 * L
+    gr = M.backward(po, cache, dy)
+    gg = g.cpu().numpy().astype(np.float64)
+    off = 0
+    for t, s in enumerate(M.SHAPES):
+        k = int(np.prod(s))
+        err = _rel(gg[off:off + k], gr[off:off + k])
+        _say(f"grad tensor {t} {s}: rel err {err:.2e}")
+        assert err <= 2e-2, (t, err)
+        off += k
+    rp, rm, rv = M.adam(params.astype(np.float64), gg, np.zeros_like(gg), np.zeros_like(gg), 1,
+                        lr=2e-3)
+    np.testing.assert_allclose(p_new.cpu().numpy(), rp, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(m_new.cpu().numpy(), rm, rtol=1e-6, atol=1e-12)
+    # 1 - beta2 rounded to FP32 (0.999f) is 1.3e-5 off 0.001 in relative terms
+    np.testing.assert_allclose(v_new.cpu().numpy(), rv, rtol=5e-5, atol=1e-15)
+    # BF16 copies of the updated masters, both layouts
+    got = bf_new.cpu().numpy().view(np.uint16)
+    pn = p_new.cpu().numpy()
+    off_b = off_p = 0
+    for t in range(M.N_HIDDEN):
+        K, N = M.SHAPES[2 * t]
+        W = pn[off_p:off_p + K * N].reshape(K, N)
+        want = M.round_to_bf16(W).astype(np.float32).view(np.uint32) >> 16
+        np.testing.assert_array_equal(got[off_b:off_b + K * N].reshape(K, N), want)
+        np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N].reshape(N, K), want.T)
+        off_b += 2 * K * N
+        off_p += K * N + N
+
+
+def test_fused_train_steps_resume_and_schedule(lcs, torch):
+    # five steps over three batches in one call equal five one-step calls
+    # (batch order, cosine schedule and moments carried across calls), and the
+    # last step is Adam at the scheduled rate on the gradient it reports
+    n, batch, total = 3 * 2048, 2048, 5
+    _say("case: fused training, 5 steps over 3 batches")
+    params, freq = _model(7)
+    xt = torch.from_numpy(_inputs(n, 8)).cuda()
+    rng = np.random.default_rng(12)
+    target = torch.from_numpy((rng.standard_normal((3, n)) * 0.3).astype(np.float32)).cuda()
+    a = lcs.Mlp(params, freq, SHIFT, SCALE, OUT_SCALE)
+    ma, va = torch.zeros_like(a.params), torch.zeros_like(a.params)
+    la = torch.empty(total, dtype=torch.float64, device="cuda")
+    lcs.lcs_mlp_train(a, xt, target, batch, 1, total, total, ma, va, lr=3e-3, lr_final=2e-4,
+                      losses=la)
+    b = lcs.Mlp(params, freq, SHIFT, SCALE, OUT_SCALE)
+    mb, vb = torch.zeros_like(b.params), torch.zeros_like(b.params)
+    lb = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(b.params)
+    for step in range(1, total + 1):
+        if step == total:
+            p_before, m_before, v_before = b.params.clone(), mb.clone(), vb.clone()
+        lcs.lcs_mlp_train(b, xt, target, batch, step, 1, total, mb, vb, lr=3e-3, lr_final=2e-4,
+                          losses=lb, grads=g if step == total else None)
+        assert float(lb.item()) == float(la[step - 1].item())
+    lcs.lcs_sync_status()
+    assert torch.equal(a.params, b.params) and torch.equal(a.bf16, b.bf16)
+    assert torch.equal(ma, mb) and torch.equal(va, vb)
+    lr5 = _cosine_lr(total, total, 3e-3, 2e-4)
+    rp, _, _ = M.adam(p_before.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64),
+                      m_before.cpu().numpy().astype(np.float64),
+                      v_before.cpu().numpy().astype(np.float64), total, lr=lr5)
+    np.testing.assert_allclose(b.params.cpu().numpy(), rp, rtol=1e-6, atol=1e-7)
+    assert bool(torch.isfinite(la).all())
