@@ -502,7 +502,7 @@ namespace {
 
 struct TrainWs {
     uint16_t *dgelu[lcs::kMlpHidden], *ht[lcs::kMlpHidden], *dzt[lcs::kMlpHidden];
-    float *dy, *part_head, *part_bias, *part_w;
+    float *dy, *part_head, *part_w;
     double *part_loss;
     long long bytes;
 };
@@ -529,7 +529,6 @@ TrainWs train_layout(long long B, void *base)
     }
     w.dy = reinterpret_cast<float *>(take(4 * 3 * Bp));
     w.part_head = reinterpret_cast<float *>(take(4 * nt * lcs::kHeadPart));
-    w.part_bias = reinterpret_cast<float *>(take(4 * nt * lcs::kMlpHidden * lcs::kMlpWidth));
     w.part_loss = reinterpret_cast<double *>(take(8 * nt));
     w.part_w = reinterpret_cast<float *>(take(4 * nch * lcs::kMlpParams));
     w.bytes = off;
@@ -588,7 +587,6 @@ lcs_status lcs_mlp_train(const lcs_mlp_t *mlp, float *params, uint16_t *params_b
     }
     A.dy = w.dy;
     A.part_head = w.part_head;
-    A.part_bias = w.part_bias;
     A.part_loss = w.part_loss;
     A.part_w = w.part_w;
     A.params = params;

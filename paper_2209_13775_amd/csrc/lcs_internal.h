@@ -276,9 +276,8 @@ struct TrainArgs {
     uint16_t *dzt[kMlpHidden];     // dz_l, T8 layout
     float *dy;                // [3][Bp] gradient at the head output
     float *part_head;         // [n_tiles][kHeadPart]
-    float *part_bias;         // [n_tiles][kMlpHidden][256]
     double *part_loss;        // [n_tiles]
-    float *part_w;            // [n_chunks][kMlpParams] (hidden-weight slots used)
+    float *part_w;            // [n_chunks][kMlpParams] gradient partials per sample chunk
     float *pred;              // optional [3][B] predictions
     float *params;            // FP32 masters (updated in place; = P.params)
     uint16_t *wbf;            // BF16 copies (updated; = P.wbf)

@@ -9,11 +9,12 @@
 //                        head's gradient and the loss as per-tile partials
 //   train_bwd_kernel     per 128 samples: back-propagation through the hidden
 //                        layers on MFMA (activation gradients in LDS); stores
-//                        dz of every layer and the bias-gradient partials
-//   train_wgrad_kernel   dW_l = h_l^T dz_l for the four layers over chunks of
-//                        2048 samples (MFMA, fragments loaded straight from
-//                        the stored layouts)
-//   train_update_kernel  fixed-order sums of the partials, Adam, and the BF16
+//                        dz of every layer
+//   train_wgrad_kernel   per chunk of 2048 samples: dW_l = h_l^T dz_l for the
+//                        four layers (MFMA, fragments loaded straight from the
+//                        stored layouts), the bias sums of dz_l, and the head
+//                        partials of the chunk's tiles summed
+//   train_update_kernel  chunk partials summed in order, Adam, and the BF16
 //                        copies of the updated hidden matrices
 //
 // Layouts in the workspace (batch padded to whole 128-sample tiles, Bp):
@@ -40,6 +41,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int kTS = 128;                    // samples per tile
 constexpr int kStr = kMlpWidth + 8;         // BF16 per LDS activation row (16-byte aligned rows)
 constexpr long long kFragTile = (long long)kTS * kMlpWidth;   // BF16 per tile and layer
+constexpr int kWgradTiles = 2 + 4 * (kMlpHidden - 1);          // 128 x 128 weight-gradient tiles
 
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -113,23 +115,17 @@ __device__ __forceinline__ void tile_product(const uint16_t *__restrict__ Arows,
     }
 }
 
-// The tile's LDS activations (128 x K) written to a T8 array of K columns, and
-// (colsum != NULL) the sum of each column over the tile's samples in sample
-// order.  Thread t takes column t % K.
+// The tile's LDS activations (128 x K) written to a T8 array of K columns;
+// thread t takes column t % K.
 template <int K>
 __device__ __forceinline__ void store_t8(const uint16_t *act, uint16_t *__restrict__ out, long long tile,
-                                         int tid, float *colsum)
+                                         int tid)
 {
     const int k = tid % K;
-    float s = 0.0f;
     for (int g = tid / K; g < kTS / 8; g += 256 / K) {
         uint16_t v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = act[(8 * g + q) * kStr + k];
-        if (colsum) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) s += bf2f(v[q]);
-        }
         uint4 w;
         w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
         w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
@@ -137,7 +133,6 @@ __device__ __forceinline__ void store_t8(const uint16_t *act, uint16_t *__restri
         w.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
         *reinterpret_cast<uint4 *>(out + ((tile * (kTS / 8) + g) * K + k) * 8) = w;
     }
-    if (colsum) *colsum = s;
 }
 
 // offset (BF16 elements) of a lane's 4 values of block (i, j) in the fragment layout
@@ -176,7 +171,7 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
         act[m * kStr + kMlpFreq + f] = __builtin_bit_cast(uint16_t, (__bf16)__builtin_amdgcn_sinf(r));
     }
     __syncthreads();
-    store_t8<kMlpFeat>(act, A.ht[0], tile, tid, nullptr);
+    store_t8<kMlpFeat>(act, A.ht[0], tile, tid);
     for (int l = 0; l < kMlpHidden; ++l) {
         const float *bias = P.params + mlp_off_b(l);
         f32x4 acc[8][4];
@@ -208,7 +203,7 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
             }
         }
         __syncthreads();
-        if (l + 1 < kMlpHidden) store_t8<kMlpWidth>(act, A.ht[l + 1], tile, tid, nullptr);
+        if (l + 1 < kMlpHidden) store_t8<kMlpWidth>(act, A.ht[l + 1], tile, tid);
     }
     // head (FP32): two threads per sample, halves of the 256 inputs uniform per
     // wave so the head weights are scalar loads
@@ -318,9 +313,7 @@ __global__ __launch_bounds__(256, 2) void train_bwd_kernel(TrainArgs A)
         }
     }
     __syncthreads();
-    float cs;
-    store_t8<kMlpWidth>(act, A.dzt[top], tile, tid, &cs);
-    A.part_bias[tile * (kMlpHidden * kMlpWidth) + top * kMlpWidth + tid] = cs;
+    store_t8<kMlpWidth>(act, A.dzt[top], tile, tid);
     for (int l = top; l >= 1; --l) {
         // dh_l = dz_l W_l^T: out^T[k][m] = sum_n W_l[k][n] dz_l[m][n], W_l rows as stored ([in][out])
         f32x4 acc[8][4];
@@ -344,25 +337,55 @@ __global__ __launch_bounds__(256, 2) void train_bwd_kernel(TrainArgs A)
             }
         }
         __syncthreads();
-        store_t8<kMlpWidth>(act, A.dzt[l - 1], tile, tid, &cs);
-        A.part_bias[tile * (kMlpHidden * kMlpWidth) + (l - 1) * kMlpWidth + tid] = cs;
+        store_t8<kMlpWidth>(act, A.dzt[l - 1], tile, tid);
     }
 }
 
-// Weight-gradient partials: part[c][off_w(l) + k*256 + n] = sum over the rows m
-// of chunk c of h_l[m][k] dz_l[m][n].  Block = one 128 x 128 output tile of
-// one layer (layer 0: 128 x 256 -> 2 tiles, the others 4) and one chunk; four
-// waves as 2 x 2 of 64 x 64.  Fragments come straight from the T8 arrays.
+// Sum of a fragment's eight BF16 values, in order
+__device__ __forceinline__ float sum8(const bf16x8 &v)
+{
+    const uint4 u = __builtin_bit_cast(uint4, v);
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+    float s = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s += __uint_as_float(w[e] << 16);
+        s += __uint_as_float(w[e] & 0xffff0000u);
+    }
+    return s;
+}
+
+// Gradient partials of chunk c (rows c*2048 .. +2047), part[c][i] in the
+// parameter layout:
+//  * hidden weights: part[c][off_w(l) + k*256 + n] = sum over the chunk's rows m
+//    of h_l[m][k] dz_l[m][n].  Block = one 128 x 128 output tile of one layer
+//    (layer 0: 128 x 256 -> 2 tiles, the others 4) and one chunk; four waves
+//    as 2 x 2 of 64 x 64; fragments come straight from the T8 arrays.
+//  * hidden biases: part[c][off_b(l) + n] = sum over the rows of dz_l[m][n], by
+//    the waves whose tile starts at k = 0, from the dz fragments they load
+//    (per lane in row order, then the four lane groups in a fixed order).
+//  * head: part[c][off_h + p] = sum of the per-tile head partials of the
+//    chunk's tiles in tile order (the last block of each chunk).
 __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
 {
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     int t = blockIdx.x;
+    const long long mb = (long long)blockIdx.y * kWgradChunk;
+    const long long me = min(mb + kWgradChunk, A.Bp);
+    if (t == kWgradTiles) {
+        const long long t0 = mb / kTS, t1 = me / kTS;
+        for (int p = threadIdx.x; p < kHeadPart; p += 256) {
+            float s = 0.0f;
+            for (long long q = t0; q < t1; ++q) s += A.part_head[q * kHeadPart + p];
+            A.part_w[(long long)blockIdx.y * kMlpParams + kOffWh + p] = s;
+        }
+        return;
+    }
     const int l = t < 2 ? 0 : 1 + (t - 2) / 4;
     if (l > 0) t = (t - 2) % 4;
     const int K = mlp_in_width(l);
     const int k0 = (t / 2) * 128 + (wave / 2) * 64, n0 = (t % 2) * 128 + (wave % 2) * 64;
-    const long long mb = (long long)blockIdx.y * kWgradChunk;
-    const long long me = min(mb + kWgradChunk, A.Bp);
+    const bool bias_wave = (k0 == 0);      // wave-uniform
     const uint16_t *H = A.ht[l];
     const uint16_t *D = A.dzt[l];
     f32x4 acc[4][4];
@@ -370,6 +393,7 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     auto load = [&](long long m, bf16x8 *a, bf16x8 *b) {
         const long long g = m / 8 + lane / 16;
 #pragma unroll
@@ -379,26 +403,29 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
         for (int j = 0; j < 4; ++j)
             b[j] = *reinterpret_cast<const bf16x8 *>(D + (g * kMlpWidth + n0 + 16 * j + lane % 16) * 8);
     };
+    auto step = [&](const bf16x8 *a, const bf16x8 *b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (bias_wave) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bsum[j] += sum8(b[j]);
+        }
+    };
     bf16x8 a0[4], b0[4], a1[4], b1[4];
     load(mb, a0, b0);
     for (long long m = mb; m < me; m += 64) {
         // rows come in whole tiles of 128, so a chunk holds a multiple of 64 rows
         load(m + 32, a1, b1);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[i], b0[j], acc[i][j], 0, 0, 0);
+        step(a0, b0);
         if (m + 64 < me) load(m + 64, a0, b0);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[i], b1[j], acc[i][j], 0, 0, 0);
+        step(a1, b1);
     }
-    float *out = A.part_w + (long long)blockIdx.y * kMlpParams + mlp_off_w(l);
+    float *out = A.part_w + (long long)blockIdx.y * kMlpParams;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -407,62 +434,48 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int k = k0 + 16 * i + 4 * (lane / 16) + e;
-                out[(long long)k * kMlpWidth + n] = acc[i][j][e];
+                out[mlp_off_w(l) + (long long)k * kMlpWidth + n] = acc[i][j][e];
             }
         }
+    if (bias_wave) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // lane groups g = lane / 16 hold rows 8g .. 8g+7 of every 32: (g0 + g1) + (g2 + g3)
+            float v = bsum[j] + __shfl_xor(bsum[j], 16);
+            v = v + __shfl_xor(v, 32);
+            if (lane < 16) out[mlp_off_b(l) + n0 + 16 * j + lane] = v;
+        }
+    }
 }
 
-// Gradient of every parameter (fixed-order sums of the partials), Adam, and
-// the BF16 copies.  Block = 64 consecutive parameters x 4 partial groups;
-// group q sums partials q, q+4, q+8, ... in order, and the four group sums are
-// added in group order.
+// Gradient of every parameter (the chunk partials summed in chunk order), Adam,
+// and the BF16 copies; block 0 also sums the per-tile losses (fixed tree).
 __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs ad)
 {
-    __shared__ float gs[4][64];
     __shared__ double ls[256];
-    const int p = threadIdx.x % 64, q = threadIdx.x / 64;
-    const long long i = (long long)blockIdx.x * 64 + p;
-    float s = 0.0f;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < kMlpParams) {
-        // which parameter: hidden weight, hidden bias, head weight or head bias
+        float g = 0.0f;
+        for (int c = 0; c < A.n_chunks; ++c) g += A.part_w[(long long)c * kMlpParams + i];
+        if (A.grads) A.grads[i] = g;
+        const float mi = ad.beta1 * A.m[i] + (1.0f - ad.beta1) * g;
+        const float vi = ad.beta2 * A.v[i] + (1.0f - ad.beta2) * g * g;
+        A.m[i] = mi;
+        A.v[i] = vi;
+        const float pi = A.params[i] - ad.lr * (mi * ad.c1) / (sqrtf(vi * ad.c2) + ad.eps);
+        A.params[i] = pi;
+        // BF16 copies of the hidden weights: [in][out] and [out][in]
         int l = 0;
         while (l + 1 < kMlpHidden && i >= mlp_off_w(l + 1)) ++l;
         if (i < kOffWh && i < mlp_off_b(l)) {
-            for (int c = q; c < A.n_chunks; c += 4) s += A.part_w[(long long)c * kMlpParams + i];
-        } else if (i < kOffWh) {
-            const long long o = l * kMlpWidth + (i - mlp_off_b(l));
-            for (long long c = q; c < A.n_tiles; c += 4) s += A.part_bias[c * (kMlpHidden * kMlpWidth) + o];
-        } else {
-            const long long o = i - kOffWh;
-            for (long long c = q; c < A.n_tiles; c += 4) s += A.part_head[c * kHeadPart + o];
+            const long long r = i - mlp_off_w(l);
+            const int K = mlp_in_width(l);
+            const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
+            const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
+            A.wbf[mlp_off_bf16(l) + r] = b;
+            A.wbf[mlp_off_bf16(l) + (long long)K * kMlpWidth + (long long)n * K + k] = b;
         }
     }
-    gs[q][p] = s;
-    __syncthreads();
-    if (q == 0 && i < kMlpParams) {
-        const float g = ((gs[0][p] + gs[1][p]) + gs[2][p]) + gs[3][p];
-        if (A.grads) A.grads[i] = g;
-        {
-            const float mi = ad.beta1 * A.m[i] + (1.0f - ad.beta1) * g;
-            const float vi = ad.beta2 * A.v[i] + (1.0f - ad.beta2) * g * g;
-            A.m[i] = mi;
-            A.v[i] = vi;
-            const float pi = A.params[i] - ad.lr * (mi * ad.c1) / (sqrtf(vi * ad.c2) + ad.eps);
-            A.params[i] = pi;
-            // BF16 copies of hidden weights: [in][out] and [out][in]
-            int l = 0;
-            while (l + 1 < kMlpHidden && i >= mlp_off_w(l + 1)) ++l;
-            if (i < kOffWh && i < mlp_off_b(l)) {
-                const long long r = i - mlp_off_w(l);
-                const int K = mlp_in_width(l);
-                const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
-                const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
-                A.wbf[mlp_off_bf16(l) + r] = b;
-                A.wbf[mlp_off_bf16(l) + (long long)K * kMlpWidth + (long long)n * K + k] = b;
-            }
-        }
-    }
-    // block 0 also sums the loss partials (fixed tree)
     if (blockIdx.x == 0 && A.loss) {
         double v = 0.0;
         for (long long c = threadIdx.x; c < A.n_tiles; c += 256) v += A.part_loss[c];
@@ -493,13 +506,13 @@ hipError_t launch_train_step(const TrainArgs &a, const AdamArgs &ad, hipStream_t
     }
     {
         LaunchTimer timer("train_wgrad_kernel", s);
-        hipLaunchKernelGGL(train_wgrad_kernel, dim3(2 + 4 * (kMlpHidden - 1), (unsigned)a.n_chunks),
+        hipLaunchKernelGGL(train_wgrad_kernel, dim3(kWgradTiles + 1, (unsigned)a.n_chunks),
                            dim3(256), 0, s, a);
         timer.stop(s);
     }
     {
         LaunchTimer timer("train_update_kernel", s);
-        hipLaunchKernelGGL(train_update_kernel, dim3((unsigned)((kMlpParams + 63) / 64)), dim3(256), 0,
+        hipLaunchKernelGGL(train_update_kernel, dim3((unsigned)((kMlpParams + 255) / 256)), dim3(256), 0,
                            s, a, ad);
         timer.stop(s);
     }
