@@ -13,8 +13,10 @@ and a short training run.
   seeds;
 * the composition matches the FP64 reference network iterated over the
   windows at sampled seeds (relative error of the displacement <= 1e-2);
-* after a short training run on a smooth field the hybrid FTLE is within
-  1e-2 (mean absolute) of plain RK4, and the validation loss has dropped.
+* training on the smooth ABC field: the validation loss drops 1000-fold, the
+  composition alone comes within 2e-2 (mean FTLE) of plain RK4, a loose
+  tolerance accepts part of the tiles and improves on the composition, and
+  the 1e-3 tolerance rejects every tile (plain RK4 bit for bit).
 """
 import math
 import sys
@@ -198,29 +200,42 @@ def test_composition_matches_reference_network(env):
     assert rel <= 1e-2
 
 
-def test_training_and_hybrid_ftle(env):
+def test_training_gain_and_fallback_frontier(env):
+    # what training buys on the smooth ABC field, measured against plain RK4
+    # over the same interval (the reference the check samples use):
+    #  * the validation loss drops by three orders of magnitude;
+    #  * the composition alone reaches a mean FTLE error within 2e-2 of RK4;
+    #  * at a tolerance of 1e-1 part of the tiles are accepted and the rest
+    #    re-advected, and the hybrid's FTLE error is below the composition's;
+    #  * at the 1e-3 tolerance every tile falls back (the network's per-window
+    #    error compounds over 8 windows to well above 1e-3), and the result
+    #    is plain RK4 bit for bit.
     torch, lcs, sur, fs, frames, cfg = env
-    _say("case: short surrogate training on the ABC field")
+    _say("case: surrogate training on the ABC field, then the accept / fallback frontier")
     mlp = sur.new_model(cfg)
-    xt, dx, fl = sur.training_data(frames, cfg, 1 << 19, seed=1)
+    xt, dx, fl = sur.training_data(frames, cfg, 1 << 20, seed=1)
     vxt, vdx, _ = sur.training_data(frames, cfg, 1 << 16, seed=2)
     assert not bool(fl.any())
     before = sur.evaluate(mlp, vxt, vdx)
-    log = sur.train(mlp, xt, dx, epochs=6, batch=16384, lr=3e-3, val=(vxt, vdx))
-    rms = float(np.sqrt(before))
-    _say(f"val MSE {before:.3e} -> {log.val_loss:.3e} in {log.seconds:.1f} s ({log.steps} steps)")
-    assert log.val_loss < 0.05 * before
+    log = sur.train(mlp, xt, dx, epochs=16, batch=16384, lr=3e-3, val=(vxt, vdx))
+    _say(f"val MSE {before:.3e} -> {log.val_loss:.3e} in {log.seconds:.2f} s ({log.steps} steps)")
+    assert log.val_loss < 1e-3 * before
     g = _seeds((64, 64, 32))
     T = cfg.n_windows * cfg.tau
+    nt = lcs.lcs_check_tile_count(g)
     ref, _, rfl = lcs.lcs_advect(frames, g, cfg.t0, T, cfg.dt)
-    _, rsig, rsfl = lcs.lcs_cg_ftle(g, ref, T, flags=rfl)
-    for tol in [1e-3, 1e-2]:
-        xf, flags, n_fail, err = sur.surrogate_flowmap(mlp, frames, g, cfg, tol=tol)
-        n_fail = torch.tensor([n_fail])
-        _, sig, sfl = lcs.lcs_cg_ftle(g, xf, T, flags=flags)
+    _, rsig, _ = lcs.lcs_cg_ftle(g, ref, T, flags=rfl)
+    res = {}
+    for tol in [float("inf"), 1e-1, 1e-3]:
+        xf, flags, n_fail, err = sur.surrogate_flowmap(mlp, frames, g, cfg, tol=tol,
+                                                       full_fallback_fraction=1.0)
+        _, sig, _ = lcs.lcs_cg_ftle(g, xf, T, flags=flags)
         lcs.lcs_sync_status()
         e = (sig - rsig).abs()
-        nt = lcs.lcs_check_tile_count(g)
-        _say(f"tol {tol}: fallback {int(n_fail.item())}/{nt} tiles, FTLE err mean "
-             f"{e.mean().item():.2e} max {e.max().item():.2e}")
-        assert e.mean().item() <= 1e-2
+        res[tol] = (n_fail, float(e.mean().item()), xf)
+        _say(f"tol {tol}: fallback {n_fail}/{nt} tiles, median tile error "
+             f"{float(err.median().item()):.3e}, FTLE err mean {e.mean().item():.2e} "
+             f"max {e.max().item():.2e}")
+    assert res[float("inf")][0] == 0 and res[float("inf")][1] <= 2e-2
+    assert 0 < res[1e-1][0] < nt and res[1e-1][1] < res[float("inf")][1]
+    assert res[1e-3][0] == nt and torch.equal(res[1e-3][2], ref)
