@@ -435,12 +435,15 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
     return make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi));
 }
 
-__global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
+constexpr int kCT = 512;                  // threads per composition workgroup (8 waves)
+
+__global__ __launch_bounds__(kCT, 2) void compose_fused_kernel(ComposeArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t act[kFT * kActStride];
     __shared__ float xs[3][kFT];
     __shared__ float yp[3][kFT];
     static_assert(2 * kFT == 256 && kMlpWidth == 256, "the head splits 256 inputs over 2 x 128 threads");
+    static_assert(kCT / kWave * 32 == kMlpWidth, "each wave owns 32 output columns");
     const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const long long s0 = (long long)blockIdx.x * kFT;
     const SeedTiling &g = A.g;
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
     for (int k = 0; k < A.n_windows; ++k) {
         const float tk = (float)(A.t0 + (double)k * A.tau);
         // features: thread -> (sample m, frequency f), f fastest
-        for (int idx = tid; idx < kFT * kMlpFreq; idx += 256) {
+        for (int idx = tid; idx < kFT * kMlpFreq; idx += kCT) {
             const int m = idx / kMlpFreq, f = idx % kMlpFreq;
             const float v0 = (xs[0][m] - P.in_shift[0]) * P.in_scale[0];
             const float v1 = (xs[1][m] - P.in_shift[1]) * P.in_scale[1];
@@ -480,22 +483,21 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             const float *bias = P.params + mlp_off_b(l);
             // the transposed product out^T[n][m] = sum_k W^T[n][k] act[m][k]: weights
             // as the A operand, activations as B, so that a lane's four results
-            // are four consecutive output columns n of one sample m
-            // the accumulators start from the bias of their output columns
-            f32x4 acc[8][4];
+            // are four consecutive output columns n of one sample m; wave w owns
+            // columns 32w .. 32w+31.  The accumulators start from the bias.
+            f32x4 acc[8][2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+            for (int j = 0; j < 2; ++j) {
+                const int n0 = wave * 32 + 16 * j + 4 * (lane / 16);
                 const f32x4 b4 = (f32x4){bias[n0], bias[n0 + 1], bias[n0 + 2], bias[n0 + 3]};
 #pragma unroll
                 for (int i = 0; i < 8; ++i) acc[i][j] = b4;
             }
             const int ko = 8 * (lane / 16);
-            // weight fragments of K-slice kk (32 wide) for this wave's 64 columns
             auto load_w = [&](int kk, bf16x8 *w) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int n = wave * 64 + 16 * j + lane % 16;
+                for (int j = 0; j < 2; ++j) {
+                    const int n = wave * 32 + 16 * j + lane % 16;
                     w[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
                 }
             };
@@ -505,17 +507,15 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
                     const bf16x8 xfr = *reinterpret_cast<const bf16x8 *>(
                         &act[(16 * i + lane % 16) * kActStride + kk + ko]);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < 2; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], xfr, acc[i][j], 0, 0, 0);
                 }
             };
             // two fragment buffers: the next slice's weights are in flight from L2
-            // while the current slice's 32 products run (K is a multiple of 64)
+            // while the current slice's products run (K is a multiple of 64)
             static_assert(kMlpFeat % 64 == 0 && kMlpWidth % 64 == 0, "K must be a multiple of 64");
-            bf16x8 wa[4], wb[4];
+            bf16x8 wa[2], wb[2];
             load_w(0, wa);
-            // (the scheduling barriers keep each prefetch ahead of the products
-            // that overlap it)
             for (int kk = 0; kk < K; kk += 64) {
                 load_w(kk + 32, wb);
                 __builtin_amdgcn_sched_barrier(0);
@@ -526,8 +526,8 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             }
             __syncthreads();   // every wave has read this layer's input
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+            for (int j = 0; j < 2; ++j) {
+                const int n0 = wave * 32 + 16 * j + 4 * (lane / 16);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int m = 16 * i + lane % 16;
@@ -538,25 +538,27 @@ __global__ __launch_bounds__(256, 2) void compose_fused_kernel(ComposeArgs A)
             }
             __syncthreads();
         }
-        // head: two threads per sample, each summing half of the 256 inputs; the
-        // half is uniform over a wave (waves 0-1 the first, 2-3 the second), so
-        // the head weights are scalar loads, and the second half's partial sums
-        // reach the first through LDS
+        // head: two threads per sample (waves 0-3), each summing half of the 256
+        // inputs; the half is uniform over a wave (waves 0-1 the first, 2-3 the
+        // second), so the head weights are scalar loads, and the second half's
+        // partial sums reach the first through LDS
         {
             const int m = tid % kFT;
             const int h = __builtin_amdgcn_readfirstlane(tid / kFT);
             float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
-            for (int q0 = h * 128; q0 < h * 128 + 128; q0 += 8) {
-                // eight activations in one 16-byte LDS read (rows are 16-byte aligned)
-                const uint4 a8 = *reinterpret_cast<const uint4 *>(&act[m * kActStride + q0]);
-                const uint32_t w2[4] = {a8.x, a8.y, a8.z, a8.w};
+            if (h < 2) {
+                for (int q0 = h * 128; q0 < h * 128 + 128; q0 += 8) {
+                    // eight activations in one 16-byte LDS read (rows are 16-byte aligned)
+                    const uint4 a8 = *reinterpret_cast<const uint4 *>(&act[m * kActStride + q0]);
+                    const uint32_t w2[4] = {a8.x, a8.y, a8.z, a8.w};
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float x = bf2f((uint16_t)(w2[e / 2] >> (16 * (e % 2))));
-                    const int q = q0 + e;
-                    y0 += x * Wh[3 * q];
-                    y1 += x * Wh[3 * q + 1];
-                    y2 += x * Wh[3 * q + 2];
+                    for (int e = 0; e < 8; ++e) {
+                        const float x = bf2f((uint16_t)(w2[e / 2] >> (16 * (e % 2))));
+                        const int q = q0 + e;
+                        y0 += x * Wh[3 * q];
+                        y1 += x * Wh[3 * q + 1];
+                        y2 += x * Wh[3 * q + 2];
+                    }
                 }
             }
             if (h == 1) {
@@ -591,7 +593,7 @@ __global__ __launch_bounds__(256) void sub_kernel(const float *__restrict__ a, c
 hipError_t launch_compose_fused(const ComposeArgs &a, hipStream_t s)
 {
     LaunchTimer timer("compose_fused_kernel", s);
-    hipLaunchKernelGGL(compose_fused_kernel, dim3((unsigned)((a.ns + kFT - 1) / kFT)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(compose_fused_kernel, dim3((unsigned)((a.ns + kFT - 1) / kFT)), dim3(kCT), 0, s, a);
     timer.stop(s);
     return hipGetLastError();
 }
