@@ -854,6 +854,70 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
     return out
 
 
+def bench_surrogate_sweep(torch, lcs, inputs, sigmas=(1.0, 2.0, 4.0, 8.0), epochs_list=(4, 16, 64)):
+    """Measured frontier of the learned surrogate (not run by default:
+    --extras surrogate_sweep): for the random-Fourier and the ABC field, every
+    frequency spread sigma_x x training length, trained on 2^24 RK4 pairs over
+    tau = 0.5; on a 256 x 256 x 128 seed grid over T = 4 from t0 = 4: the
+    validation RMS per window, the check-sample tile errors (fraction of tiles
+    within 1e-2 and 1e-1) and the mean FTLE error of the composition alone
+    against plain RK4 at dt = 0.01."""
+    from paper_2209_13775_amd import surrogate as S
+    L = 2 * math.pi
+    out = []
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    for field in ("random_fourier", "abc"):
+        if field == "random_fourier":
+            fs = inputs.random_fourier_frames(n=256, n_frames=65, dt_frame=0.125, device="cuda")
+            soa = lcs.DeviceFrames(fs, tensors=fs.u)
+            speed = 1.0
+        else:
+            fs = inputs.abc_frames(n=128, n_frames=33, dt_frame=0.5)
+            soa = lcs.DeviceFrames(fs)
+            speed = math.sqrt(6.0)
+        frames = lcs.lcs_frames_interleave(soa, "tpair")
+        del soa
+        g = inputs.SeedGrid(3, (256, 256, 128), (0.0,) * 3, (L / 256, L / 256, L / 128), (True,) * 3)
+        T, dt = 4.0, 0.01
+        e0, e1 = ev(), ev()
+        e0.record()
+        ref, _, rfl = lcs.lcs_advect_sorted(frames, g, 4.0, T, dt, 100, want_cell=False)
+        _, rsig, _ = lcs.lcs_cg_ftle(g, ref, T, flags=rfl)
+        e1.record()
+        torch.cuda.synchronize()
+        rk4_ms = e0.elapsed_time(e1)
+        for sx in sigmas:
+            cfg = S.SurrogateConfig(tau=0.5, n_windows=8, t0=4.0, dt=dt, sigma_x=sx, sigma_t=1.0,
+                                    speed_scale=speed)
+            xt, dx, _ = S.training_data(frames, cfg, 1 << 24, seed=1)
+            vxt, vdx, _ = S.training_data(frames, cfg, 1 << 16, seed=2)
+            for ep in epochs_list:
+                mlp = S.new_model(cfg)
+                log = S.train(mlp, xt, dx, epochs=ep, batch=65536, lr=2e-3, val=(vxt, vdx))
+                e0.record()
+                xf, flags, _, _, err = lcs.lcs_surrogate_flowmap(mlp, frames, g, 4.0, 0.5, 8,
+                                                                 float("inf"), dt)
+                e1.record()
+                torch.cuda.synchronize()
+                _, sig, _ = lcs.lcs_cg_ftle(g, xf, T, flags=flags)
+                te = err.float()
+                out.append({"field": field, "sigma_x": sx, "epochs": ep, "steps": log.steps,
+                            "train_s": log.seconds, "val_rms_per_window": math.sqrt(log.val_loss),
+                            "tile_err_median": float(te.median().item()),
+                            "tiles_within_1e-3": float((te <= 1e-3).float().mean().item()),
+                            "tiles_within_1e-2": float((te <= 1e-2).float().mean().item()),
+                            "tiles_within_1e-1": float((te <= 1e-1).float().mean().item()),
+                            "ftle_err_mean_composition": float((sig - rsig).abs().mean().item()),
+                            "compose_and_check_ms": e0.elapsed_time(e1), "rk4_ms": rk4_ms})
+                print(f"bench: surrogate sweep {out[-1]}", file=sys.stderr, flush=True)
+                del mlp, xf, flags, err, sig
+            del xt, dx, vxt, vdx
+            torch.cuda.empty_cache()
+        del frames, fs, ref, rsig
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1059,6 +1123,10 @@ def main():
         if "aux" in want:
             print("bench: auxiliary points", file=sys.stderr, flush=True)
             extra["auxiliary_points"] = bench_aux(torch, lcs, inputs)
+            torch.cuda.empty_cache()
+        if "surrogate_sweep" in want:
+            print("bench: surrogate frontier sweep", file=sys.stderr, flush=True)
+            extra["surrogate_sweep"] = bench_surrogate_sweep(torch, lcs, inputs)
             torch.cuda.empty_cache()
         if "time_resolved" in want:
             print("bench: time-resolved and early FTLE", file=sys.stderr, flush=True)
