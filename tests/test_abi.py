@@ -321,3 +321,40 @@ def test_tuned_and_surrogate_flowmap_validate():
     assert L.lcs_surrogate_flowmap(C.byref(m), C.byref(v2), C.byref(s), 0.0, 0.5, 2, 1e-3, 0.1,
                                    0.25, 0x10, None, None, None, None, 0x1000, 1 << 20,
                                    None) == lcs.LCS_E_UNSUPPORTED
+
+
+def test_mlp_train_validates():
+    """lcs_mlp_train rejects bad arguments before any device work (the fake
+    pointers are never dereferenced); its workspace grows with the batch and
+    covers whole 128-sample tiles."""
+    L = lcs.lib()
+    m = lcs.lcs_mlp_t()
+    m.freq, m.params, m.params_bf16 = 0x100, 0x200, 0x300
+    for a in range(4):
+        m.in_scale[a] = 1.0
+    m.out_scale = 1.0
+    w1, w128, w129 = (L.lcs_mlp_train_workspace_bytes(b) for b in (1, 128, 129))
+    assert 0 < w1 == w128 < w129
+    assert L.lcs_mlp_train_workspace_bytes(0) == 0
+    need = L.lcs_mlp_train_workspace_bytes(256)
+
+    def call(mlp=C.byref(m), params=0x200, bf=0x300, xt=0x400, n=1024, batch=256, first=1, ns=2,
+             total=2, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, mm=0x500, vv=0x600, ws=0x700, wsb=need):
+        return L.lcs_mlp_train(mlp, params, bf, xt, 0x800, n, batch, first, ns, total, lr, 1e-4, b1, b2,
+                               eps, mm, vv, None, None, ws, wsb, None)
+    assert call(mlp=None) == lcs.LCS_E_ARG
+    assert call(params=0x204) == lcs.LCS_E_ARG          # not the descriptor's masters
+    assert call(bf=None) == lcs.LCS_E_ARG
+    assert call(xt=None) == lcs.LCS_E_ARG
+    assert call(mm=None) == lcs.LCS_E_ARG
+    assert call(ws=None) == lcs.LCS_E_ARG
+    assert call(batch=2048) == lcs.LCS_E_SHAPE           # batch > n
+    assert call(batch=0) == lcs.LCS_E_SHAPE
+    assert call(first=0) == lcs.LCS_E_ARG
+    assert call(ns=-1) == lcs.LCS_E_ARG
+    assert call(total=0) == lcs.LCS_E_ARG
+    assert call(b1=1.0) == lcs.LCS_E_ARG
+    assert call(eps=0.0) == lcs.LCS_E_ARG
+    assert call(lr=float("nan")) == lcs.LCS_E_ARG
+    assert call(wsb=need - 1) == lcs.LCS_E_SHAPE
+    assert call(ns=0) == lcs.LCS_OK                       # zero steps: nothing launched
