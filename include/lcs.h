@@ -307,14 +307,17 @@ lcs_status lcs_cg_ftle(const lcs_seed_grid_t *seeds, const float *xf, const uint
 
 /*
  * lcs_advect_batched -- the flow map of one seed grid for a time series of
- * start times (Sec. 1: the computation may be repeated for a time series of
- * seed grids at different t0; Sec. 4: sampling is dense in space, not in
- * time), all windows in ONE persistent launch replayed from a HIP graph.
+ * start times (Sec. 1: the FTLE field of a flow is usually wanted for many
+ * start times; Sec. 4: sampling is dense in space, not in time), all windows
+ * in ONE persistent launch replayed from a HIP graph.
  *
  * Window w integrates N_w = T_w/dt RK4 steps from windows[w].t0 (same
  * integrator, same outputs as lcs_advect, bit-identical to calling lcs_advect
- * per window).  Work items are (window, seed tile) pairs taken longest window
- * first from a device counter by persistent workgroups.  The (counter reset,
+ * per window).  Work items are (window, seed tile) pairs, windows in order of
+ * start time; the tiles are split into 8 contiguous runs along the Morton
+ * curve, one per XCD, each drained from its own device counter by that XCD's
+ * persistent workgroups (each XCD then reads one compact part of the domain).
+ * The (counter reset,
  * kernel) pair is captured once into a graph on a plan-owned stream and
  * replayed on `stream`; a call whose arguments differ from the captured ones
  * re-captures.
@@ -334,7 +337,7 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
                               uint8_t *flags, void *stream);
 
 /* lcs_plan_create / lcs_plan_destroy -- allocate / free a plan on the current
- * device (hipMalloc of a 4-byte counter, one non-blocking stream).
+ * device (hipMalloc of 8 four-byte work counters, one non-blocking stream).
  * autotune_cache_path [host] NUL-terminated file name or NULL: the
  * autotuner's choices are read from it now (one JSON object per line, as
  * lcs_advect_tuned appends them; a missing file is an empty cache) and every

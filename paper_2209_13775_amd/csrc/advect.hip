@@ -815,24 +815,36 @@ __global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *u0, 
     o[2] = make_float2(u1[b], u2[b]);
 }
 
-__global__ void reset_counter_kernel(int *counter) { *counter = 0; }
+__global__ void reset_counter_kernel(int *counter)
+{
+    if (threadIdx.x < kBatchCounters) counter[threadIdx.x] = 0;
+}
 
-// Persistent batched advection: every block repeatedly claims the next
-// (window, tile) item; items run longest window first and, within a window,
-// along the Morton curve.  All lanes of a block leave the loop together once
-// the counter passes the item count.
+// Persistent batched advection.  The seed tiles (in Morton order) are split
+// into 8 contiguous runs, one per XCD (blocks are dealt round-robin to the
+// XCDs, so block b works on run b % 8): each XCD then gathers from one
+// compact eighth of the domain, which its L2 holds, instead of every XCD
+// reading whole frames.  A block repeatedly claims the next (window, tile) item
+// of its run from the run's own counter, windows in start-time order and,
+// within a window, tiles along the Morton curve.  All lanes of a block leave
+// the loop together once the run's counter passes its item count.
 template <int D>
 __global__ __launch_bounds__(256) void advect_batched_kernel(BatchArgs A)
 {
     __shared__ int s_item;
+    const int x = blockIdx.x % kBatchCounters;
+    const int nb = A.g.n_blocks, q8 = nb / kBatchCounters, r8 = nb % kBatchCounters;
+    const int run = q8 + (x < r8 ? 1 : 0);                 // tiles of this XCD's run
+    const int first = x * q8 + min(x, r8);                 // its first tile
+    const int items = A.n_windows * run;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(A.counter, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(A.counter + x, 1);
         __syncthreads();
         const int q = s_item;
         __syncthreads();
-        if (q >= A.total_items) break;
-        const int k = q / A.g.n_blocks;
-        const int m = q - k * A.g.n_blocks;
+        if (q >= items) break;
+        const int k = q / run;
+        const int m = first + (q - k * run);
         const WindowDev w = A.win[k];
         int sc[3];
         const long long s = seed_of<D>(A.g, m, threadIdx.x, sc);
@@ -1364,7 +1376,7 @@ hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_co
 
 hipError_t launch_reset_counter(int *counter, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(kBatchCounters), 0, s, counter);
     return hipGetLastError();
 }
 

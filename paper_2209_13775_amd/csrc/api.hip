@@ -410,7 +410,7 @@ lcs_status lcs_plan_create(lcs_plan_t *plan, const char *autotune_cache_path)
         read_tune_cache(p);
     }
     hipError_t e = hipGetDevice(&p->device);
-    if (e == hipSuccess) e = hipMalloc((void **)&p->d_counter, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void **)&p->d_counter, lcs::kBatchCounters * sizeof(int));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         if (p->d_counter) (void)hipFree(p->d_counter);
@@ -805,11 +805,14 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
         A.win[w].nsteps = nsteps;
         A.win[w].out_index = w;
     }
-    // longest window first (stable, so equal lengths keep the caller's order)
+    // earliest start first (stable): the blocks working at any moment then
+    // hold tiles of one or two windows that started together and advance
+    // together, so they read the same few frame pairs, which stay in L2 and
+    // the MALL instead of every window's frames streaming from HBM at once
     for (int i = 1; i < n_windows; ++i) {
         lcs::WindowDev x = A.win[i];
         int j = i - 1;
-        while (j >= 0 && A.win[j].nsteps < x.nsteps) {
+        while (j >= 0 && A.win[j].t0 > x.t0) {
             A.win[j + 1] = A.win[j];
             --j;
         }
@@ -836,7 +839,9 @@ lcs_status lcs_advect_batched(lcs_plan_t plan, const lcs_velocity_t *vel,
     int n_cu = 0;
     e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return lcs::hip_error(e, "hipDeviceGetAttribute");
-    const int grid = n_cu * lcs::batched_blocks_per_cu(vel->dim);
+    // a whole number of blocks per XCD (each XCD's blocks drain its own share)
+    int grid = n_cu * lcs::batched_blocks_per_cu(vel->dim);
+    grid = (grid + lcs::kBatchCounters - 1) / lcs::kBatchCounters * lcs::kBatchCounters;
 
     const bool same = plan->have_graph && plan->key_dim == vel->dim && plan->key_grid == grid &&
                       memcmp(&plan->key, &A, sizeof(A)) == 0;

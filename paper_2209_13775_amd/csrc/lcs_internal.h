@@ -162,6 +162,10 @@ struct WindowDev {
     int out_index;            // position of the window in the caller's order
 };
 
+// Persistent batched advection: one work counter per XCD (blocks are dealt
+// round-robin to the 8 XCDs, so block b runs on XCD b % 8).
+constexpr int kBatchCounters = 8;
+
 struct BatchArgs {
     VelDev v;
     SeedTiling g;
@@ -169,7 +173,7 @@ struct BatchArgs {
     long long ns;
     int n_windows;
     int total_items;          // n_windows * g.n_blocks
-    int *counter;             // work counter (device)
+    int *counter;             // kBatchCounters work counters (device), one per XCD
     float *xf;
     long long *cell;
     uint8_t *flags;
