@@ -237,25 +237,23 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restr
 }
 
 // The same sum for short outputs with many chunks (bias and head gradients):
-// one block per output, thread t summing chunks t, t + 256, ... in order, then
-// a fixed pairwise tree in LDS (deterministic, and 256-way parallel where the
-// per-output loop above would run nchunk dependent loads in one thread).
+// a block takes 64 consecutive outputs and four chunk groups; thread (g, o)
+// sums chunks g, g + 4, g + 8, ... of output o in order (a wave reads 64
+// adjacent floats of one chunk per load), then the four group sums are added
+// in group order (deterministic).
 __global__ __launch_bounds__(256) void reduce_chunks_tree_kernel(const float *__restrict__ part,
                                                                  int nchunk, long long len,
                                                                  float *__restrict__ out)
 {
-    __shared__ float sh[256];
-    const long long i = blockIdx.x;
-    const int t = threadIdx.x;
+    __shared__ float sh[4][64];
+    const int o = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const long long i = (long long)blockIdx.x * 64 + o;
     float s = 0.0f;
-    for (int c = t; c < nchunk; c += 256) s += part[(long long)c * len + i];
-    sh[t] = s;
+    if (i < len)
+        for (int c = grp; c < nchunk; c += 4) s += part[(long long)c * len + i];
+    sh[grp][o] = s;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) sh[t] += sh[t + off];
-        __syncthreads();
-    }
-    if (t == 0) out[i] = sh[0];
+    if (grp == 0 && i < len) out[i] = ((sh[0][o] + sh[1][o]) + sh[2][o]) + sh[3][o];
 }
 
 // ---------------------------------------------------------------------------
@@ -644,8 +642,8 @@ hipError_t launch_reduce_chunks(const float *part, int nchunk, long long len, fl
 {
     if (len <= 0) return hipSuccess;
     if (len <= 4096 && nchunk > 64)
-        hipLaunchKernelGGL(reduce_chunks_tree_kernel, dim3((unsigned)len), dim3(256), 0, s, part,
-                           nchunk, len, out);
+        hipLaunchKernelGGL(reduce_chunks_tree_kernel, dim3((unsigned)((len + 63) / 64)), dim3(256), 0, s,
+                           part, nchunk, len, out);
     else
         hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
                            part, nchunk, len, out);
