@@ -477,10 +477,13 @@ lcs_status lcs_sub(const float *a, const float *b, int64_t n, float *out, void *
  * params_bf16 must be the descriptor's own buffers; both are updated after
  * every step.  losses [device] FP64, n_steps values (or NULL): the MSE of each
  * step's batch before its update.  grads [device] FP32 LCS_MLP_PARAMS (or
- * NULL): the last step's gradient.  The arithmetic and rounding points are
- * those of lcs_mlp_forward / lcs_mse_grad / lcs_mlp_backward / lcs_adam_step
- * (BF16 operands, FP32 accumulation); every sum runs in a fixed order, so a
- * call is bit-reproducible.  Four launches per step: forward with the loss
+ * NULL): the last step's gradient.  The rounding points are those of
+ * lcs_mlp_forward / lcs_mse_grad / lcs_mlp_backward / lcs_adam_step (BF16
+ * operands and activations, FP32 accumulation), but the Fourier features take
+ * the hardware sine and cosine of the exactly reduced phase and GELU and its
+ * derivative come from one base-2 exponential and reciprocal, so the results
+ * agree with those entry points to rounding, not bit for bit; every sum runs
+ * in a fixed order, so a call is bit-reproducible.  Four launches per step: forward with the loss
  * gradient, backward through the hidden layers, weight gradients over
  * 2048-sample chunks, and the reduction with Adam and the BF16 copies.
  * workspace [device] of at least lcs_mlp_train_workspace_bytes(batch) bytes
