@@ -529,7 +529,7 @@ lcs_status lcs_advect_tiles(const lcs_velocity_t *vel, const lcs_seed_grid_t *se
 /*
  * lcs_surrogate_flowmap -- the whole surrogate flow map of a 3D seed grid over
  * T = n_windows * tau (a local flow-map approximation, Sec. 4, with plain RK4
- * as the judge and the fallback): lcs_surrogate_compose, then
+ * as the reference and the fallback): lcs_surrogate_compose, then
  * lcs_surrogate_check with RK4 step dt and tolerance tol, then plain RK4 for
  * the seeds of every failing tile.  When more than whole_grid_fraction of the
  * check tiles fail, the whole grid is re-advected instead with the re-bundled
