@@ -125,13 +125,14 @@ def profiled_record(kernel, workload):
     return None
 
 
-def roofline_record(kernel, avg_ms, launches, units_per_launch, workload):
-    """Roofline of an RK4 advection kernel: algorithmic stencil bytes per
-    launch over its average launch duration (HIP events around each launch on
-    its stream), against the vector L1 data path that binds these gathers,
-    with the HBM traffic and busy fractions from the committed counter
-    profile."""
-    A = BYTES_PER_STEP_3D * units_per_launch / (avg_ms * 1e-3) / 1e9
+def roofline_record(kernel, avg_ms, launches, units_per_launch, workload,
+                    bytes_per_unit=None, unit_of_work=None):
+    """Roofline of an advection kernel: algorithmic stencil bytes per launch
+    over its average launch duration (HIP events around each launch on its
+    stream), against the vector L1 data path that binds these gathers, with the
+    HBM traffic and busy fractions from the committed counter profile."""
+    bpu = BYTES_PER_STEP_3D if bytes_per_unit is None else bytes_per_unit
+    A = bpu * units_per_launch / (avg_ms * 1e-3) / 1e9
     prof = profiled_record(kernel, workload) or {}
     traffic = prof.get("traffic_bytes_per_launch")
     hbm = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
@@ -139,9 +140,9 @@ def roofline_record(kernel, avg_ms, launches, units_per_launch, workload):
             "unit": "GB/s", "frac": A / VL1D_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, each "
                             "scaled by the same counter on a plain copy of known size)",
-            "bytes_per_unit": BYTES_PER_STEP_3D,
-            "unit_of_work": "3D tracer-RK4-step (4 evaluations x 8 corners x 2 frames x 3 "
-                            "components x 4 B of stencil data)",
+            "bytes_per_unit": bpu,
+            "unit_of_work": unit_of_work or ("3D tracer-RK4-step (4 evaluations x 8 corners x 2 "
+                                             "frames x 3 components x 4 B of stencil data)"),
             "units_per_launch": units_per_launch, "launches_timed": launches,
             "avg_launch_ms": avg_ms,
             "timing": "HIP events recorded by the library around every launch of the kernel, "
@@ -153,9 +154,10 @@ def roofline_record(kernel, avg_ms, launches, units_per_launch, workload):
             "ta_busy": prof.get("ta_busy"), "td_busy": prof.get("td_busy"),
             "counters_workload": workload if prof else None,
             "note": "the stencil gathers are served from the per-tracer register cache, L1 and "
-                    "L2: the kernel is not HBM-bound (hbm_frac); the texture address / data "
-                    "units of the vector-memory path are busy for most of its cycles (ta_busy, "
-                    "td_busy), so the vector L1 data path is the roofline it is held to"}
+                    "L2 (algorithmic_bytes_over_hbm_peak counts them as if none were): the "
+                    "kernel's HBM traffic is hbm_frac of the peak, and the texture address / "
+                    "data units of the vector-memory path are busy for most of its cycles "
+                    "(ta_busy, td_busy), so the vector L1 data path is the roofline it is held to"}
 
 
 def measure_copy_gbs(torch, dev, mib=1024, reps=5):
@@ -385,10 +387,10 @@ def bench_batched(torch, lcs, inputs, reps=3, layout="xyz"):
            "windows": nw,
            "seeds_per_window": ns, "tracer_steps": steps, "ms_per_launch": ms,
            "tracer_steps_per_s": steps / (ms * 1e-3),
-           "roofline": {"kernel": "advect_batched_kernel<2>", "bound": "hbm",
-                        "achieved": 256 * steps / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": 256 * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                        "bytes_per_unit": 256, "unit_of_work": "2D tracer-RK4-step"},
+           "roofline": roofline_record("advect_batched_kernel<2>", ms, len(times), steps,
+                                       "double_gyre_batched_1025x513_64windows", 256,
+                                       "2D tracer-RK4-step (4 evaluations x 4 corners x 2 frames "
+                                       "x 2 components x 4 B)"),
            "graph": plan.stats()}
     plan.close()
     return out
@@ -458,6 +460,14 @@ def bench_abc(torch, lcs, inputs, reps=5):
     return out
 
 
+# fused training step, per sample: forward reads inputs and targets (28 B) and writes the
+# layer inputs h_0..h_3 (1792 B), gelu' of 4 layers (2048 B) and dy (12 B); backward reads
+# gelu' and dy and writes dz of 4 layers (2048 B); weight gradients read h and dz
+TRAIN_BYTES_PER_SAMPLE = (28 + 1792 + 2048 + 12) + (2048 + 12 + 2048) + (1792 + 2048)
+TRAIN_FLOPS_PER_SAMPLE = 1.32e6   # forward 0.46 + backward-data 0.39 + weight gradients 0.46 MFLOP
+MLP_PARAMS = 231171
+MLP_BF16 = 458752
+
 MESH_BYTES_PER_STEP_3D = 640   # 4 x (cell map 48 B + node ids 16 B + 2 frames x 4 nodes x 12 B)
 MESH_BYTES_PER_STEP_2D = 256   # 4 x (cell map 24 B + node ids 16 B + 2 frames x 3 nodes x 8 B)
 
@@ -522,13 +532,9 @@ def bench_mesh(torch, lcs, inputs, reps=3, cpu_sample=0):
                "tracer_steps_per_s_advect_kernel": steps / (adv * 1e-3),
                "ftle_points_per_s": ns / (cgf * 1e-3), "mean_ftle": float(sig.mean().item()),
                "flagged_tracers": int((fl != 0).sum()), "lost_tracers": int(((fl & 16) != 0).sum()),
-               "roofline": {"kernel": "mesh_advect_grid_kernel<%d>" % dim, "bound": "hbm",
-                            "achieved": bps * steps / (adv * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s",
-                            "frac": bps * steps / (adv * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                            "traffic": (profiled_record("mesh_advect_grid_kernel<%d>" % dim, name) or {}).get(
-                                "traffic_bytes_per_launch"),
-                            "bytes_per_unit": bps, "unit_of_work": "%dD mesh tracer-RK4-step" % dim}}
+               "roofline": roofline_record("mesh_advect_grid_kernel<%d>" % dim, adv, reps, steps,
+                                           name, bps, "%dD mesh tracer-RK4-step (cell maps, node "
+                                           "ids and node values of the 4 evaluations)" % dim)}
         if cpu_sample and dim == 3:
             import oracle
             mv = oracle.MeshVelocity(mf)
@@ -779,6 +785,26 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
     base = S.evaluate(mlp, vxt, vdx)
     log = S.train(mlp, xt, dx, epochs=epochs, batch=65536, lr=2e-3, val=(vxt, vdx))
     del xt, dx
+    # training-step roofline: the step is bound by its activation traffic
+    # (TRAIN_BYTES_PER_SAMPLE per sample plus the per-step partial sums and
+    # Adam), not by the matrix cores
+    step_s = log.seconds / max(log.steps, 1)
+    nch = 65536 // 2048                               # weight-gradient chunks of 2048 samples
+    step_bytes = TRAIN_BYTES_PER_SAMPLE * 65536 + (2 * nch * 4 + 6 * 4) * MLP_PARAMS + 2 * MLP_BF16
+    prof = profiled_record("training step", "surrogate_training_batch65536") or {}
+    traffic = prof.get("traffic_bytes_per_launch")
+    train_roof = {"kernel": "training step (train_fwd + train_bwd + train_wgrad + train_update)",
+                  "bound": "hbm", "achieved": step_bytes / step_s / 1e9, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": step_bytes / step_s / 1e9 / HBM_PEAK_GBS,
+                  "bytes_per_unit": step_bytes, "unit_of_work": "Adam step of 65,536 samples",
+                  "avg_step_ms": step_s * 1e3, "traffic": traffic,
+                  "hbm_gbs": traffic / step_s / 1e9 if traffic else None,
+                  "hbm_frac": traffic / step_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+                  "bf16_tflops": TRAIN_FLOPS_PER_SAMPLE * 65536 / step_s / 1e12,
+                  "mfma_frac": TRAIN_FLOPS_PER_SAMPLE * 65536 / step_s / 1e12 / 2500.0,
+                  "note": "algorithmic bytes: inputs, the layer inputs and gelu' written and read "
+                          "back, dz written and read back, chunk partials and Adam; an arithmetic "
+                          "intensity of ~100 flop/B, below the 312 flop/B of 2.5 PFLOP/s / 8 TB/s"}
     flop = 2.0 * 230144 * g.count * cfg.n_windows    # 2 x multiply-adds of all layers
     lcs.lcs_timing_enable(True)
     e0.record(stream)
@@ -821,6 +847,7 @@ def bench_surrogate(torch, lcs, keep, n_train=1 << 24, epochs=4):
            "val_mse_before": base, "val_mse_after": log.val_loss,
            "val_rms_per_window": math.sqrt(log.val_loss),
            "sigma_x": cfg.sigma_x, "sigma_t": cfg.sigma_t,
+           "train_roofline": train_roof,
            "compose_ms": compose_ms,
            "compose_tflops": flop / (compose_ms * 1e-3) / 1e12,
            "roofline": {"kernel": "compose_fused_kernel", "bound": "mfma",
