@@ -29,6 +29,7 @@
 // Every sum runs in a fixed order, so a step is bit-reproducible.
 
 #include "lcs_internal.h"
+#include "device_common.h"
 
 namespace lcs {
 namespace {
@@ -369,15 +370,20 @@ __device__ __forceinline__ float sum8(const bf16x8 &v)
 __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
 {
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    int t = blockIdx.x;
-    const long long mb = (long long)blockIdx.y * kWgradChunk;
+    // one-dimensional grid of (tile, chunk) pairs, tile fastest, remapped so
+    // that each XCD runs a contiguous run of them: the tiles of one chunk, which
+    // read the same activations and gradients, then share that XCD's L2
+    const int lin = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    int t = lin % (kWgradTiles + 1);
+    const int chunk = lin / (kWgradTiles + 1);
+    const long long mb = (long long)chunk * kWgradChunk;
     const long long me = min(mb + kWgradChunk, A.Bp);
     if (t == kWgradTiles) {
         const long long t0 = mb / kTS, t1 = me / kTS;
         for (int p = threadIdx.x; p < kHeadPart; p += 256) {
             float s = 0.0f;
             for (long long q = t0; q < t1; ++q) s += A.part_head[q * kHeadPart + p];
-            A.part_w[(long long)blockIdx.y * kMlpParams + kOffWh + p] = s;
+            A.part_w[(long long)chunk * kMlpParams + kOffWh + p] = s;
         }
         return;
     }
@@ -425,7 +431,7 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(TrainArgs A)
         __builtin_amdgcn_sched_barrier(0);
         step(a1, b1);
     }
-    float *out = A.part_w + (long long)blockIdx.y * kMlpParams;
+    float *out = A.part_w + (long long)chunk * kMlpParams;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -506,7 +512,7 @@ hipError_t launch_train_step(const TrainArgs &a, const AdamArgs &ad, hipStream_t
     }
     {
         LaunchTimer timer("train_wgrad_kernel", s);
-        hipLaunchKernelGGL(train_wgrad_kernel, dim3(kWgradTiles + 1, (unsigned)a.n_chunks),
+        hipLaunchKernelGGL(train_wgrad_kernel, dim3((unsigned)((kWgradTiles + 1) * a.n_chunks)),
                            dim3(256), 0, s, a);
         timer.stop(s);
     }
