@@ -40,6 +40,12 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kTS = 128;                    // samples per tile
+constexpr int kTT = 512;                    // threads of the forward and backward kernels
+constexpr int kTW = kTT / 64;               // their waves: wave w owns outputs kNJ*16*w ..
+constexpr int kNJ = kMlpWidth / (16 * kTW); // 16-wide output blocks per wave
+static_assert(kNJ * 16 * kTW == kMlpWidth && kTT >= 2 * kTS && kTT >= kMlpWidth,
+              "the output blocks, the head's two threads per sample and its gradient's thread per "
+              "input must fit the workgroup");
 constexpr int kStr = kMlpWidth + 8;         // BF16 per LDS activation row (16-byte aligned rows)
 constexpr long long kFragTile = (long long)kTS * kMlpWidth;   // BF16 per tile and layer
 constexpr int kWgradTiles = 2 + 4 * (kMlpHidden - 1);          // 128 x 128 weight-gradient tiles
@@ -80,18 +86,18 @@ __device__ __forceinline__ void gelu_pair(float z, float &h, float &d)
 
 // One layer's product for the tile, transposed: out^T[n][m] = sum_k A[n][k] act[m][k]
 // with A rows from global memory (BF16, row length K) and the activations in
-// LDS; wave w owns outputs 64w .. 64w+63.  acc must hold the starting values.
+// LDS; wave w owns outputs 32w .. 32w+31.  acc must hold the starting values.
 // The next 32-wide slice of A is loaded while the current one's products run.
 template <int K>
 __device__ __forceinline__ void tile_product(const uint16_t *__restrict__ Arows, const uint16_t *act,
-                                             f32x4 (&acc)[8][4], int wave, int lane)
+                                             f32x4 (&acc)[8][kNJ], int wave, int lane)
 {
     static_assert(K % 64 == 0, "K must be a multiple of 64");
     const int ko = 8 * (lane / 16);
     auto load_a = [&](int kk, bf16x8 *w) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = wave * 64 + 16 * j + lane % 16;
+        for (int j = 0; j < kNJ; ++j) {
+            const int n = wave * 16 * kNJ + 16 * j + lane % 16;
             w[j] = *reinterpret_cast<const bf16x8 *>(Arows + (long long)n * K + kk + ko);
         }
     };
@@ -100,11 +106,11 @@ __device__ __forceinline__ void tile_product(const uint16_t *__restrict__ Arows,
         for (int i = 0; i < 8; ++i) {
             const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(&act[(16 * i + lane % 16) * kStr + kk + ko]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < kNJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j], xb, acc[i][j], 0, 0, 0);
         }
     };
-    bf16x8 wa[4], wb[4];
+    bf16x8 wa[kNJ], wb[kNJ];
     load_a(0, wa);
     for (int kk = 0; kk < K; kk += 64) {
         load_a(kk + 32, wb);
@@ -123,7 +129,7 @@ __device__ __forceinline__ void store_t8(const uint16_t *act, uint16_t *__restri
                                          int tid)
 {
     const int k = tid % K;
-    for (int g = tid / K; g < kTS / 8; g += 256 / K) {
+    for (int g = tid / K; g < kTS / 8; g += kTT / K) {
         uint16_t v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) v[q] = act[(8 * g + q) * kStr + k];
@@ -139,10 +145,10 @@ __device__ __forceinline__ void store_t8(const uint16_t *act, uint16_t *__restri
 // offset (BF16 elements) of a lane's 4 values of block (i, j) in the fragment layout
 __device__ __forceinline__ long long frag_off(long long tile, int wave, int j, int i, int lane)
 {
-    return tile * kFragTile + ((long long)((wave * 4 + j) * 8 + i) * 64 + lane) * 4;
+    return tile * kFragTile + ((long long)((wave * kNJ + j) * 8 + i) * 64 + lane) * 4;
 }
 
-__global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
+__global__ __launch_bounds__(kTT, 4) void train_fwd_kernel(TrainArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t act[kTS * kStr];
     __shared__ float xs[4][kTS];
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
     __syncthreads();
     // Fourier features, thread -> (sample m, frequency f), f fastest; phase in
     // revolutions reduced exactly to [-1/2, 1/2], hardware sine and cosine
-    for (int idx = tid; idx < kTS * kMlpFreq; idx += 256) {
+    for (int idx = tid; idx < kTS * kMlpFreq; idx += kTT) {
         const int m = idx / kMlpFreq, f = idx % kMlpFreq;
         const float *b = P.freq + 4 * f;
         float rev = 0.0f;
@@ -175,10 +181,10 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
     store_t8<kMlpFeat>(act, A.ht[0], tile, tid);
     for (int l = 0; l < kMlpHidden; ++l) {
         const float *bias = P.params + mlp_off_b(l);
-        f32x4 acc[8][4];
+        f32x4 acc[8][kNJ];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+        for (int j = 0; j < kNJ; ++j) {
+            const int n0 = wave * 16 * kNJ + 16 * j + 4 * (lane / 16);
             const f32x4 b4 = (f32x4){bias[n0], bias[n0 + 1], bias[n0 + 2], bias[n0 + 3]};
 #pragma unroll
             for (int i = 0; i < 8; ++i) acc[i][j] = b4;
@@ -190,8 +196,8 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
         __syncthreads();   // every wave has read the layer input
         uint16_t *dl = A.dgelu[l];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+        for (int j = 0; j < kNJ; ++j) {
+            const int n0 = wave * 16 * kNJ + 16 * j + 4 * (lane / 16);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 float h[4], d[4];
@@ -206,24 +212,26 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
         __syncthreads();
         if (l + 1 < kMlpHidden) store_t8<kMlpWidth>(act, A.ht[l + 1], tile, tid);
     }
-    // head (FP32): two threads per sample, halves of the 256 inputs uniform per
-    // wave so the head weights are scalar loads
+    // head (FP32): two threads per sample (waves 0-3), halves of the 256 inputs
+    // uniform per wave so the head weights are scalar loads
     const float *Wh = P.params + kOffWh;
     const float *bh = P.params + kOffBh;
     {
         const int m = tid % kTS;
         const int h = __builtin_amdgcn_readfirstlane(tid / kTS);
         float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f;
-        for (int q0 = h * 128; q0 < h * 128 + 128; q0 += 8) {
-            const uint4 a8 = *reinterpret_cast<const uint4 *>(&act[m * kStr + q0]);
-            const uint32_t w2[4] = {a8.x, a8.y, a8.z, a8.w};
+        if (h < 2) {
+            for (int q0 = h * 128; q0 < h * 128 + 128; q0 += 8) {
+                const uint4 a8 = *reinterpret_cast<const uint4 *>(&act[m * kStr + q0]);
+                const uint32_t w2[4] = {a8.x, a8.y, a8.z, a8.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float x = bf2f((uint16_t)(w2[e / 2] >> (16 * (e % 2))));
-                const int q = q0 + e;
-                y0 += x * Wh[3 * q];
-                y1 += x * Wh[3 * q + 1];
-                y2 += x * Wh[3 * q + 2];
+                for (int e = 0; e < 8; ++e) {
+                    const float x = bf2f((uint16_t)(w2[e / 2] >> (16 * (e % 2))));
+                    const int q = q0 + e;
+                    y0 += x * Wh[3 * q];
+                    y1 += x * Wh[3 * q + 1];
+                    y2 += x * Wh[3 * q + 2];
+                }
             }
         }
         if (h == 1) {
@@ -252,7 +260,7 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
     }
     __syncthreads();
     // head gradient partials: dW_h[k][c] = sum_m h4[m][k] dy_c[m], db_h[c] = sum_m dy_c[m]
-    {
+    if (tid < kMlpWidth) {
         const int k = tid;
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
         for (int m = 0; m < kTS; ++m) {
@@ -278,7 +286,7 @@ __global__ __launch_bounds__(256, 2) void train_fwd_kernel(TrainArgs A)
     }
 }
 
-__global__ __launch_bounds__(256, 2) void train_bwd_kernel(TrainArgs A)
+__global__ __launch_bounds__(kTT, 4) void train_bwd_kernel(TrainArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t act[kTS * kStr];
     __shared__ float dys[3][kTS];
@@ -295,8 +303,8 @@ __global__ __launch_bounds__(256, 2) void train_bwd_kernel(TrainArgs A)
     const float *Wh = P.params + kOffWh;
     const int top = kMlpHidden - 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+    for (int j = 0; j < kNJ; ++j) {
+        const int n0 = wave * 16 * kNJ + 16 * j + 4 * (lane / 16);
         float w[4][3];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -317,17 +325,17 @@ __global__ __launch_bounds__(256, 2) void train_bwd_kernel(TrainArgs A)
     store_t8<kMlpWidth>(act, A.dzt[top], tile, tid);
     for (int l = top; l >= 1; --l) {
         // dh_l = dz_l W_l^T: out^T[k][m] = sum_n W_l[k][n] dz_l[m][n], W_l rows as stored ([in][out])
-        f32x4 acc[8][4];
+        f32x4 acc[8][kNJ];
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+            for (int j = 0; j < kNJ; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
         tile_product<kMlpWidth>(P.wbf + mlp_off_bf16(l), act, acc, wave, lane);
         __syncthreads();
         const uint16_t *dl = A.dgelu[l - 1];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n0 = wave * 64 + 16 * j + 4 * (lane / 16);
+        for (int j = 0; j < kNJ; ++j) {
+            const int n0 = wave * 16 * kNJ + 16 * j + 4 * (lane / 16);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 float d[4];
@@ -502,12 +510,12 @@ hipError_t launch_train_step(const TrainArgs &a, const AdamArgs &ad, hipStream_t
     const unsigned nt = (unsigned)a.n_tiles;
     {
         LaunchTimer timer("train_fwd_kernel", s);
-        hipLaunchKernelGGL(train_fwd_kernel, dim3(nt), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(train_fwd_kernel, dim3(nt), dim3(kTT), 0, s, a);
         timer.stop(s);
     }
     {
         LaunchTimer timer("train_bwd_kernel", s);
-        hipLaunchKernelGGL(train_bwd_kernel, dim3(nt), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(train_bwd_kernel, dim3(nt), dim3(kTT), 0, s, a);
         timer.stop(s);
     }
     {
