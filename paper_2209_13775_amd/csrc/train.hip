@@ -469,8 +469,17 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs
     __shared__ double ls[256];
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < kMlpParams) {
+        // the partials in chunk order, eight loads in flight before their adds
         float g = 0.0f;
-        for (int c = 0; c < A.n_chunks; ++c) g += A.part_w[(long long)c * kMlpParams + i];
+        int c = 0;
+        for (; c + 8 <= A.n_chunks; c += 8) {
+            float p[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) p[e] = A.part_w[(long long)(c + e) * kMlpParams + i];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g += p[e];
+        }
+        for (; c < A.n_chunks; ++c) g += A.part_w[(long long)c * kMlpParams + i];
         if (A.grads) A.grads[i] = g;
         const float mi = ad.beta1 * A.m[i] + (1.0f - ad.beta1) * g;
         const float vi = ad.beta2 * A.v[i] + (1.0f - ad.beta2) * g * g;
