@@ -181,7 +181,9 @@ def _cosine_lr(step, total, lr, lr_final):
     return lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * min(frac, 1.0)))
 
 
-@pytest.mark.parametrize("n", [6000, 300, 4096])
+# 20000 samples: 157 tiles (the last ragged), 10 weight-gradient chunks (the
+# last partial), so the chunk sum runs both its eight-wide loop and its tail
+@pytest.mark.parametrize("n", [6000, 300, 4096, 20000])
 def test_fused_train_step_matches_reference(lcs, torch, n):
     # one fused step (lcs_mlp_train): the loss and every gradient tensor
     # against the FP64 reference at the same BF16 rounding points, the update
