@@ -123,3 +123,47 @@ def test_tuned_equals_plain_and_cache_round_trip(lcs, tmp_path):
     b = lcs.lcs_advect(frames, g, 0.0, 4.0, 0.02)
     lcs.lcs_sync_status()
     assert _same(b, (x4, c4, f4))
+
+
+def _tpair_case(name):
+    """(frames, seeds, t0, T, dt) of the time-paired re-bundling cases."""
+    L = 2 * math.pi
+    if name == "closed_box_exits_nan":
+        fs = inputs.sample_field(inputs.abc_velocity, 3, (33, 33, 33), (0.0,) * 3, (L / 32,) * 3,
+                                 (False,) * 3, 0.0, 0.5, 9).astype(np.float32)
+        fs.u[0][4, 10, 12, 14] = np.nan
+        g = inputs.linspace_seeds(3, (40, 36, 30), (0.3,) * 3, (L - 0.3,) * 3)
+        return fs, g, 0.5, 3.0, 0.02
+    if name == "mixed_periodic":
+        fs = inputs.sample_field(inputs.abc_velocity, 3, (32, 33, 32), (0.0,) * 3, (L / 32,) * 3,
+                                 (True, False, True), 0.0, 0.5, 9).astype(np.float32)
+        g = inputs.SeedGrid(3, (40, 30, 36), (0.0, 0.3, 0.0), (L / 40, (L - 0.6) / 29, L / 36),
+                            (True, False, True))
+        return fs, g, 0.0, 3.5, 0.02
+    if name == "periodic_backward":
+        fs = inputs.abc_frames(n=32, n_frames=17, dt_frame=0.5)
+        return fs, inputs.periodic_seeds(3, (45, 38, 29), (L, L, L)), 8.0, -6.0, -0.02
+    # a 9^3 closed box: the region can cover the whole grid
+    fs = inputs.uniform_frames(np.array([0.37, -0.21, 0.13]), dim=3, n=9, lo=0.0, hi=1.0)
+    g = inputs.linspace_seeds(3, (20, 18, 16), (0.013, 0.011, 0.017), (0.987, 0.989, 0.983))
+    return fs, g, 0.0, 3.0, 0.05
+
+
+@pytest.mark.parametrize("seg", [13, 100])
+@pytest.mark.parametrize("case", ["closed_box_exits_nan", "mixed_periodic", "periodic_backward",
+                                  "small_box"])
+def test_sorted_tpair_equals_plain(lcs, case, seg):
+    """Re-bundled 3D segments on time-paired frames (closed walls with exits
+    and a NaN node, mixed periodic and closed axes, backward time, a grid
+    smaller than a workgroup's spread): the same bits as the single launch."""
+    _say(f"case: sorted 3D on time-paired frames, {case}, segment {seg}")
+    fs, g, t0, T, dt = _tpair_case(case)
+    frames = lcs.DeviceFrames.interleaved(fs, "tpair")
+    a = lcs.lcs_advect(frames, g, t0, T, dt)
+    b = lcs.lcs_advect_sorted(frames, g, t0, T, dt, segment_steps=seg)
+    lcs.lcs_sync_status()
+    if case in ("closed_box_exits_nan", "small_box"):
+        assert int((a[2] != 0).sum()) > 0
+    if case == "closed_box_exits_nan":
+        assert int((a[2] == 2).sum()) > 0           # the NaN node was sampled
+    assert _same(a, b)
