@@ -122,3 +122,19 @@ def test_fp64_error_table_is_zero_for_the_oracle_itself():
     assert errs["clean_stencils"] == 40 and errs["flags_equal"]
     for k in ("xf_abs", "C_rel_frobenius", "lambda_max_rel", "ftle_abs"):
         assert errs[k]["max"] <= 1e-14, (k, errs[k])
+
+
+def test_committed_profile_records_match_the_kernel_sources():
+    # every machine-readable counter record under profiles/ was taken on the
+    # kernel sources as they stand (comments aside): a kernel change must come
+    # with regenerated profiles, or the bench would drop their figures
+    import json
+    recs = []
+    for name in sorted(os.listdir(bench.PROFILES)):
+        if name.endswith(".md"):
+            for line in open(os.path.join(bench.PROFILES, name)).read().splitlines():
+                if line.startswith("{"):
+                    recs.append((name, json.loads(line)))
+    assert {r["kernel"] for _, r in recs} >= {"rebundle_segment_kernel<3, 0>", "training step"}
+    for name, r in recs:
+        assert bench.source_hash(r["source_files"]) == r["source_sha1"], (name, r["kernel"])
