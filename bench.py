@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 # AMD's profiler for this chip) x 256 CUs x 2.4 GHz peak engine clock
 VL1D_PEAK_GBS = 128 * 256 * 2.4
 BYTES_PER_STEP_3D = 768      # 4 evals x 8 corners x 2 frames x 3 comps x 4 B
+N_CUS = 256
+VMEM_FLOOR_CYCLES = 16       # CU cycles per wave load instruction, at least (measured)
 WORKLOAD = dict(name="random_fourier_256cubed_65frames_seeds512x512x256_T4_forward_backward",
                 grid=256, frames=65, dt_frame=0.125, seeds=(512, 512, 256), t0=4.0, T=4.0,
                 dt=0.01)
@@ -136,6 +138,18 @@ def roofline_record(kernel, avg_ms, launches, units_per_launch, workload,
     prof = profiled_record(kernel, workload) or {}
     traffic = prof.get("traffic_bytes_per_launch")
     hbm = traffic / (avg_ms * 1e-3) / 1e9 if traffic else None
+    # the data path's instruction floor: VMEM_FLOOR_CYCLES CU cycles per wave load
+    # instruction times the profile's load instructions per wave-step, against
+    # the measured CU cycles per wave-step (at the profile's mean clock)
+    floor = None
+    lpw, ghz = prof.get("vmem_loads_per_wave_step"), prof.get("mean_clock_ghz")
+    if lpw and ghz:
+        cyc = avg_ms * 1e-3 * ghz * 1e9 * N_CUS / (units_per_launch / 64.0)
+        floor = {"frac": VMEM_FLOOR_CYCLES * lpw / cyc, "loads_per_wave_step": lpw,
+                 "floor_cycles_per_wave_step": VMEM_FLOOR_CYCLES * lpw,
+                 "measured_cycles_per_wave_step": cyc,
+                 "basis": "a wave's 16-byte-per-lane load takes at least 16 CU cycles in the "
+                          "texture data path (one per quad of lanes, inactive quads included)"}
     return {"kernel": kernel, "bound": "vl1d", "achieved": A, "peak": VL1D_PEAK_GBS,
             "unit": "GB/s", "frac": A / VL1D_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, each "
@@ -153,6 +167,7 @@ def roofline_record(kernel, avg_ms, launches, units_per_launch, workload,
             "l2_hit_rate": prof.get("l2_hit_rate"), "l1_hit_rate": prof.get("l1_hit_rate"),
             "ta_busy": prof.get("ta_busy"), "td_busy": prof.get("td_busy"),
             "counters_workload": workload if prof else None,
+            "vmem_instruction_floor": floor,
             "note": "the stencil gathers are served from the per-tracer register cache, L1 and "
                     "L2 (algorithmic_bytes_over_hbm_peak counts them as if none were): the "
                     "kernel's HBM traffic is hbm_frac of the peak, and the texture address / "
