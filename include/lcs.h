@@ -385,8 +385,8 @@ lcs_status lcs_advect_tuned(lcs_plan_t plan, const lcs_velocity_t *vel,
  * Learned flow-map surrogate: a Fourier-feature MLP that predicts the
  * displacement of a point over a window tau (a local approximation of the
  * flow map; the paper's discussion cites such approximations as a way to cut
- * interpolation work on time series of seed grids, Sec. 4).  Plain RK4
- * remains the reference and the fallback.
+ * interpolation work when flow maps are wanted for many start times, Sec. 4).
+ * Plain RK4 remains the reference and the fallback.
  *
  * Fixed architecture: input (x, y, z, t) -> v = (input - in_shift) * in_scale
  * -> 128 features [cos(2 pi B v), sin(2 pi B v)] (B: 64 x 4) -> 4 hidden

@@ -415,8 +415,8 @@ void orc_advect_seeds(const orc_velocity *v, const orc_seed_grid *g, const int64
 /* ------------------------------------------------------------------------ */
 
 /* Flow map at several integration times (Sec. 3.1: the CG tensor can be
- * evaluated at any step of the interval; Sec. 4: the CG tensor at various
- * times).  snap_steps (n_snap values, strictly increasing, >= 1): the step
+ * evaluated at any step of the interval; Sec. 4: CG fields wanted at several
+ * instants).  snap_steps (n_snap values, strictly increasing, >= 1): the step
  * counts at which positions are recorded; xf[(k*dim + a)*m + p] and
  * flags[k*m + p] hold snapshot k (a tracer frozen earlier keeps its frozen
  * position and its flag); steps_done[p] = accepted steps before the tracer

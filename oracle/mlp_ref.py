@@ -5,8 +5,8 @@ imports this module.
 
 The surrogate (a learned local approximation of the flow map over a window
 tau; the paper's discussion cites local flow-map approximation as a way to
-cut interpolation cost for time series of seed grids, Sec. 4) maps an input
-(x, y, z, t) to a displacement dx over the window:
+cut interpolation cost when flow maps are wanted for many start times,
+Sec. 4) maps an input (x, y, z, t) to a displacement dx over the window:
 
   v      = (input - shift) * scale                     (4 values)
   gamma  = [cos(2 pi B v), sin(2 pi B v)]              (B: 64 x 4, 128 features)

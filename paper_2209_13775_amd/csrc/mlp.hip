@@ -2,8 +2,8 @@
 // BF16 MFMA layers with FP32 accumulation, head, loss gradient, backward and
 // Adam.  The surrogate approximates the flow map over a window tau locally in
 // space and time (the paper's discussion cites local flow-map approximation
-// as a way to save interpolation work on time series of seed grids, Sec. 4);
-// plain RK4 stays the fallback and the reference.
+// as a way to save interpolation work when flow maps are wanted for many
+// start times, Sec. 4); plain RK4 stays the fallback and the reference.
 //
 // Matrix products use v_mfma_f32_16x16x32_bf16 (16x16 output tile, K = 32 per
 // instruction).  Lane layout (checked on the device): A fragment = row l%16,
