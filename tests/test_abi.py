@@ -70,6 +70,10 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("frame_over_4gib", lcs.LCS_E_SHAPE),
     ("tpair_in_2d", lcs.LCS_E_ARG),
     ("misaligned_tpair", lcs.LCS_E_ARG),
+    ("empty_seed_axis", lcs.LCS_E_SHAPE),
+    ("single_seed_axis", lcs.LCS_E_SHAPE),
+    ("seed_grid_over_2g", lcs.LCS_E_SHAPE),
+    ("seed_dim_mismatch", lcs.LCS_E_ARG),
 ])
 def test_advect_validation(case, expect):
     v, s = _vel(), _seeds()
@@ -118,6 +122,15 @@ def test_advect_validation(case, expect):
         v.layout = lcs.LCS_LAYOUT_TPAIR
         v.u[0] = 0x1008                # time-paired records need 16-byte alignment
         s.dim, s.n[2], s.spacing[2] = 3, 1, 0.2
+    elif case == "empty_seed_axis":
+        s.n[0] = 0                     # no seeds: the gradient needs two per axis
+    elif case == "single_seed_axis":
+        s.n[1] = 1
+    elif case == "seed_grid_over_2g":
+        s.n[0], s.n[1] = 1 << 16, 1 << 15     # 2^31 seeds
+        s.spacing[0] = s.spacing[1] = 1e-6
+    elif case == "seed_dim_mismatch":
+        s.dim = 3
     elif case == "frame_over_4gib":
         v.layout = lcs.LCS_LAYOUT_XYZ  # 2^29 nodes x 8 B per interleaved 2D frame = 4 GiB
         v.n[0], v.n[1] = 1 << 15, (1 << 14) + 1
