@@ -252,6 +252,7 @@ lcs_status lcs_advect_sorted_noalloc(const lcs_velocity_t *vel, const lcs_seed_g
  *        interval [t0, t0+T] leaves the frame span is not advected and gets
  *        LCS_FLAG_TIME_OUT (its xf is x0).
  * xf, cell, flags as in lcs_advect (cell and flags may be NULL).
+ * n must be in [1, 2^31-1] (LCS_E_SHAPE otherwise, as for lcs_ftle).
  * Errors: LCS_E_ARG, LCS_E_SHAPE, LCS_E_STEP, LCS_E_HIP.
  */
 lcs_status lcs_advect_points(const lcs_velocity_t *vel, const float *x0, const double *t0,
@@ -853,7 +854,8 @@ lcs_status lcs_mesh_advect(lcs_mesh_t mesh, const lcs_mesh_frames_t *frames,
  * lcs_mesh_advect_points -- as lcs_mesh_advect for arbitrary points x0
  * ([device] FP32 dim x n) with their own start times t0 ([device] FP64 n);
  * a point whose interval [t0, t0+T] leaves the frame span is not moved and is
- * flagged LCS_FLAG_TIME_OUT.
+ * flagged LCS_FLAG_TIME_OUT.  n = 0 does nothing (after the mesh, frames and
+ * step count are validated); n must stay below 2^31.
  */
 lcs_status lcs_mesh_advect_points(lcs_mesh_t mesh, const lcs_mesh_frames_t *frames,
                                   const float *x0, const double *t0, int64_t n, double T,
