@@ -383,6 +383,7 @@ lcs_status lcs_mlp_forward(const lcs_mlp_t *mlp, const float *xt, int64_t batch,
         memset(&g, 0, sizeof(g));
         g.A = w.H[l];
         g.Bt = P.wbf + lcs::mlp_off_bf16(l) + (long long)lcs::mlp_in_width(l) * lcs::kMlpWidth;
+        g.bt_frag = 1;                                    // W_l^T, fragment order
         g.M = batch;
         g.N = lcs::kMlpWidth;
         g.K = lcs::mlp_in_width(l);

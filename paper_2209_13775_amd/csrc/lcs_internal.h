@@ -208,7 +208,8 @@ __host__ __device__ constexpr long long mlp_off_b(int l)
 constexpr long long kOffWh = mlp_off_w(kMlpHidden);
 constexpr long long kOffBh = kOffWh + 3LL * kMlpWidth;
 static_assert(kOffBh + 3 == kMlpParams, "parameter layout");
-// BF16 copies: for each hidden layer, W_l as [in][out] then W_l^T as [out][in]
+// BF16 copies: for each hidden layer, W_l as [in][out] (row-major) then W_l^T
+// ([out][in]) in fragment order (frag_index)
 __host__ __device__ constexpr long long mlp_off_bf16(int l)
 {
     return l == 0 ? 0 : mlp_off_bf16(l - 1) + 2LL * mlp_in_width(l - 1) * kMlpWidth;
@@ -224,14 +225,25 @@ struct MlpDev {
     const uint16_t *wbf;
 };
 
+// Element (n, k) of an N x K BF16 matrix kept in MFMA fragment order: blocks
+// of 16 rows x 32 columns (K/32 blocks per block row, block rows in order),
+// each 64 lanes x 8 values, lane (n % 16) + 16 ((k % 32) / 8) holding the 8
+// consecutive k of its row -- so a wave's A-operand fragment of a block is one
+// contiguous 1 KiB.  N % 16 == 0 and K % 32 == 0.
+__host__ __device__ constexpr long long frag_index(int n, int k, int K)
+{
+    return ((long long)(n / 16) * (K / 32) + k / 32) * 512 + ((n % 16) + 16 * ((k % 32) / 8)) * 8 + k % 8;
+}
+
 struct GemmArgs {
     const uint16_t *A;        // [M][K]
-    const uint16_t *Bt;       // [N][K]
+    const uint16_t *Bt;       // [N][K], row-major or (bt_frag) in fragment order
     long long M;
     int N, K;
     const float *bias;        // forward only
     uint16_t *H;              // output [M][N]
     uint16_t *Z;              // forward: pre-activation out (optional); backward: pre-activation in
+    int bt_frag;              // Bt in fragment order (frag_index)
 };
 
 struct WgradArgs {

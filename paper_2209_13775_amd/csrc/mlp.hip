@@ -101,8 +101,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             if (m0 + row < g.M)
                 va = *reinterpret_cast<const uint4 *>(g.A + (m0 + row) * g.K + k0 + kc);
             *reinterpret_cast<uint4 *>(&As[row * kLdsStride + kc]) = va;
-            const uint4 vb = *reinterpret_cast<const uint4 *>(g.Bt + (long long)(n0 + row) * g.K +
-                                                               k0 + kc);
+            const long long bo = g.bt_frag ? frag_index(n0 + row, k0 + kc, g.K)
+                                           : (long long)(n0 + row) * g.K + k0 + kc;
+            const uint4 vb = *reinterpret_cast<const uint4 *>(g.Bt + bo);
             *reinterpret_cast<uint4 *>(&Bs[row * kLdsStride + kc]) = vb;
         }
         __syncthreads();
@@ -379,8 +380,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
     p[i] = p[i] - a.lr * mhat / (sqrtf(vhat) + a.eps);
 }
 
-// BF16 copies of the four hidden-layer matrices in both layouts:
-// W_l as [K][N] (as stored) and W_l^T as [N][K].
+// BF16 copies of the four hidden-layer matrices: W_l as [K][N] (as stored)
+// and W_l^T ([N][K]) in fragment order (frag_index).
 __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restrict__ params,
                                                            uint16_t *__restrict__ out)
 {
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
     const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
     const uint16_t b = f2bf(params[mlp_off_w(l) + r]);
     out[mlp_off_bf16(l) + r] = b;                                   // [K][N]
-    out[mlp_off_bf16(l) + (long long)K * kMlpWidth + (long long)n * K + k] = b;   // [N][K]
+    out[mlp_off_bf16(l) + (long long)K * kMlpWidth + frag_index(n, k, K)] = b;   // W^T, fragment order
 }
 
 // ---------------------------------------------------------------------------
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(kCT, 2) void compose_fused_kernel(ComposeArgs A)
         __syncthreads();
         for (int l = 0; l < kMlpHidden; ++l) {
             const int K = mlp_in_width(l);
-            const uint16_t *Wt = P.wbf + mlp_off_bf16(l) + (long long)K * kMlpWidth;   // [256][K]
+            const uint16_t *Wt = P.wbf + mlp_off_bf16(l) + (long long)K * kMlpWidth;   // W^T, fragment order
             const float *bias = P.params + mlp_off_b(l);
             // the transposed product out^T[n][m] = sum_k W^T[n][k] act[m][k]: weights
             // as the A operand, activations as B, so that a lane's four results
@@ -492,12 +493,12 @@ __global__ __launch_bounds__(kCT, 2) void compose_fused_kernel(ComposeArgs A)
                 for (int i = 0; i < 8; ++i) acc[i][j] = b4;
             }
             const int ko = 8 * (lane / 16);
+            // a wave's weight fragment of one 16 x 32 block: 1 KiB contiguous
             auto load_w = [&](int kk, bf16x8 *w) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int n = wave * 32 + 16 * j + lane % 16;
-                    w[j] = *reinterpret_cast<const bf16x8 *>(Wt + (long long)n * K + kk + ko);
-                }
+                for (int j = 0; j < 2; ++j)
+                    w[j] = *reinterpret_cast<const bf16x8 *>(
+                        Wt + (uint32_t)(((wave * 2 + j) * (K / 32) + kk / 32) * 512 + lane * 8));
             };
             auto mfma_slice = [&](int kk, const bf16x8 *w) {
 #pragma unroll

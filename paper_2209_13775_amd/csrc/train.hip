@@ -85,21 +85,29 @@ __device__ __forceinline__ void gelu_pair(float z, float &h, float &d)
 }
 
 // One layer's product for the tile, transposed: out^T[n][m] = sum_k A[n][k] act[m][k]
-// with A rows from global memory (BF16, row length K) and the activations in
-// LDS; wave w owns outputs 32w .. 32w+31.  acc must hold the starting values.
-// The next 32-wide slice of A is loaded while the current one's products run.
-template <int K>
+// with A from global memory (BF16, N x K, row-major or -- FRAG -- in fragment
+// order, where a wave's fragment is one contiguous 1 KiB) and the activations
+// in LDS; wave w owns outputs 32w .. 32w+31.  acc must hold the starting
+// values.  The next 32-wide slice of A is loaded while the current one's
+// products run.
+template <int K, bool FRAG>
 __device__ __forceinline__ void tile_product(const uint16_t *__restrict__ Arows, const uint16_t *act,
                                              f32x4 (&acc)[8][kNJ], int wave, int lane)
 {
     static_assert(K % 64 == 0, "K must be a multiple of 64");
     const int ko = 8 * (lane / 16);
+    // per output block j, the lane's 32-bit element offset at k = 0 (a matrix
+    // holds at most 256 x 256 values); a k-slice adds a wave-uniform step
+    uint32_t base[kNJ];
+#pragma unroll
+    for (int j = 0; j < kNJ; ++j)
+        base[j] = FRAG ? (uint32_t)((wave * kNJ + j) * (K / 32) * 512 + lane * 8)
+                       : (uint32_t)((wave * 16 * kNJ + 16 * j + lane % 16) * K + ko);
     auto load_a = [&](int kk, bf16x8 *w) {
 #pragma unroll
-        for (int j = 0; j < kNJ; ++j) {
-            const int n = wave * 16 * kNJ + 16 * j + lane % 16;
-            w[j] = *reinterpret_cast<const bf16x8 *>(Arows + (long long)n * K + kk + ko);
-        }
+        for (int j = 0; j < kNJ; ++j)
+            w[j] = *reinterpret_cast<const bf16x8 *>(Arows + base[j] + (FRAG ? (uint32_t)(kk / 32 * 512)
+                                                                          : (uint32_t)kk));
     };
     auto slice = [&](int kk, const bf16x8 *w) {
 #pragma unroll
@@ -200,10 +208,10 @@ __global__ __launch_bounds__(kTT, 4) void train_fwd_kernel(TrainArgs A)
 #pragma unroll
             for (int i = 0; i < 8; ++i) acc[i][j] = b4;
         }
-        // W_l^T rows ([out][in] copy)
+        // W_l^T ([out][in] copy, fragment order)
         const uint16_t *Wt = P.wbf + mlp_off_bf16(l) + (long long)mlp_in_width(l) * kMlpWidth;
-        if (l == 0) tile_product<kMlpFeat>(Wt, act, acc, wave, lane);
-        else tile_product<kMlpWidth>(Wt, act, acc, wave, lane);
+        if (l == 0) tile_product<kMlpFeat, true>(Wt, act, acc, wave, lane);
+        else tile_product<kMlpWidth, true>(Wt, act, acc, wave, lane);
         __syncthreads();   // every wave has read the layer input
         uint16_t *dl = A.dgelu[l];
 #pragma unroll
@@ -341,7 +349,7 @@ __global__ __launch_bounds__(kTT, 4) void train_bwd_kernel(TrainArgs A)
         for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int j = 0; j < kNJ; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-        tile_product<kMlpWidth>(P.wbf + mlp_off_bf16(l), act, acc, wave, lane);
+        tile_product<kMlpWidth, false>(P.wbf + mlp_off_bf16(l), act, acc, wave, lane);
         __syncthreads();
         const uint16_t *dl = A.dgelu[l - 1];
 #pragma unroll
@@ -498,7 +506,7 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs
         A.v[i] = vi;
         const float pi = A.params[i] - ad.lr * (mi * ad.c1) / (sqrtf(vi * ad.c2) + ad.eps);
         A.params[i] = pi;
-        // BF16 copies of the hidden weights: [in][out] and [out][in]
+        // BF16 copies of the hidden weights: [in][out], and [out][in] in fragment order
         int l = 0;
         while (l + 1 < kMlpHidden && i >= mlp_off_w(l + 1)) ++l;
         if (i < kOffWh && i < mlp_off_b(l)) {
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs
             const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
             const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
             A.wbf[mlp_off_bf16(l) + r] = b;
-            A.wbf[mlp_off_bf16(l) + (long long)K * kMlpWidth + (long long)n * K + k] = b;
+            A.wbf[mlp_off_bf16(l) + (long long)K * kMlpWidth + frag_index(n, k, K)] = b;
         }
     }
     if (blockIdx.x == 0 && A.loss) {

@@ -65,6 +65,18 @@ def _oracle_params(params):
     return p
 
 
+def _fragment_order(WT):
+    """An N x K matrix laid out as the BF16 W^T copies are (the MFMA fragment
+    order the header documents): blocks of 16 x 32, each 64 lanes x 8 k."""
+    N, K = WT.shape
+    n = np.arange(N)[:, None]
+    k = np.arange(K)[None, :]
+    idx = ((n // 16) * (K // 32) + k // 32) * 512 + ((n % 16) + 16 * ((k % 32) // 8)) * 8 + k % 8
+    out = np.empty(N * K, dtype=WT.dtype)
+    out[idx.ravel()] = WT.ravel()
+    return out
+
+
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
@@ -81,7 +93,7 @@ def test_bf16_copies_exact(lcs, torch):
         W = params[off_p:off_p + K * N].reshape(K, N)
         want = M.round_to_bf16(W).astype(np.float32).view(np.uint32) >> 16
         np.testing.assert_array_equal(got[off_b:off_b + K * N].reshape(K, N), want)
-        np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N].reshape(N, K), want.T)
+        np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N], _fragment_order(want.T))
         off_b += 2 * K * N
         off_p += K * N + N
 
@@ -239,7 +251,7 @@ def test_fused_train_step_matches_reference(lcs, torch, n):
         W = pn[off_p:off_p + K * N].reshape(K, N)
         want = M.round_to_bf16(W).astype(np.float32).view(np.uint32) >> 16
         np.testing.assert_array_equal(got[off_b:off_b + K * N].reshape(K, N), want)
-        np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N].reshape(N, K), want.T)
+        np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N], _fragment_order(want.T))
         off_b += 2 * K * N
         off_p += K * N + N
 
