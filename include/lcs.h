@@ -400,10 +400,11 @@ lcs_status lcs_advect_tuned(lcs_plan_t plan, const lcs_velocity_t *vel,
  *   W_l [256][256], b_l [256] for l = 1, 2, 3,
  *   W_h [256][3], b_h [3].
  * BF16 compute copies (LCS_MLP_BF16 values, written by lcs_mlp_refresh_bf16):
- *   for l = 0..3: W_l as [in][out] (row-major), then W_l^T ([out][in], N = 256
- *   rows of K = in values) in MFMA fragment order: element (n, k) at
- *   ((n/16)*(K/32) + k/32)*512 + ((n%16) + 16*((k%32)/8))*8 + k%8, so that each
- *   16 x 32 block is 64 lanes x 8 consecutive k, one contiguous 1 KiB.
+ *   for l = 0..3: W_l ([in][out]: R = in rows of C = 256 values), then W_l^T
+ *   ([out][in]: R = 256 rows of C = in values), each in MFMA fragment order:
+ *   element (r, c) at ((r/16)*(C/32) + c/32)*512 + ((r%16) + 16*((c%32)/8))*8
+ *   + c%8, so that each 16 x 32 block is 64 lanes x 8 consecutive c, one
+ *   contiguous 1 KiB.
  * ------------------------------------------------------------------------ */
 #define LCS_MLP_FREQ 64
 #define LCS_MLP_WIDTH 256

@@ -446,6 +446,7 @@ lcs_status lcs_mlp_backward(const lcs_mlp_t *mlp, const void *workspace, const f
             memset(&g, 0, sizeof(g));
             g.A = cur;                                        // dZ_{l+1} [B][256]
             g.Bt = P.wbf + lcs::mlp_off_bf16(l);              // W_l as [in][out] = Bt[N=in][K=out]
+            g.bt_frag = 1;                                    // fragment order
             g.M = batch;
             g.N = K;
             g.K = lcs::kMlpWidth;

@@ -208,8 +208,8 @@ __host__ __device__ constexpr long long mlp_off_b(int l)
 constexpr long long kOffWh = mlp_off_w(kMlpHidden);
 constexpr long long kOffBh = kOffWh + 3LL * kMlpWidth;
 static_assert(kOffBh + 3 == kMlpParams, "parameter layout");
-// BF16 copies: for each hidden layer, W_l as [in][out] (row-major) then W_l^T
-// ([out][in]) in fragment order (frag_index)
+// BF16 copies: for each hidden layer, W_l ([in][out]) then W_l^T ([out][in]),
+// both in fragment order (frag_index)
 __host__ __device__ constexpr long long mlp_off_bf16(int l)
 {
     return l == 0 ? 0 : mlp_off_bf16(l - 1) + 2LL * mlp_in_width(l - 1) * kMlpWidth;

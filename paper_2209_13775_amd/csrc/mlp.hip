@@ -380,8 +380,8 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, const 
     p[i] = p[i] - a.lr * mhat / (sqrtf(vhat) + a.eps);
 }
 
-// BF16 copies of the four hidden-layer matrices: W_l as [K][N] (as stored)
-// and W_l^T ([N][K]) in fragment order (frag_index).
+// BF16 copies of the four hidden-layer matrices, both in fragment order
+// (frag_index): W_l ([K][N], as stored) and W_l^T ([N][K]).
 __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restrict__ params,
                                                            uint16_t *__restrict__ out)
 {
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *__restri
     const int K = mlp_in_width(l);
     const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
     const uint16_t b = f2bf(params[mlp_off_w(l) + r]);
-    out[mlp_off_bf16(l) + r] = b;                                   // [K][N]
+    out[mlp_off_bf16(l) + frag_index(k, n, kMlpWidth)] = b;         // W, fragment order
     out[mlp_off_bf16(l) + (long long)K * kMlpWidth + frag_index(n, k, K)] = b;   // W^T, fragment order
 }
 

@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kTT, 4) void train_bwd_kernel(TrainArgs A)
         for (int i = 0; i < 8; ++i)
 #pragma unroll
             for (int j = 0; j < kNJ; ++j) acc[i][j] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
-        tile_product<kMlpWidth, false>(P.wbf + mlp_off_bf16(l), act, acc, wave, lane);
+        tile_product<kMlpWidth, true>(P.wbf + mlp_off_bf16(l), act, acc, wave, lane);
         __syncthreads();
         const uint16_t *dl = A.dgelu[l - 1];
 #pragma unroll
@@ -506,7 +506,7 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs
         A.v[i] = vi;
         const float pi = A.params[i] - ad.lr * (mi * ad.c1) / (sqrtf(vi * ad.c2) + ad.eps);
         A.params[i] = pi;
-        // BF16 copies of the hidden weights: [in][out], and [out][in] in fragment order
+        // BF16 copies of the hidden weights, [in][out] and [out][in], in fragment order
         int l = 0;
         while (l + 1 < kMlpHidden && i >= mlp_off_w(l + 1)) ++l;
         if (i < kOffWh && i < mlp_off_b(l)) {
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void train_update_kernel(TrainArgs A, AdamArgs
             const int K = mlp_in_width(l);
             const int k = (int)(r / kMlpWidth), n = (int)(r % kMlpWidth);
             const uint16_t b = __builtin_bit_cast(uint16_t, (__bf16)pi);
-            A.wbf[mlp_off_bf16(l) + r] = b;
+            A.wbf[mlp_off_bf16(l) + frag_index(k, n, kMlpWidth)] = b;
             A.wbf[mlp_off_bf16(l) + (long long)K * kMlpWidth + frag_index(n, k, K)] = b;
         }
     }

@@ -66,8 +66,8 @@ def _oracle_params(params):
 
 
 def _fragment_order(WT):
-    """An N x K matrix laid out as the BF16 W^T copies are (the MFMA fragment
-    order the header documents): blocks of 16 x 32, each 64 lanes x 8 k."""
+    """An R x C matrix laid out as the BF16 weight copies are (the MFMA fragment
+    order the header documents): blocks of 16 x 32, each 64 lanes x 8 c."""
     N, K = WT.shape
     n = np.arange(N)[:, None]
     k = np.arange(K)[None, :]
@@ -92,7 +92,7 @@ def test_bf16_copies_exact(lcs, torch):
         K, N = M.SHAPES[2 * t]
         W = params[off_p:off_p + K * N].reshape(K, N)
         want = M.round_to_bf16(W).astype(np.float32).view(np.uint32) >> 16
-        np.testing.assert_array_equal(got[off_b:off_b + K * N].reshape(K, N), want)
+        np.testing.assert_array_equal(got[off_b:off_b + K * N], _fragment_order(want))
         np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N], _fragment_order(want.T))
         off_b += 2 * K * N
         off_p += K * N + N
@@ -250,7 +250,7 @@ def test_fused_train_step_matches_reference(lcs, torch, n):
         K, N = M.SHAPES[2 * t]
         W = pn[off_p:off_p + K * N].reshape(K, N)
         want = M.round_to_bf16(W).astype(np.float32).view(np.uint32) >> 16
-        np.testing.assert_array_equal(got[off_b:off_b + K * N].reshape(K, N), want)
+        np.testing.assert_array_equal(got[off_b:off_b + K * N], _fragment_order(want))
         np.testing.assert_array_equal(got[off_b + K * N:off_b + 2 * K * N], _fragment_order(want.T))
         off_b += 2 * K * N
         off_p += K * N + N
