@@ -234,7 +234,7 @@ lcs_status lcs_advect_sorted(const lcs_velocity_t *vel, const lcs_seed_grid_t *s
  * results; serialise them.
  * Errors: those of lcs_advect_sorted, and LCS_E_SHAPE when the grid needs
  * more workspace than the array holds (lcs_advect_sorted_workspace_bytes >
- * LCS_NOALLOC_SCRATCH_BYTES; about 65 B per seed plus 4 B per sort bin).
+ * LCS_NOALLOC_SCRATCH_BYTES; about 70 B per seed plus 4 B per sort bin).
  */
 #define LCS_NOALLOC_SCRATCH_BYTES (64LL << 20)
 lcs_status lcs_advect_sorted_noalloc(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,

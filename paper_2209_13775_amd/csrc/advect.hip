@@ -997,7 +997,9 @@ __device__ __forceinline__ uint32_t bin_key(const VelDev &v, const SortKeys &k, 
 // counts[key] += 1 for every active lane, one atomic per run of consecutive
 // active lanes with equal keys (tracers that stay together keep landing in the
 // same bin, and same-address atomics from one wave serialise).  Returns the
-// lane's slot: the counter's old value plus the lane's rank in its run.
+// lane's rank among the slots of its key: the counter's old value plus the
+// lane's rank in its run (kept, so the permutation needs no second pass of
+// atomics).
 __device__ __forceinline__ uint32_t run_atomic_inc(uint32_t *counts, uint32_t key)
 {
     const uint64_t act = __ballot(1);
@@ -1057,13 +1059,13 @@ __global__ __launch_bounds__(256) void rebundle_init_kernel(SegmentArgs A)
         for (int q = 0; q < 3 * D; ++q) A.st.hist[q][p] = 0.0f;
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
-    (void)run_atomic_inc(A.sk.counts, key);
+    A.sk.rank[p] = run_atomic_inc(A.sk.counts, key);
 }
 
 // Steps [n_begin, n_end) for every tracer slot p of the sorted order, whose
 // state is read from slot perm[p] of the previous order; then either the
 // outputs (last segment) or the state at slot p of the other buffer plus its
-// new key and the histogram.
+// new key, the histogram and the slot's rank within its key.
 template <int D, int S>
 __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_segment_kernel(SegmentArgs A)
 {
@@ -1122,7 +1124,7 @@ __global__ __launch_bounds__(256, S == 0 ? LCS_RK4_MIN_WAVES : 1) void rebundle_
     }
     const uint32_t key = bin_key<D>(A.v, A.sk, xh);
     A.sk.keys[p] = key;
-    (void)run_atomic_inc(A.sk.counts, key);
+    A.sk.rank[p] = run_atomic_inc(A.sk.counts, key);
 }
 
 // Exclusive scan of the counts: blocks of 1024 (4 per thread), block totals,
@@ -1193,8 +1195,10 @@ __global__ __launch_bounds__(256) void permute_kernel(SortKeys sk, long long n)
 {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const uint32_t key = sk.keys[p];
-    const long long q = run_atomic_inc(sk.counts, key);
+    // counts holds each key's first sorted slot (the scanned histogram) and
+    // rank the slot's place among its key's slots, taken when the histogram
+    // was counted: together a bijection onto [0, n)
+    const long long q = (long long)sk.counts[sk.keys[p]] + sk.rank[p];
     if (q >= n) return;   // cannot happen when the histogram matches the keys
     sk.perm[q] = (uint32_t)p;
 }

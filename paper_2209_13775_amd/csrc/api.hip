@@ -946,6 +946,7 @@ SortedLayout sorted_layout(const lcs_velocity_t *vel, long long n, char *base, l
     }
     L.sk.keys = reinterpret_cast<uint32_t *>(take(4 * n));
     L.sk.perm = reinterpret_cast<uint32_t *>(take(4 * n));
+    L.sk.rank = reinterpret_cast<uint32_t *>(take(4 * n));
     L.sk.counts = reinterpret_cast<uint32_t *>(take(4 * nk));
     L.sk.block_sums = reinterpret_cast<uint32_t *>(take(4 * ((nk + 1023) / 1024 + 1)));
     L.bytes = off;

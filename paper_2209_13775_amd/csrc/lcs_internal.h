@@ -360,6 +360,7 @@ struct SortKeys {
     uint32_t *counts;                 // [n_keys]; turned into offsets by the scan
     uint32_t *block_sums;             // scan scratch
     uint32_t *perm;                   // [N]: sorted slot -> slot of the state it reads
+    uint32_t *rank;                   // [N]: slot's place among the slots of its key (histogram)
     long long n_keys;
 };
 
