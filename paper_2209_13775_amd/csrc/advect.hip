@@ -789,30 +789,46 @@ __global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const f
     if (S == 4) o[3] = 0.0f;
 }
 
-// Time-paired records: one thread per record q of pair p = pair0 + blockIdx.y
-// (frames f_first + p and f_first + p + 1) on the grid with n0 + 1 nodes per
-// row, the last repeating node 0 of the row.  The records of one pair number
-// fewer than 2^28 (a frame-pair block is limited to 4 GiB), so the index
-// arithmetic within a pair is 32-bit.
-__global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *u0, const float *u1,
-                                                               const float *u2, int n0, int n1,
-                                                               int n2, long long f_first,
-                                                               long long pair0, float *out)
+// Time-paired records: one thread per record q on the grid with n0 + 1 nodes
+// per row (the last repeating node 0 of the row), for the kTPairRun
+// consecutive pairs p = pair0 + kTPairRun*blockIdx.y .. (< pairs) (frames
+// f_first + p and f_first + p + 1): the frame two neighbouring pairs share
+// stays in registers, so each frame is read once per run instead of twice.
+// The records of one pair number fewer than 2^28 (a frame-pair block is
+// limited to 4 GiB), so the index arithmetic within a pair is 32-bit.
+constexpr int kTPairRun = 8;
+
+__global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *__restrict__ u0,
+                                                               const float *__restrict__ u1,
+                                                               const float *__restrict__ u2,
+                                                               int n0, int n1, int n2,
+                                                               long long f_first, long long pair0,
+                                                               long long pairs,
+                                                               float *__restrict__ out)
 {
     const uint32_t w = (uint32_t)n0 + 1u;
     const uint32_t per_pair = w * (uint32_t)n1 * (uint32_t)n2;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= per_pair) return;
-    const long long p = pair0 + (long long)blockIdx.y;
+    const long long p0 = pair0 + (long long)kTPairRun * blockIdx.y;
+    const long long p1 = (pairs - p0 < kTPairRun) ? pairs : p0 + kTPairRun;
     const uint32_t row = q / w;                    // j + n1*k
     const uint32_t i = q - row * w;
     const long long nodes = (long long)n0 * n1 * n2;
     const long long node = (long long)row * n0 + (i == (uint32_t)n0 ? 0u : i);
-    const long long a = (f_first + p) * nodes + node, b = a + nodes;
-    float2 *o = reinterpret_cast<float2 *>(out + (p * (long long)per_pair + q) * 6);
-    o[0] = make_float2(u0[a], u1[a]);
-    o[1] = make_float2(u2[a], u0[b]);
-    o[2] = make_float2(u1[b], u2[b]);
+    long long a = (f_first + p0) * nodes + node;
+    float x0 = u0[a], y0 = u1[a], z0 = u2[a];
+    for (long long p = p0; p < p1; ++p) {
+        a += nodes;
+        const float x1 = u0[a], y1 = u1[a], z1 = u2[a];
+        float2 *o = reinterpret_cast<float2 *>(out + (p * (long long)per_pair + q) * 6);
+        o[0] = make_float2(x0, y0);
+        o[1] = make_float2(z0, x1);
+        o[2] = make_float2(y1, z1);
+        x0 = x1;
+        y0 = y1;
+        z0 = z1;
+    }
 }
 
 __global__ void reset_counter_kernel(int *counter)
@@ -1370,10 +1386,11 @@ hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_co
     if (per_pair <= 0 || pairs <= 0) return hipSuccess;
     if (per_pair >= (1LL << 32)) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((per_pair + 255) / 256);
-    for (long long p0 = 0; p0 < pairs; p0 += 65535) {   // grid y covers up to 65535 pairs
-        const unsigned by = (unsigned)(pairs - p0 < 65535 ? pairs - p0 : 65535);
+    const long long runs = (pairs + kTPairRun - 1) / kTPairRun;
+    for (long long r0 = 0; r0 < runs; r0 += 65535) {   // grid y covers up to 65535 runs
+        const unsigned by = (unsigned)(runs - r0 < 65535 ? runs - r0 : 65535);
         hipLaunchKernelGGL(interleave_tpair_kernel, dim3(bx, by), dim3(256), 0, s, u[0], u[1], u[2],
-                           n[0], n[1], n[2], (long long)f_first, p0, out);
+                           n[0], n[1], n[2], (long long)f_first, r0 * kTPairRun, pairs, out);
     }
     return hipGetLastError();
 }
