@@ -211,7 +211,8 @@ lcs_status lcs_advect(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds,
  * spatially coherent re-bundling as a remedy.)
  *
  * workspace [device] of at least lcs_advect_sorted_workspace_bytes(vel, seeds)
- * bytes (about 63 B per seed): two copies of the tracer state, keys, the bin
+ * bytes (about 70 B per seed plus 4 B per sort bin): two copies of the tracer
+ * state, each slot's key and rank within its key, the permutation, the bin
  * histogram.  Other arguments and errors as lcs_advect.
  */
 int64_t lcs_advect_sorted_workspace_bytes(const lcs_velocity_t *vel, const lcs_seed_grid_t *seeds);
