@@ -76,26 +76,29 @@ def test_interleave_copies_exactly(lcs, torch, dim, layout):
     assert il.desc.layout == (lcs.LCS_LAYOUT_XYZW if S == 4 else lcs.LCS_LAYOUT_XYZ)
 
 
-@pytest.mark.parametrize("periodic", [True, False])
-def test_tpair_records_exact(lcs, torch, periodic):
+@pytest.mark.parametrize("periodic,n_frames,f_first,f_count",
+                         [(True, 6, 1, 4), (False, 6, 1, 4), (True, 24, 2, 21)])
+def test_tpair_records_exact(lcs, torch, periodic, n_frames, f_first, f_count):
     """Time-paired records: frames p and p+1 of each node side by side, one
-    extra node per x row repeating node 0."""
-    fs = inputs.random_frames(3, (9, 7, 5), 6, seed=4,
+    extra node per x row repeating node 0 (3 pairs; and 20 pairs, which the
+    staging kernel takes as runs of 8, 8 and 4)."""
+    fs = inputs.random_frames(3, (9, 7, 5), n_frames, seed=4,
                               periodic=(True, True, True) if periodic else None).astype(np.float32)
     soa = lcs.DeviceFrames(fs)
-    il = lcs.lcs_frames_interleave(soa, "tpair", f_first=1, f_count=4)
+    il = lcs.lcs_frames_interleave(soa, "tpair", f_first=f_first, f_count=f_count)
     lcs.lcs_sync_status()
-    got = _np(il.u[0]).reshape(3, 5, 7, 10, 6)
-    u = [np.asarray(c)[1:5] for c in fs.u]          # (4, 5, 7, 9) per component
-    for p in range(3):
+    pairs = f_count - 1
+    got = _np(il.u[0]).reshape(pairs, 5, 7, 10, 6)
+    u = [np.asarray(c)[f_first:f_first + f_count] for c in fs.u]   # (f_count, 5, 7, 9) per component
+    for p in range(pairs):
         for c in range(3):
             np.testing.assert_array_equal(got[p, :, :, :9, c], u[c][p])
             np.testing.assert_array_equal(got[p, :, :, :9, 3 + c], u[c][p + 1])
             np.testing.assert_array_equal(got[p, :, :, 9, c], u[c][p][:, :, 0])
             np.testing.assert_array_equal(got[p, :, :, 9, 3 + c], u[c][p + 1][:, :, 0])
-    assert il.desc.layout == lcs.LCS_LAYOUT_TPAIR and il.desc.n_frames == 4
-    assert il.desc.t_first == fs.t_first + fs.dt_frame
-    want = lcs.lib().lcs_frames_interleave_floats(soa.ref, lcs.LCS_LAYOUT_TPAIR, 4)
+    assert il.desc.layout == lcs.LCS_LAYOUT_TPAIR and il.desc.n_frames == f_count
+    assert il.desc.t_first == fs.t_first + f_first * fs.dt_frame
+    want = lcs.lib().lcs_frames_interleave_floats(soa.ref, lcs.LCS_LAYOUT_TPAIR, f_count)
     assert want == il.u[0].numel()
 
 
