@@ -81,6 +81,22 @@ def test_sorted_equals_plain_with_coarse_bins(lcs):
     assert _same(a, b)
 
 
+def test_sorted_equals_plain_with_crowded_bins(lcs):
+    # 3 x 3 nodes: four sort bins for 90,000 tracers (~22,500 per bin, the
+    # slot ranks the histogram hands out run that high), half of them leaving
+    # the closed box and frozen on its edge
+    _say("case: sorted 2D, 90,000 tracers in four one-cell bins")
+    fs = inputs.uniform_frames(np.array([0.31, -0.17]), dim=2, n=3, lo=0.0, hi=1.0)
+    g = inputs.linspace_seeds(2, (300, 300), (0.005, 0.005), (0.995, 0.995))
+    frames = lcs.DeviceFrames(fs)
+    a = lcs.lcs_advect(frames, g, 0.0, 2.0, 0.05)
+    b = lcs.lcs_advect_sorted(frames, g, 0.0, 2.0, 0.05, segment_steps=10)
+    lcs.lcs_sync_status()
+    assert _same(a, b)
+    n_out = int((a[2] != 0).sum())
+    assert 0 < n_out < g.count
+
+
 def test_tuned_equals_plain_and_cache_round_trip(lcs, tmp_path):
     # the autotuner times every candidate once, keeps the fastest, writes it to
     # the cache; a second plan reads the cache and runs the choice without
