@@ -369,10 +369,11 @@ def cpu_model():
     return None
 
 
-def bench_batched(torch, lcs, inputs, reps=3, layout="xyz"):
-    """Double gyre on 1025x513 nodes x 101 FP32 frames (t = 0.25 f); 64 windows
-    (t0 ~ U[0,10], T from {5, 7.5, 10, 12.5, 15}, default_rng(0)) of a
-    1024x512 seed grid, dt = 0.05, all in one graph-replayed persistent launch."""
+def bench_batched(torch, lcs, inputs, reps=3, layout="tpair"):
+    """Double gyre on 1025x513 nodes x 101 FP32 frames (t = 0.25 f), read as
+    time-paired records; 64 windows (t0 ~ U[0,10], T from {5, 7.5, 10, 12.5,
+    15}, default_rng(0)) of a 1024x512 seed grid, dt = 0.05, all in one
+    graph-replayed persistent launch."""
     fs = inputs.double_gyre_frames(nx=1025, ny=513, n_frames=101, dt_frame=0.25,
                                    dtype=np.float32)
     g = inputs.linspace_seeds(2, (1024, 512), (0.0, 0.0), (2.0, 1.0))

@@ -89,14 +89,15 @@ enum {
  *                    (8-byte in 2D).
  *   LCS_LAYOUT_XYZW  3D only: u[0][(f*N + node)*4 + c], the 4th float unused;
  *                    16-byte aligned.
- *   LCS_LAYOUT_TPAIR 3D only, time-paired records: for each frame pair
- *                    (p, p+1), p < n_frames-1, and each node of a grid with
- *                    one extra x node (n0+1 per row; the extra node repeats
- *                    node 0 of the row), the 6 floats of frame p then frame
- *                    p+1:  u[0][(((p*n2 + k)*n1 + j)*(n0+1) + i)*6 + c'],
- *                    c' < 3 frame p, c' >= 3 frame p+1; 16-byte aligned;
- *                    (n_frames-1)*(n0+1)*n1*n2*24 bytes.  The two x nodes of
- *                    a cell row and both frames are then 48 contiguous bytes.
+ *   LCS_LAYOUT_TPAIR time-paired records: for each frame pair (p, p+1),
+ *                    p < n_frames-1, and each node of a grid with one extra
+ *                    x node (n0+1 per row; the extra node repeats node 0 of
+ *                    the row), the dim floats of frame p then those of frame
+ *                    p+1:  u[0][(((p*n2 + k)*n1 + j)*(n0+1) + i)*2*dim + c'],
+ *                    c' < dim frame p, c' >= dim frame p+1; 16-byte aligned;
+ *                    (n_frames-1)*(n0+1)*n1*n2*8*dim bytes.  The two x nodes
+ *                    of a cell row and both frames are then 16*dim contiguous
+ *                    bytes.
  *              Every layout gives the same field; the interleaved ones need
  *              fewer memory transactions per interpolation (one record per
  *              node instead of one value per component array), see
@@ -158,7 +159,7 @@ typedef struct lcs_plan *lcs_plan_t;
 /*
  * lcs_frames_interleave -- copy frames f_first .. f_first+f_count-1 of a
  * structure-of-arrays velocity (layout LCS_LAYOUT_SOA) into an interleaved
- * layout (LCS_LAYOUT_XYZ; in 3D also LCS_LAYOUT_XYZW or LCS_LAYOUT_TPAIR) on
+ * layout (LCS_LAYOUT_XYZ or LCS_LAYOUT_TPAIR; in 3D also LCS_LAYOUT_XYZW) on
  * the device, and describe the copy (Sec. 2 Reader/Cache filters: velocity
  * data staged in GPU memory in the form the kernels read).
  * out       [device] FP32, lcs_frames_interleave_floats(soa, layout, f_count)
@@ -171,7 +172,7 @@ lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int
                                  void *stream);
 
 /* Floats that f_count frames of soa's grid occupy in an interleaved layout
- * (f_count * N * S for XYZ / XYZW; (f_count-1) * (n0+1)*n1*n2 * 6 for TPAIR),
+ * (f_count * N * S for XYZ / XYZW; (f_count-1) * (n0+1)*n1*n2 * 2*dim for TPAIR),
  * or -1 for an invalid layout, dimension or f_count < 2. */
 int64_t lcs_frames_interleave_floats(const lcs_velocity_t *soa, uint32_t layout, int32_t f_count);
 

@@ -104,9 +104,10 @@ __device__ __forceinline__ void frame_at_uniform(const VelDev &v, double t, long
 // Frame layouts: structure of arrays (one array per component; the x pair
 // (i, i+1) of a cell row is one 8-byte load per component), interleaved
 // records (2, 3 or 4 floats per node with the components together; one 12-byte
-// load per node in 3D, one 16-byte load per x pair in 2D) or, in 3D,
-// time-paired records (both frames of a pair per node, an extra node per x row;
-// the x pair of a cell row in both frames is three 16-byte loads).  Every load
+// load per node in 3D, one 16-byte load per x pair in 2D) or time-paired
+// records (both frames of a pair per node, 2*dim floats, an extra node per x
+// row; the x pair of a cell row in both frames is three 16-byte loads in 3D,
+// two in 2D).  Every load
 // is a 32-bit byte offset from a wave-uniform frame base.
 
 // Corner values of the cell a tracer sampled last, for both frames of the
@@ -195,9 +196,24 @@ __device__ __forceinline__ void gather_cell(const VelDev &v, long long base, con
 {
     constexpr int R = CellCache<D>::R;
     const long long fs = v.frame_stride;
-    if constexpr (L == kLayTPair) {
-        // time-paired records: per row the lower and upper x node, both frames,
-        // in 48 contiguous bytes (a wrapped cell reads the row's extra node)
+    if constexpr (L == kLayTPair && D == 2) {
+        // time-paired records (2D): per row the lower and upper x node, both
+        // frames, in 32 contiguous bytes (a wrapped cell reads the row's extra
+        // node)
+        const char *__restrict__ P = reinterpret_cast<const char *>(v.ilv_u + base * 4);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t e = rowb[r] + xb0;
+            const float4 q0 = load_at<float4>(P, e), q1 = load_at<float4>(P, e + 16u);
+            c[0][r][0][0] = q0.x; c[0][r][0][1] = q0.y;
+            c[1][r][0][0] = q0.z; c[1][r][0][1] = q0.w;
+            c[0][r][1][0] = q1.x; c[0][r][1][1] = q1.y;
+            c[1][r][1][0] = q1.z; c[1][r][1][1] = q1.w;
+        }
+    } else if constexpr (L == kLayTPair) {
+        // time-paired records (3D): per row the lower and upper x node, both
+        // frames, in 48 contiguous bytes (a wrapped cell reads the row's extra
+        // node)
         const char *__restrict__ P = reinterpret_cast<const char *>(v.ilv_u + base * 6);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -452,9 +468,8 @@ template <int D, bool UNIFORM_T = true>
 __device__ uint32_t advect_steps(const VelDev &v, float *xh, float *xl, double t0, double dt,
                                  int n_begin, int n_end, int *n_stop = nullptr)
 {
-    if constexpr (D == 3)
-        if (v.ilv == 6)
-            return advect_steps_l<D, UNIFORM_T, kLayTPair>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
+    if (v.ilv == 2 * D)   // time-paired records (interleaved records have dim or 4 floats, 4 only in 3D)
+        return advect_steps_l<D, UNIFORM_T, kLayTPair>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
     if (v.ilv)
         return advect_steps_l<D, UNIFORM_T, kLayInterleaved>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
     return advect_steps_l<D, UNIFORM_T, kLaySoa>(v, xh, xl, t0, dt, n_begin, n_end, n_stop);
@@ -634,8 +649,7 @@ template <int D, int S>
 __device__ uint32_t advect_steps_ab(const VelDev &v, float *xh, float *xl, float (*hist)[3],
                                     double t0, double dt, int n_begin, int n_end)
 {
-    if constexpr (D == 3)
-        if (v.ilv == 6) return advect_steps_ab_l<D, S, kLayTPair>(v, xh, xl, hist, t0, dt, n_begin, n_end);
+    if (v.ilv == 2 * D) return advect_steps_ab_l<D, S, kLayTPair>(v, xh, xl, hist, t0, dt, n_begin, n_end);
     if (v.ilv) return advect_steps_ab_l<D, S, kLayInterleaved>(v, xh, xl, hist, t0, dt, n_begin, n_end);
     return advect_steps_ab_l<D, S, kLaySoa>(v, xh, xl, hist, t0, dt, n_begin, n_end);
 }
@@ -789,15 +803,18 @@ __global__ __launch_bounds__(256) void interleave_kernel(int dim, int S, const f
     if (S == 4) o[3] = 0.0f;
 }
 
-// Time-paired records: one thread per record q on the grid with n0 + 1 nodes
-// per row (the last repeating node 0 of the row), for the kTPairRun
-// consecutive pairs p = pair0 + kTPairRun*blockIdx.y .. (< pairs) (frames
-// f_first + p and f_first + p + 1): the frame two neighbouring pairs share
-// stays in registers, so each frame is read once per run instead of twice.
-// The records of one pair number fewer than 2^28 (a frame-pair block is
-// limited to 4 GiB), so the index arithmetic within a pair is 32-bit.
+// Time-paired records (2*D floats: the D components of frame p, then those of
+// frame p + 1): one thread per record q on the grid with n0 + 1 nodes per row
+// (the last repeating node 0 of the row), for the kTPairRun consecutive pairs
+// p = pair0 + kTPairRun*blockIdx.y .. (< pairs) (frames f_first + p and
+// f_first + p + 1): the frame two neighbouring pairs share stays in
+// registers, so each frame is read once per run instead of twice.  The
+// records of one pair number fewer than 2^28 (a frame-pair block is limited
+// to 4 GiB), so the index arithmetic within a pair is 32-bit.  In 2D, n2 = 1
+// and u2 is not read.
 constexpr int kTPairRun = 8;
 
+template <int D>
 __global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *__restrict__ u0,
                                                                const float *__restrict__ u1,
                                                                const float *__restrict__ u2,
@@ -817,14 +834,19 @@ __global__ __launch_bounds__(256) void interleave_tpair_kernel(const float *__re
     const long long nodes = (long long)n0 * n1 * n2;
     const long long node = (long long)row * n0 + (i == (uint32_t)n0 ? 0u : i);
     long long a = (f_first + p0) * nodes + node;
-    float x0 = u0[a], y0 = u1[a], z0 = u2[a];
+    float x0 = u0[a], y0 = u1[a], z0 = (D == 3) ? u2[a] : 0.0f;
     for (long long p = p0; p < p1; ++p) {
         a += nodes;
-        const float x1 = u0[a], y1 = u1[a], z1 = u2[a];
-        float2 *o = reinterpret_cast<float2 *>(out + (p * (long long)per_pair + q) * 6);
-        o[0] = make_float2(x0, y0);
-        o[1] = make_float2(z0, x1);
-        o[2] = make_float2(y1, z1);
+        const float x1 = u0[a], y1 = u1[a], z1 = (D == 3) ? u2[a] : 0.0f;
+        if constexpr (D == 3) {
+            float2 *o = reinterpret_cast<float2 *>(out + (p * (long long)per_pair + q) * 6);
+            o[0] = make_float2(x0, y0);
+            o[1] = make_float2(z0, x1);
+            o[2] = make_float2(y1, z1);
+        } else {
+            *reinterpret_cast<float4 *>(out + (p * (long long)per_pair + q) * 4) =
+                make_float4(x0, y0, x1, y1);
+        }
         x0 = x1;
         y0 = y1;
         z0 = z1;
@@ -1378,8 +1400,8 @@ hipError_t launch_interleave(int dim, int S, const float *const *u, long long no
     return hipGetLastError();
 }
 
-hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_count, int f_first,
-                                  float *out, hipStream_t s)
+hipError_t launch_interleave_tpair(int dim, const float *const *u, const int *n, int f_count,
+                                  int f_first, float *out, hipStream_t s)
 {
     const long long per_pair = (long long)(n[0] + 1) * n[1] * n[2];
     const long long pairs = f_count - 1;
@@ -1389,8 +1411,12 @@ hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_co
     const long long runs = (pairs + kTPairRun - 1) / kTPairRun;
     for (long long r0 = 0; r0 < runs; r0 += 65535) {   // grid y covers up to 65535 runs
         const unsigned by = (unsigned)(runs - r0 < 65535 ? runs - r0 : 65535);
-        hipLaunchKernelGGL(interleave_tpair_kernel, dim3(bx, by), dim3(256), 0, s, u[0], u[1], u[2],
-                           n[0], n[1], n[2], (long long)f_first, r0 * kTPairRun, pairs, out);
+        if (dim == 2)
+            hipLaunchKernelGGL(interleave_tpair_kernel<2>, dim3(bx, by), dim3(256), 0, s, u[0], u[1],
+                               u[1], n[0], n[1], 1, (long long)f_first, r0 * kTPairRun, pairs, out);
+        else
+            hipLaunchKernelGGL(interleave_tpair_kernel<3>, dim3(bx, by), dim3(256), 0, s, u[0], u[1],
+                               u[2], n[0], n[1], n[2], (long long)f_first, r0 * kTPairRun, pairs, out);
     }
     return hipGetLastError();
 }

@@ -54,8 +54,7 @@ lcs_status check_velocity(const lcs_velocity_t *v)
 {
     if (!v) return lcs::set_error(LCS_E_ARG, "velocity descriptor is NULL");
     if (v->dim != 2 && v->dim != 3) return lcs::set_error(LCS_E_ARG, "velocity dim must be 2 or 3 (got %d)", v->dim);
-    if (v->layout > LCS_LAYOUT_TPAIR ||
-        ((v->layout == LCS_LAYOUT_XYZW || v->layout == LCS_LAYOUT_TPAIR) && v->dim != 3))
+    if (v->layout > LCS_LAYOUT_TPAIR || (v->layout == LCS_LAYOUT_XYZW && v->dim != 3))
         return lcs::set_error(LCS_E_ARG, "velocity layout %u is not valid for %dD", v->layout, v->dim);
     if (v->layout != LCS_LAYOUT_SOA) {
         const uintptr_t align = (v->layout == LCS_LAYOUT_XYZW || v->layout == LCS_LAYOUT_TPAIR)
@@ -86,7 +85,7 @@ lcs_status check_velocity(const lcs_velocity_t *v)
     // byte offsets
     const long long rec = (v->layout == LCS_LAYOUT_SOA) ? 4 :
                           (v->layout == LCS_LAYOUT_XYZW) ? 16 :
-                          (v->layout == LCS_LAYOUT_TPAIR) ? 24 : 4LL * v->dim;
+                          (v->layout == LCS_LAYOUT_TPAIR) ? 8LL * v->dim : 4LL * v->dim;
     const long long recs = (v->layout == LCS_LAYOUT_TPAIR) ? nodes / v->n[0] * (v->n[0] + 1) : nodes;
     if (recs * rec > (1LL << 32))
         return lcs::set_error(LCS_E_SHAPE, "a velocity frame array exceeds 4 GiB (%lld records x %lld B)",
@@ -162,12 +161,12 @@ lcs::VelDev make_vel(const lcs_velocity_t *v)
 {
     lcs::VelDev d;
     memset(&d, 0, sizeof(d));
-    // TPAIR: a "frame" is a frame-pair block of (n0+1)*n1*n2 records of 6 floats
+    // TPAIR: a "frame" is a frame-pair block of (n0+1)*n1*n2 records of 2*dim floats
     const bool tpair = (v->layout == LCS_LAYOUT_TPAIR);
     const long long n0r = tpair ? v->n[0] + 1 : v->n[0];
     d.frame_stride = n0r * v->n[1] * v->n[2];
     if (v->layout != LCS_LAYOUT_SOA) {
-        d.ilv = tpair ? 6 : (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
+        d.ilv = tpair ? 2 * v->dim : (v->layout == LCS_LAYOUT_XYZW) ? 4 : v->dim;
         d.ilv_u = v->u[0];
     }
     const uint32_t rec = (v->layout == LCS_LAYOUT_SOA) ? 4u : 4u * (uint32_t)(d.ilv);
@@ -460,9 +459,9 @@ lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int
     lcs_status st;
     if ((st = check_velocity(soa)) != LCS_OK) return st;
     if (soa->layout != LCS_LAYOUT_SOA) return lcs::set_error(LCS_E_ARG, "source frames must be LCS_LAYOUT_SOA");
-    if (layout != LCS_LAYOUT_XYZ &&
-        !((layout == LCS_LAYOUT_XYZW || layout == LCS_LAYOUT_TPAIR) && soa->dim == 3))
-        return lcs::set_error(LCS_E_ARG, "target layout must be LCS_LAYOUT_XYZ (or XYZW / TPAIR in 3D)");
+    if (layout != LCS_LAYOUT_XYZ && layout != LCS_LAYOUT_TPAIR &&
+        !(layout == LCS_LAYOUT_XYZW && soa->dim == 3))
+        return lcs::set_error(LCS_E_ARG, "target layout must be LCS_LAYOUT_XYZ, TPAIR (or XYZW in 3D)");
     if (!out || !out_desc) return lcs::set_error(LCS_E_ARG, "out and out_desc must not be NULL");
     if (f_first < 0 || f_count < 2 || (long long)f_first + f_count > soa->n_frames)
         return lcs::set_error(LCS_E_SHAPE, "frame span [%d, %d) outside [0, %d) or shorter than 2",
@@ -481,7 +480,8 @@ lcs_status lcs_frames_interleave(const lcs_velocity_t *soa, uint32_t layout, int
     hipError_t e;
     if (layout == LCS_LAYOUT_TPAIR) {
         const int n[3] = {(int)soa->n[0], (int)soa->n[1], (int)soa->n[2]};
-        e = lcs::launch_interleave_tpair(soa->u, n, f_count, f_first, out, (hipStream_t)stream);
+        e = lcs::launch_interleave_tpair(soa->dim, soa->u, n, f_count, f_first, out,
+                                         (hipStream_t)stream);
     } else {
         e = lcs::launch_interleave(soa->dim, S, soa->u, nodes, f_count, f_first, out,
                                    (hipStream_t)stream);
@@ -505,7 +505,7 @@ int64_t lcs_frames_interleave_floats(const lcs_velocity_t *soa, uint32_t layout,
     case LCS_LAYOUT_XYZ: return (int64_t)f_count * nodes * soa->dim;
     case LCS_LAYOUT_XYZW: return soa->dim == 3 ? (int64_t)f_count * nodes * 4 : -1;
     case LCS_LAYOUT_TPAIR:
-        return soa->dim == 3 ? (int64_t)(f_count - 1) * (soa->n[0] + 1) * soa->n[1] * soa->n[2] * 6 : -1;
+        return (int64_t)(f_count - 1) * (soa->n[0] + 1) * soa->n[1] * soa->n[2] * 2 * soa->dim;
     default: return -1;
     }
 }

@@ -418,7 +418,7 @@ lcs_status hip_error(hipError_t e, const char *where);
 hipError_t launch_advect_grid(int dim, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_interleave(int dim, int S, const float *const *u, long long nodes, int f_count,
                              long long f_first, float *out, hipStream_t s);
-hipError_t launch_interleave_tpair(const float *const *u, const int *n, int f_count, int f_first,
+hipError_t launch_interleave_tpair(int dim, const float *const *u, const int *n, int f_count, int f_first,
                                  float *out, hipStream_t s);
 hipError_t launch_advect_ab(int dim, int order, const AdvectArgs &a, hipStream_t s);
 hipError_t launch_advect_aux(int dim, const AuxArgs &a, hipStream_t s);

@@ -255,7 +255,7 @@ class DeviceFrames:
     def interleaved(cls, fs, layout: str = "xyz", device="cuda", stream=None) -> "DeviceFrames":
         """Frames of the FrameSet fs staged on the device in an interleaved layout
         ("xyz": dim floats per node, "xyzw": 4 in 3D, "tpair": time-paired
-        records in 3D) by lcs_frames_interleave."""
+        records of 2*dim floats) by lcs_frames_interleave."""
         return lcs_frames_interleave(cls(fs, device=device), layout, stream=stream)
 
 
@@ -264,7 +264,7 @@ _LAYOUTS = {"xyz": LCS_LAYOUT_XYZ, "xyzw": LCS_LAYOUT_XYZW, "tpair": LCS_LAYOUT_
 
 
 class _InterleavedFrames(DeviceFrames):
-    """Frames in an interleaved layout: one tensor ((F, N, S), or (F-1, N', 6)
+    """Frames in an interleaved layout: one tensor ((F, N, S), or (F-1, N', 2*dim)
     for time-paired records) and its descriptor."""
 
     def __init__(self, fs, tensor, desc):     # noqa: D401 (no SoA construction)
@@ -281,7 +281,7 @@ def lcs_frames_interleave(frames: DeviceFrames, layout: str = "xyz", f_first: in
     d = frames.desc
     F = int(d.n_frames) if f_count is None else int(f_count)
     if lay == LCS_LAYOUT_TPAIR:
-        shape = (F - 1, int((d.n[0] + 1) * d.n[1] * d.n[2]), 6)
+        shape = (F - 1, int((d.n[0] + 1) * d.n[1] * d.n[2]), 2 * int(d.dim))
     else:
         shape = (F, int(d.n[0] * d.n[1] * d.n[2]), 4 if lay == LCS_LAYOUT_XYZW else int(d.dim))
     if out is None:

@@ -68,7 +68,7 @@ def _advect(v, s, t0, T, dt, xf=0x2000):
     ("xyzw_in_2d", lcs.LCS_E_ARG),
     ("misaligned_interleaved", lcs.LCS_E_ARG),
     ("frame_over_4gib", lcs.LCS_E_SHAPE),
-    ("tpair_in_2d", lcs.LCS_E_ARG),
+    ("misaligned_tpair_2d", lcs.LCS_E_ARG),
     ("misaligned_tpair", lcs.LCS_E_ARG),
     ("empty_seed_axis", lcs.LCS_E_SHAPE),
     ("single_seed_axis", lcs.LCS_E_SHAPE),
@@ -115,8 +115,9 @@ def test_advect_validation(case, expect):
     elif case == "misaligned_interleaved":
         v.layout = lcs.LCS_LAYOUT_XYZ
         v.u[0] = 0x1004                # 2D interleaved frames need 8-byte alignment
-    elif case == "tpair_in_2d":
+    elif case == "misaligned_tpair_2d":
         v.layout = lcs.LCS_LAYOUT_TPAIR
+        v.u[0] = 0x1008                # 2D time-paired records need 16-byte alignment too
     elif case == "misaligned_tpair":
         v.dim, v.n[2] = 3, 4
         v.layout = lcs.LCS_LAYOUT_TPAIR
@@ -247,8 +248,9 @@ def test_frames_interleave_floats():
     assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 4) == 3 * 6 * 4 * 3 * 6
     assert L.lcs_frames_interleave_floats(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 1) == -1
     assert L.lcs_frames_interleave_floats(C.byref(v), 9, 4) == -1
-    v2 = _vel()
-    assert L.lcs_frames_interleave_floats(C.byref(v2), lcs.LCS_LAYOUT_TPAIR, 3) == -1
+    v2 = _vel()                                            # 2D, 5 x 4 nodes
+    assert L.lcs_frames_interleave_floats(C.byref(v2), lcs.LCS_LAYOUT_TPAIR, 3) == 2 * 6 * 4 * 4
+    assert L.lcs_frames_interleave_floats(C.byref(v2), lcs.LCS_LAYOUT_XYZW, 3) == -1
 
 
 def test_frames_interleave_validates():
@@ -257,8 +259,8 @@ def test_frames_interleave_validates():
     out_desc = lcs.lcs_velocity_t()
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZW, 0, 2, 0x1000, C.byref(out_desc),
                                    None) == lcs.LCS_E_ARG          # XYZW is 3D only
-    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 0, 2, 0x1000, C.byref(out_desc),
-                                   None) == lcs.LCS_E_ARG          # TPAIR is 3D only
+    assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_TPAIR, 0, 2, 0x1008, C.byref(out_desc),
+                                   None) == lcs.LCS_E_ARG          # TPAIR output 16-byte aligned
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 0, 1, 0x1000, C.byref(out_desc),
                                    None) == lcs.LCS_E_SHAPE        # fewer than 2 frames
     assert L.lcs_frames_interleave(C.byref(v), lcs.LCS_LAYOUT_XYZ, 1, 9, 0x1000, C.byref(out_desc),

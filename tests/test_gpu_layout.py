@@ -102,23 +102,49 @@ def test_tpair_records_exact(lcs, torch, periodic, n_frames, f_first, f_count):
     assert want == il.u[0].numel()
 
 
-def test_double_gyre_interleaved(orc, lcs):
+@pytest.mark.parametrize("periodic,n_frames,f_first,f_count",
+                         [(True, 6, 1, 4), (False, 24, 2, 21)])
+def test_tpair_records_exact_2d(lcs, torch, periodic, n_frames, f_first, f_count):
+    """2D time-paired records: (u, v) of frame p then of frame p+1 per node,
+    16 bytes, one extra node per x row repeating node 0."""
+    fs = inputs.random_frames(2, (9, 7), n_frames, seed=6,
+                              periodic=(True, True) if periodic else None).astype(np.float32)
+    soa = lcs.DeviceFrames(fs)
+    il = lcs.lcs_frames_interleave(soa, "tpair", f_first=f_first, f_count=f_count)
+    lcs.lcs_sync_status()
+    pairs = f_count - 1
+    got = _np(il.u[0]).reshape(pairs, 7, 10, 4)
+    u = [np.asarray(c)[f_first:f_first + f_count] for c in fs.u]   # (f_count, 7, 9) per component
+    for p in range(pairs):
+        for c in range(2):
+            np.testing.assert_array_equal(got[p, :, :9, c], u[c][p])
+            np.testing.assert_array_equal(got[p, :, :9, 2 + c], u[c][p + 1])
+            np.testing.assert_array_equal(got[p, :, 9, c], u[c][p][:, 0])
+            np.testing.assert_array_equal(got[p, :, 9, 2 + c], u[c][p + 1][:, 0])
+    assert il.desc.layout == lcs.LCS_LAYOUT_TPAIR and il.desc.n_frames == f_count
+    want = lcs.lib().lcs_frames_interleave_floats(soa.ref, lcs.LCS_LAYOUT_TPAIR, f_count)
+    assert want == il.u[0].numel()
+
+
+@pytest.mark.parametrize("layout", ["xyz", "tpair"])
+def test_double_gyre_interleaved(orc, lcs, layout):
     fs = inputs.double_gyre_frames()
     g = inputs.linspace_seeds(2, (256, 128), (0.0, 0.0), (2.0, 1.0))
-    _say("case: double gyre, interleaved xy frames")
-    frames = lcs.DeviceFrames.interleaved(fs, "xyz")
+    _say(f"case: double gyre, {layout} frames")
+    frames = lcs.DeviceFrames.interleaved(fs, layout)
     compare_full(orc, fs, g, _gpu(lcs, frames, g, 0.0, 10.0, 0.05), _orc(orc, fs, g, 0.0, 10.0, 0.05),
-                 "double gyre xy")
+                 f"double gyre {layout}")
 
 
-def test_periodic_2d_interleaved_wrap(orc, lcs):
+@pytest.mark.parametrize("layout", ["xyz", "tpair"])
+def test_periodic_2d_interleaved_wrap(orc, lcs, layout):
     fs = inputs.taylor_green_frames(n=48, n_frames=9)
     L = 2 * math.pi
     g = inputs.periodic_seeds(2, (96, 80), (L, L))
-    _say("case: periodic Taylor-Green, interleaved xy frames")
-    frames = lcs.DeviceFrames.interleaved(fs, "xyz")
+    _say(f"case: periodic Taylor-Green, {layout} frames")
+    frames = lcs.DeviceFrames.interleaved(fs, layout)
     compare_full(orc, fs, g, _gpu(lcs, frames, g, 0.0, 3.5, 0.05), _orc(orc, fs, g, 0.0, 3.5, 0.05),
-                 "taylor-green xy")
+                 f"taylor-green {layout}")
 
 
 @pytest.mark.parametrize("layout", ["xyz", "xyzw", "tpair"])
@@ -144,10 +170,11 @@ def test_exits_and_nan_interleaved(orc, lcs, layout3):
     fs2 = inputs.double_gyre_frames(nx=51, ny=26, n_frames=11)
     fs2.u[1][3, 12, 20] = np.nan
     g2 = inputs.linspace_seeds(2, (64, 32), (0.02, 0.02), (1.98, 0.98))
-    frames2 = lcs.DeviceFrames.interleaved(fs2, "xyz")
     ref2 = _orc(orc, fs2, g2, 0.0, 8.0, 0.05)
     assert (ref2["flags"] == 2).sum() > 0
-    compare_full(orc, fs2, g2, _gpu(lcs, frames2, g2, 0.0, 8.0, 0.05), ref2, "NaN xy")
+    layout2 = "xyz" if layout3 == "xyzw" else "tpair"
+    frames2 = lcs.DeviceFrames.interleaved(fs2, layout2)
+    compare_full(orc, fs2, g2, _gpu(lcs, frames2, g2, 0.0, 8.0, 0.05), ref2, f"NaN {layout2}")
 
 
 @pytest.mark.parametrize("layout", ["xyz", "xyzw", "tpair"])
@@ -182,10 +209,11 @@ def test_abc_full_size_interleaved_sampled(orc, lcs, torch, layout):
     assert err.max() <= parity.FTLE_TOL
 
 
-def test_batched_interleaved_equals_per_window(lcs, torch):
+@pytest.mark.parametrize("layout", ["xyz", "tpair"])
+def test_batched_interleaved_equals_per_window(lcs, torch, layout):
     fs = inputs.double_gyre_frames(nx=101, ny=51, n_frames=41, dt_frame=0.25)
     g = inputs.linspace_seeds(2, (96, 48), (0.0, 0.0), (2.0, 1.0))
-    frames = lcs.DeviceFrames.interleaved(fs, "xyz")
+    frames = lcs.DeviceFrames.interleaved(fs, layout)
     windows = [(0.5, 4.0), (2.0, 1.5), (1.0, 6.5)]
     plan = lcs.Plan()
     xb, cb, fb = lcs.lcs_advect_batched(plan, frames, g, windows, 0.05)
@@ -217,10 +245,18 @@ def test_layouts_give_identical_bits(lcs, torch):
         assert torch.equal(outs[0][0], outs[k][0]) and torch.equal(outs[0][1], outs[k][1])
     fs2 = inputs.double_gyre_frames(nx=51, ny=26, n_frames=11)
     g2 = inputs.linspace_seeds(2, (97, 45), (0.0, 0.0), (2.0, 1.0))
-    x_soa = lcs.lcs_advect(lcs.DeviceFrames(fs2), g2, 0.5, 7.0, 0.05)[0]
-    x_xy = lcs.lcs_advect(lcs.DeviceFrames.interleaved(fs2, "xyz"), g2, 0.5, 7.0, 0.05)[0]
-    lcs.lcs_sync_status()
-    assert torch.equal(x_soa, x_xy)
+    outs2 = []
+    for layout in ("soa", "xyz", "tpair"):
+        fr = lcs.DeviceFrames(fs2) if layout == "soa" else lcs.DeviceFrames.interleaved(fs2, layout)
+        a = lcs.lcs_advect(fr, g2, 0.5, 7.0, 0.05)
+        b = lcs.lcs_advect_sorted(fr, g2, 0.5, 7.0, 0.05, 20)
+        c = lcs.lcs_advect_ab_sorted(fr, g2, 0.5, 7.0, 0.05, order=3, segment_steps=20)
+        lcs.lcs_sync_status()
+        for u, v in zip(a, b):
+            assert torch.equal(u, v), layout
+        outs2.append((a[0], c[0]))
+    for k in (1, 2):
+        assert torch.equal(outs2[0][0], outs2[k][0]) and torch.equal(outs2[0][1], outs2[k][1])
 
 
 def test_tpair_equals_soa_in_every_entry_point(lcs, torch):
